@@ -1,0 +1,267 @@
+"""Plain FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may import this
+package.  The product library never links or calls it; the two share no code.
+
+The arithmetic lives in ``a2a_oracle.c`` (C99 complex doubles + OpenMP, canonical layout,
+plain definitions).  This module compiles it with gcc and wraps it with ctypes, taking
+and returning numpy complex128 arrays in the canonical layouts:
+
+    links   (T, Z, Y, X, 4, 3, 3)      spinors (nsrc, T, Z, Y, X, 4, 3)
+
+Parity status of every function: pinned by the ``-m "not gpu"`` tests in
+``tests/test_oracle_*.py`` (free-field closed form, gamma5-hermiticity, gauge covariance,
+a hand-computed clover, dense LU solves, the exact correlator from unit sources, the
+free-field correlator closed form, estimator statistics).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "a2a_oracle.c")
+_LIB = os.path.join(_HERE, "_build", "liba2a_oracle.so")
+_lib = None
+
+
+def build(force=True):
+    """Compile the oracle with gcc (-O2 -fopenmp, no fast-math)."""
+    os.makedirs(os.path.dirname(_LIB), exist_ok=True)
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-std=c99", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I = ctypes.c_int
+        D = ctypes.c_double
+        Lg = ctypes.c_long
+        sig = {
+            "orc_gamma": [I, P],
+            "orc_hop": [P, I, P, P, P],
+            "orc_field_strength": [P, P, P],
+            "orc_clover": [P, P, D, D, P],
+            "orc_invert_sites": [Lg, P, P],
+            "orc_site_matvec": [Lg, P, P, P],
+            "orc_apply_D": [P, I, P, P, D, P, P],
+            "orc_schur": [P, I, P, P, P, D, P, P],
+            "orc_solve": [P, I, P, P, D, I, P, P, D, I, P],
+            "orc_bicgstab_fixed": [P, I, P, P, D, P, P, I, P],
+            "orc_stochastic_operators": [P, I, P, P, P],
+            "orc_pion_from_O": [I, I, P, I, P],
+            "orc_contract_pion": [P, I, P, P, I, P, P],
+            "orc_pipi_from_O": [I, I, P, I, P, P],
+            "orc_contract_pipi": [P, I, P, P, P, P],
+            "orc_num_threads": [],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = I
+        _lib = L
+    return _lib
+
+
+def _c(a, dtype=np.complex128):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dims(links_or_dims):
+    if isinstance(links_or_dims, np.ndarray) and links_or_dims.ndim == 7:
+        T, Z, Y, X = links_or_dims.shape[:4]
+        return np.array([X, Y, Z, T], dtype=np.int32)
+    return np.array([int(d) for d in links_or_dims], dtype=np.int32)
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+    return rc
+
+
+def num_threads():
+    return lib().orc_num_threads()
+
+
+def gamma(mu):
+    """gamma_mu (mu = 0..3 for x, y, z, t) or gamma_5 (mu = 4) as a 4x4 complex matrix."""
+    out = np.zeros((4, 4), np.complex128)
+    _check(lib().orc_gamma(int(mu), _p(out)), "gamma")
+    return out
+
+
+def hop(U, psi, tbc):
+    """Full-lattice hopping term H psi (Wilson, r = 1, time boundary sign tbc)."""
+    U = _c(U)
+    psi = _c(psi)
+    out = np.empty_like(psi)
+    _check(lib().orc_hop(_p(_dims(U)), int(tbc), _p(U), _p(psi), _p(out)), "hop")
+    return out
+
+
+def field_strength(U):
+    """F_munu per site, planes (xy, xz, xt, yz, yt, zt): shape (T,Z,Y,X,6,3,3)."""
+    U = _c(U)
+    out = np.empty(U.shape[:4] + (6, 3, 3), np.complex128)
+    _check(lib().orc_field_strength(_p(_dims(U)), _p(U), _p(out)), "field_strength")
+    return out
+
+
+def clover(U, kappa, csw):
+    """Dense 12x12 clover matrix A(x) = 1 + i kappa c_sw sum sigma F per site: (T,Z,Y,X,12,12)."""
+    U = _c(U)
+    out = np.empty(U.shape[:4] + (12, 12), np.complex128)
+    _check(lib().orc_clover(_p(_dims(U)), _p(U), float(kappa), float(csw), _p(out)), "clover")
+    return out
+
+
+def invert_sites(A):
+    A = _c(A)
+    out = np.empty_like(A)
+    n = A.size // 144
+    _check(lib().orc_invert_sites(n, _p(A), _p(out)), "invert_sites")
+    return out
+
+
+def site_matvec(A, psi):
+    A = _c(A)
+    psi = _c(psi)
+    out = np.empty_like(psi)
+    _check(lib().orc_site_matvec(A.size // 144, _p(A), _p(psi), _p(out)), "site_matvec")
+    return out
+
+
+def apply_D(U, A, kappa, psi, tbc):
+    """D psi = A psi - kappa H psi on the full lattice (one spinor field)."""
+    U = _c(U)
+    A = _c(A)
+    psi = _c(psi)
+    out = np.empty_like(psi)
+    _check(lib().orc_apply_D(_p(_dims(U)), int(tbc), _p(U), _p(A), float(kappa), _p(psi), _p(out)), "apply_D")
+    return out
+
+
+def schur(U, A, Ainv, kappa, psi, tbc):
+    """Odd-site Schur complement A_oo x - kappa^2 H_oe A_ee^{-1} H_eo x (even part zero)."""
+    U, A, Ainv, psi = _c(U), _c(A), _c(Ainv), _c(psi)
+    out = np.empty_like(psi)
+    _check(lib().orc_schur(_p(_dims(U)), int(tbc), _p(U), _p(A), _p(Ainv), float(kappa), _p(psi), _p(out)),
+           "schur")
+    return out
+
+
+def solve(U, A, kappa, eta, tbc, tol=1e-13, maxit=100000):
+    """X_i = D^{-1} eta_i (BiCGStab on the full system, restarted on the true residual).
+
+    Returns (X, info) with info[i] = (iterations, restarts, converged, true rel. residual).
+    """
+    U, A, eta = _c(U), _c(A), _c(eta)
+    single = eta.ndim == 6
+    if single:
+        eta = eta[None]
+    X = np.empty_like(eta)
+    info = np.zeros((eta.shape[0], 4))
+    rc = lib().orc_solve(_p(_dims(U)), int(tbc), _p(U), _p(A), float(kappa), eta.shape[0], _p(eta), _p(X),
+                         float(tol), int(maxit), _p(info))
+    _check(rc, "solve")
+    return (X[0] if single else X), info
+
+
+def bicgstab_fixed(U, A, kappa, eta, tbc, iters):
+    """Exactly `iters` BiCGStab iterations from zero on one source; returns (x, residual history)."""
+    U, A, eta = _c(U), _c(A), _c(eta)
+    X = np.empty_like(eta)
+    hist = np.zeros(int(iters))
+    _check(lib().orc_bicgstab_fixed(_p(_dims(U)), int(tbc), _p(U), _p(A), float(kappa), _p(eta), _p(X), int(iters),
+                                    _p(hist)), "bicgstab_fixed")
+    return X, hist
+
+
+def stochastic_operators(eta, X):
+    """O[t, a, b] = sum_{y in t} eta_a(y)^dag gamma_5 X_b(y)."""
+    eta, X = _c(eta), _c(X)
+    N = eta.shape[0]
+    T = eta.shape[1]
+    dims = np.array([eta.shape[4], eta.shape[3], eta.shape[2], T], np.int32)
+    O = np.empty((T, N, N), np.complex128)
+    _check(lib().orc_stochastic_operators(_p(dims), N, _p(eta), _p(X), _p(O)), "stochastic_operators")
+    return O
+
+
+MODE_UNBIASED, MODE_ALL_PAIRS, MODE_RAW_UNBIASED, MODE_RAW_ALL = 0, 1, 2, 3
+
+
+def pion_from_O(O, mode=MODE_UNBIASED):
+    O = _c(O)
+    T, N, _ = O.shape
+    corr = np.empty(T, np.complex128)
+    _check(lib().orc_pion_from_O(T, N, _p(O), int(mode), _p(corr)), "pion_from_O")
+    return corr
+
+
+def contract_pion(eta, X, mode=MODE_UNBIASED):
+    """Pion correlator C(dt) and the stochastic operators O."""
+    O = stochastic_operators(eta, X)
+    return pion_from_O(O, mode), O
+
+
+def pipi_from_O(O, normalise=True):
+    """(diagrams[4, T] = D0..D3, vac[T]) from the four-group block structure of O."""
+    O = _c(O)
+    T, N, _ = O.shape
+    d = np.empty((4, T), np.complex128)
+    v = np.empty(T, np.complex128)
+    _check(lib().orc_pipi_from_O(T, N, _p(O), 1 if normalise else 0, _p(d), _p(v)), "pipi_from_O")
+    return d, v
+
+
+def contract_pipi(eta, X):
+    return pipi_from_O(stochastic_operators(eta, X), True)
+
+
+# ------------------------------------------------------------------------------------------
+# even-odd helpers (plain definitions on full-lattice arrays)
+# ------------------------------------------------------------------------------------------
+def parity_mask(dims):
+    X, Y, Z, T = dims
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    return ((x + y + z + t) & 1).astype(np.int8)
+
+
+def schur_rhs(U, A, Ainv, kappa, eta, tbc):
+    """b_o = eta_o + kappa H_oe A_ee^{-1} eta_e, returned as a full-lattice field (zero on even)."""
+    dims = _dims(U)
+    odd = parity_mask(dims)[..., None, None] == 1
+    e = np.where(odd, 0, eta)
+    t = site_matvec(Ainv, e)
+    t = np.where(odd, 0, t)
+    h = hop(U, t, tbc)
+    return np.where(odd, eta + kappa * h, 0)
+
+
+def reconstruct_even(U, Ainv, kappa, eta, x_odd, tbc):
+    """x_e = A_ee^{-1}(eta_e + kappa H_eo x_o); returns the full solution."""
+    dims = _dims(U)
+    odd = parity_mask(dims)[..., None, None] == 1
+    xo = np.where(odd, x_odd, 0)
+    h = hop(U, xo, tbc)
+    xe = site_matvec(Ainv, np.where(odd, 0, eta + kappa * h))
+    return np.where(odd, xo, xe)
