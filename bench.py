@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark: solved RHS/s of the stochastic-propagator solve, and the stencil's HBM roofline.
+
+One step is one pass of the whole hot path over one batch of synthetic input resident in HBM:
+  gauge ingest (canonical FP64 links -> even-odd fields), clover build, per-kappa clover and
+  inverse, even-odd source preparation, batched mixed-precision BiCGStab with FP64 reliable
+  updates for every noise source to ||eta - D X|| <= 1e-10 ||eta||, reconstruction and FP64
+  true residual, the stochastic-operator contraction, the pion and the pi-pi correlators.
+value = sources solved per second over the timed steps (whole job, one GPU).
+
+Beside it: the same solve in plain FP64 (FP64 storage and arithmetic, one source at a time),
+the stencil alone in GB/s, the roofline of the dominant kernel measured with HIP events over
+the timed region, and the CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload l32t64] [--prec f16] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Dslash HBM GB/s; solved RHS/s at rel. residual 1e-10 (mixed+batched vs FP64)"
+HBM_PEAK_GBS = 8000.0
+PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+STORAGE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="l32t64")
+    ap.add_argument("--prec", default="f16", choices=list(PREC))
+    ap.add_argument("--rhs-block", type=int, default=4)
+    ap.add_argument("--check-every", type=int, default=4)
+    ap.add_argument("--fp64-sources", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and stencil side measurements")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1405_4524_amd import a2a, inputs
+
+    w = inputs.WORKLOADS[args.workload]
+    dims, tbc, kappa, csw, nsrc, tol = w["dims"], w["tbc"], w["kappa"], w["csw"], w["nsrc"], w["tol"]
+    X, Y, Z, T = dims
+    V = X * Y * Z * T
+    prec = PREC[args.prec]
+    log(f"workload {args.workload}: {dims} V={V} nsrc={nsrc} kappa={kappa} csw={csw} prec={args.prec}")
+
+    # ---- inputs, resident in HBM before timing
+    t = time.time()
+    links_np = inputs.gauge_field(dims, w["eps"], w["gauge_seed"])
+    log(f"gauge field generated on host in {time.time() - t:.1f}s")
+    dev = torch.device("cuda:0")
+    links = torch.from_numpy(links_np.view(np.float64)).to(dev)
+    src = torch.empty((nsrc, T, Z, Y, X, 4, 3, 2), dtype=torch.float64, device=dev)
+    sol = torch.zeros_like(src)
+    torch.cuda.synchronize()
+    ctx = a2a.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+    ctx.z2_noise_dev(dims, w["noise_seed"], 0, nsrc, src)
+    ctx.set_option("rhs_block", args.rhs_block)
+    ctx.set_option("check_every", args.check_every)
+
+    infos = []
+
+    def step():
+        g = ctx.load_gauge_dev(links, dims, tbc)
+        c = ctx.load_clover(g, csw)
+        info, rc = ctx.solve_propagators_dev(c, src, sol, nsrc, kappa, csw, tol=tol, prec=prec, allow=())
+        corr, _ = ctx.contract_pion_2pt_dev(src, sol, nsrc, dims, tbc)
+        diag, vac = ctx.contract_pipi_2pt_dev(src, sol, nsrc, dims, tbc) if nsrc % 4 == 0 and nsrc <= 128 \
+            else (None, None)
+        ctx.unload(g)
+        infos.append(info)
+        return corr, diag
+
+    for i in range(args.warmup):
+        t = time.time()
+        step()
+        log(f"warmup step {i} {time.time() - t:.2f}s")
+    ctx.set_option("kernel_timing", 1)
+    ctx.kernel_stats("schur2", reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        corr, diag = step()
+        log(f"timed step {i} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_option("kernel_timing", 0)
+    elapsed = t1 - t0
+    value = nsrc * args.steps / elapsed
+    kstats = {k: ctx.kernel_stats(k) for k in ("schur1", "schur2", "blas")}
+    last = infos[-1]
+    iters = [x["iters"] for x in last]
+    resid = [x["true_rel_residual"] for x in last]
+    rus = [x["reliable_updates"] for x in last]
+    log(f"{value:.2f} RHS/s; iters {min(iters)}-{max(iters)}; max residual {max(resid):.2e}")
+
+    # dominant kernel of the timed region
+    dom = max(kstats, key=lambda k: kstats[k][1])
+    n_l, ms_l, by_l = kstats[dom]
+    achieved = by_l / (ms_l * 1e-3) / 1e9 if ms_l > 0 else 0.0
+    roofline = {"bound": "hbm", "kernel": {"schur1": "k_hop<.., EPI_INV> (H_eo + A_ee^-1)",
+                                            "schur2": "k_hop<.., EPI_CLOV> (H_oe + A_oo + axpy + dot)",
+                                            "blas": "k_vec (BiCGStab updates)"}[dom],
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "launches": n_l, "avg_launch_ms": round(ms_l / max(1, n_l), 4),
+                "alg_bytes_per_launch": round(by_l / max(1, n_l))}
+    kernels = {k: {"launches": v[0], "total_ms": round(v[1], 2),
+                   "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None} for k, v in kstats.items()}
+
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 1), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec else "f64",
+           "storage": args.prec, "data": "synthetic",
+           "config": {"workload": f"{args.workload}: {X}^3x{T}" if X == Y == Z else args.workload,
+                      "dims": list(dims), "kappa": kappa, "c_sw": csw, "t_bc": tbc, "nsrc": nsrc,
+                      "tol": tol, "links": f"exp(i {w['eps']} H), seed {w['gauge_seed']}",
+                      "noise": f"complex Z2 splitmix64 seed {w['noise_seed']}",
+                      "precision": f"inner {args.prec} storage / f32 arithmetic, f64 reliable updates"
+                      if prec else "f64", "rhs_block": args.rhs_block},
+           "solve": {"iters_min": min(iters), "iters_max": max(iters), "reliable_updates_max": max(rus),
+                     "max_true_rel_residual": max(resid), "all_converged": all(x["converged"] for x in last)},
+           "roofline": roofline, "kernels": kernels}
+
+    if not args.no_extras:
+        # ---- plain FP64: FP64 storage and arithmetic, one source at a time
+        ctx.set_option("rhs_block", 1)
+        g = ctx.load_gauge_dev(links, dims, tbc)
+        c = ctx.load_clover(g, csw)
+        nf = min(args.fp64_sources, nsrc)
+        ctx.solve_propagators_dev(c, src[:1], sol[:1], 1, kappa, csw, tol=tol, prec=0)  # warm
+        torch.cuda.synchronize()
+        tf = time.perf_counter()
+        f64_iters = []
+        for i in range(nf):
+            info, _ = ctx.solve_propagators_dev(c, src[i:i + 1], sol[i:i + 1], 1, kappa, csw, tol=tol, prec=0)
+            f64_iters.append(info[0]["iters"])
+        torch.cuda.synchronize()
+        f64_rate = nf / (time.perf_counter() - tf)
+        log(f"plain FP64: {f64_rate:.2f} RHS/s, iters {f64_iters}")
+        out["fp64_plain"] = {"value": round(f64_rate, 3), "unit": "RHS/s", "sources": nf, "iters": f64_iters,
+                             "note": "FP64 storage+arithmetic, rhs_block 1, one source per solve"}
+        out["speedup_vs_fp64_plain"] = round(value / f64_rate, 2)
+        # ---- the hopping stencil alone (one parity, H_eo), compulsory bytes (V/2)(8l + 2 n s)/launch
+        ds = {}
+        for p_name, p, n in (("f64", 0, 1), ("f32", 1, 1), ("f16", 2, 1), ("f16", 2, 16)):
+            ctx.set_option("rhs_block", 4 if n > 1 else 1)
+            ms = ctx.bench_stencil(c, kappa, a2a.OP_HOP_EO, p, n, 20)
+            sb = STORAGE_BYTES[p]
+            byts = (V // 2) * (8 * 18 * sb + 2 * n * 24 * sb)
+            ds[f"{p_name}_n{n}"] = {"ms": round(ms, 4), "GBps": round(byts / (ms * 1e-3) / 1e9, 1),
+                                    "frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
+        ctx.set_option("rhs_block", args.rhs_block)
+        log(f"stencil: {ds}")
+        out["dslash_hop_eo"] = ds
+        ctx.unload(g)
+
+    ctx.finalize()
+    del src, sol
+    torch.cuda.empty_cache()
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, links_np)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, links_np):
+    """The FP64 CPU oracle on a bounded sample of the same workload (about 20 s of CPU work):
+    two BiCGStab iterations of its plain full-lattice solver on one source at the full lattice
+    (time per iteration), times the iteration count its solver needs at the same kappa, c_sw
+    and field recipe on an 8^3x16 lattice (solved to 1e-10); gives RHS/s."""
+    import numpy as np
+
+    import oracle
+    from paper_1405_4524_amd import inputs
+
+    dims, tbc, kappa, csw = w["dims"], w["tbc"], w["kappa"], w["csw"]
+    t = time.time()
+    A = oracle.clover(links_np, kappa, csw)
+    t_clover = time.time() - t
+    eta = inputs.z2_noise(dims, 1, w["noise_seed"])[0]
+    t = time.time()
+    _, hist = oracle.bicgstab_fixed(links_np, A, kappa, eta, tbc, 2)
+    t_iter = (time.time() - t) / 2
+    del A
+    log(f"oracle: clover {t_clover:.1f}s, {t_iter:.2f}s per full-lattice BiCGStab iteration")
+    small = (8, 8, 8, 16)
+    Us = inputs.gauge_field(small, w["eps"], w["gauge_seed"])
+    As = oracle.clover(Us, kappa, csw)
+    es = inputs.z2_noise(small, 1, w["noise_seed"])
+    t = time.time()
+    _, info = oracle.solve(Us, As, kappa, es, tbc, tol=w["tol"])
+    t_small = time.time() - t
+    iters = int(info[0, 0])
+    rate = 1.0 / (iters * t_iter)
+    log(f"oracle: {iters} iterations at 8^3x16 ({t_small:.1f}s); {rate:.5f} RHS/s estimated at full size")
+    return {"value": rate, "unit": "RHS/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"2 full-lattice BiCGStab iterations on 1 source ({t_iter:.2f} s/iter) x {iters} "
+                      f"iterations needed by the same oracle solver at 8^3x16 with the same kappa, c_sw, "
+                      f"field recipe and tol; clover build {t_clover:.1f} s not counted",
+            "secs_per_iter": t_iter, "iters_8c16": iters}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * a2a.h -- C ABI of liba2a: stochastic all-to-all propagators for lattice QCD on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (Giedt & Howarth, "Stochastic propagators for multi-pion correlation
+ * functions in lattice QCD with GPUs", arXiv:1405.4524):
+ *   - Sec. 7, eq. (Sfill): the all-to-all propagator is estimated from noise sources,
+ *     S ~ (1/N_r) sum_i X_i eta_i^dag, with X_i = D^{-1} eta_i.  This library solves
+ *     D X_i = eta_i for many complex-Z2 sources at once (a2a_solve_propagators).
+ *   - D is the clover-improved Wilson "lattice fermion matrix" of Sec. 7 with the
+ *     tree-level coefficient c_SW of Sec. 8, written in the hopping-parameter form
+ *         D = A - kappa H,
+ *         (H psi)(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu),
+ *         A(x) = 1 + i kappa c_sw sum_{mu<nu} sigma_munu F_munu(x),
+ *     with F the four-leaf clover field strength (Q - Q^dag)/8, sigma_munu = (i/2)[gamma_mu,
+ *     gamma_nu], Hermitian gamma matrices in the chiral basis
+ *         gamma_k = [[0, -i s_k], [i s_k, 0]], gamma_4 = [[0, 1], [1, 0]], gamma_5 = diag(1,1,-1,-1),
+ *     periodic links and a fermion sign t_bc on hops that wrap around in time.
+ *   - Sec. 7, eq. (stoop): stochastic operators O_ij(t) = sum_{y in t} eta_i^dag(y) gamma_5 X_j(y)
+ *     and the zero-momentum pion correlator built from them (a2a_contract_pion_2pt); the
+ *     pi-pi diagram pieces of Secs. 5 and 8 from the same operators with independent noise
+ *     groups (a2a_contract_pipi_2pt).
+ *
+ * Canonical host/device layouts (complex128 = two doubles, real first):
+ *   links    [t][z][y][x][mu][row][col]          mu = 0..3 for x, y, z, t
+ *   spinors  [src][t][z][y][x][spin][colour]
+ *   site index inside a field: ((t*Z + z)*Y + y)*X + x  (x fastest)
+ *
+ * Conventions for every call:
+ *   - return value 0 (A2A_OK) or a negative A2A_E* code; a2a_last_error() describes the
+ *     last failure on that context.  No exception crosses the ABI.
+ *   - the caller owns every buffer it passes; host buffers are not kept after a call
+ *     returns.  *_dev calls take device pointers (for instance torch data_ptr()) and run
+ *     on the context's stream; their buffers must stay alive until that stream is
+ *     synchronised (the synchronous calls synchronise before returning).
+ *   - the context owns resident fields (gauge and clover handles) until a2a_unload or
+ *     a2a_finalize; all its device memory counts against the HBM budget given at
+ *     a2a_init, and a call that would exceed it fails with A2A_ENOMEM before allocating.
+ *   - a context is not thread-safe; use one per host thread.
+ */
+#ifndef A2A_H
+#define A2A_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------ */
+#define A2A_OK 0
+#define A2A_EINVAL (-1)      /* bad argument: odd or < 2 extents, nrhs <= 0, kappa <= 0, tol <= 0, ... */
+#define A2A_ENOMEM (-2)      /* the HBM budget (or the device) cannot hold the request; nothing allocated */
+#define A2A_ENOTCONV (-3)    /* max_iter reached; solutions hold the best iterate, info the residuals */
+#define A2A_EBREAKDOWN (-4)  /* the Krylov solver broke down repeatedly after restarts */
+#define A2A_ENAN (-5)        /* non-finite input */
+#define A2A_EHANDLE (-6)     /* unknown or wrong-kind handle */
+#define A2A_EDEVICE (-7)     /* a HIP runtime error; the message carries the HIP error string */
+#define A2A_EAGAIN (-8)      /* engine: queue full, retry after a step */
+
+/* ---- precision modes: storage / arithmetic of the inner Krylov solve ----------------- */
+#define A2A_F64 0        /* FP64 storage and arithmetic throughout ("plain" solver)          */
+#define A2A_F32 1        /* FP32 storage and arithmetic, FP64 reliable updates               */
+#define A2A_F16_F32 2    /* FP16 storage, FP32 arithmetic, FP64 reliable updates             */
+#define A2A_BF16_F32 3   /* BF16 storage, FP32 arithmetic, FP64 reliable updates             */
+
+/* ---- operator selectors for a2a_dslash_clover ---------------------------------------- */
+#define A2A_OP_FULL_D 0  /* out = D in on the full lattice                                  */
+#define A2A_OP_SCHUR 1   /* odd sites: out_o = (A_oo - kappa^2 H_oe A_ee^{-1} H_eo) in_o; out_e = 0 */
+#define A2A_OP_HOP_EO 2  /* out_e = (H in)_e from in_o; out_o = 0                           */
+#define A2A_OP_HOP_OE 3  /* out_o = (H in)_o from in_e; out_e = 0                           */
+
+/* ---- correlator normalisation modes -------------------------------------------------- */
+#define A2A_PION_UNBIASED 0   /* C(dt) = 1/(T N (N-1)) sum_t0 sum_{a != b} O_ab(t0+dt) O_ba(t0) */
+#define A2A_PION_ALL_PAIRS 1  /* C(dt) = 1/(T N^2) sum_t0 sum_{a, b} ... (the printed Sec. 7 form)  */
+
+typedef struct a2a_ctx a2a_ctx;
+typedef struct a2a_engine a2a_engine;
+
+typedef struct {
+  int dims[4]; /* X, Y, Z, T: each even and >= 2 */
+  int t_bc;    /* +1 periodic or -1 antiperiodic fermion boundary in time */
+} a2a_geom;
+
+typedef struct {
+  int iters;             /* inner Krylov iterations                                     */
+  int reliable_updates;  /* FP64 true-residual recomputations                           */
+  int converged;         /* 1 if ||eta - D X|| <= tol ||eta|| was verified in FP64       */
+  int restarts;          /* Krylov restarts after a breakdown                           */
+  double true_rel_residual; /* ||eta - D X||_2 / ||eta||_2 on the full lattice, in FP64  */
+  double seconds;        /* wall time from admission to completion                      */
+} a2a_solve_info;
+
+/* ---- context ------------------------------------------------------------------------- */
+/* Create a context on HIP device `device`.  hbm_budget_bytes = 0 means 90% of the free
+ * device memory.  hip_stream = NULL creates a private stream owned by the context;
+ * otherwise all work is queued on the given hipStream_t (not owned). */
+int a2a_init(a2a_ctx **ctx, int device, size_t hbm_budget_bytes, void *hip_stream);
+/* Release every handle, engine and allocation of the context. */
+int a2a_finalize(a2a_ctx *ctx);
+/* Message for the last failed call on ctx (never NULL; empty after success). */
+const char *a2a_last_error(const a2a_ctx *ctx);
+/* Tuning knobs: "rhs_block" (1, 2, 4: RHS per thread in the stencil), "check_every"
+ * (iterations between residual checks), "delta" (reliable-update reduction factor),
+ * "xcd_order" (0/1), "kernel_timing" (0/1), "hbm_budget" (bytes; resets the budget given at
+ * a2a_init).  Returns A2A_EINVAL for an unknown key. */
+int a2a_set_option(a2a_ctx *ctx, const char *key, double value);
+/* Bytes of device memory currently held by the context. */
+size_t a2a_mem_in_use(const a2a_ctx *ctx);
+
+/* ---- resident fields (Sec. 7 "inversions in the background of the gauge field") ------ */
+/* Upload a gauge field (canonical layout) and convert it to the even-odd device layout in
+ * every precision; *gauge_h receives a handle.  Links must be finite. */
+int a2a_load_gauge(a2a_ctx *ctx, const a2a_geom *geom, const double *links_host, int *gauge_h);
+int a2a_load_gauge_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *links_dev, int *gauge_h);
+/* Build the kappa-independent clover field for c_sw (Sec. 8, c_SW) on a gauge handle.
+ * A(kappa) and A^{-1}(kappa) are made and cached on first use of each kappa. */
+int a2a_load_clover(a2a_ctx *ctx, int gauge_h, double c_sw, int *clover_h);
+/* Free a gauge or clover handle (a gauge handle also frees its clover handles). */
+int a2a_unload(a2a_ctx *ctx, int handle);
+
+/* ---- operator application (parity tests and the stencil benchmark) -------------------- */
+/* out = op(in) for nrhs spinor fields in canonical layout, computed in precision `prec`
+ * (inputs are rounded to that storage precision first).  dagger = 1 applies op^dag
+ * through gamma_5 hermiticity (gamma_5 op gamma_5).  Host and device variants. */
+int a2a_dslash_clover(a2a_ctx *ctx, int clover_h, double kappa, int op, int dagger, int prec,
+                      const double *in_host, double *out_host, int nrhs);
+int a2a_dslash_clover_dev(a2a_ctx *ctx, int clover_h, double kappa, int op, int dagger, int prec,
+                          const double *in_dev, double *out_dev, int nrhs);
+/* Time `reps` applications of one stencil launch (op = A2A_OP_HOP_EO or A2A_OP_SCHUR) on
+ * nrhs device-resident fields already converted to the device layout; returns the mean
+ * kernel milliseconds per application measured with HIP events on the context stream. */
+int a2a_bench_stencil(a2a_ctx *ctx, int clover_h, double kappa, int op, int prec, int nrhs, int reps,
+                      double *ms_per_apply);
+
+/* ---- solves (Sec. 7: X_i = D^{-1} eta_i) --------------------------------------------- */
+/* Solve D X_i = eta_i for nrhs sources with even-odd preconditioning (odd-site Schur
+ * complement A_oo - kappa^2 H_oe A_ee^{-1} H_eo), batched BiCGStab in precision `prec`
+ * and FP64 reliable updates, until the FP64 true residual of the full system satisfies
+ * ||eta - D X||_2 <= tol ||eta||_2 for every source.  c_sw must equal the clover handle's.
+ * x0_or_null: optional initial guess (resume); info: nrhs records (may be NULL).
+ * A zero source gives X = 0, converged, residual 0.  Returns A2A_ENOTCONV if some source
+ * did not converge within max_iter (solutions hold the best iterates). */
+int a2a_solve_propagators(a2a_ctx *ctx, int clover_h, const double *sources_host, int nrhs, double kappa,
+                          double c_sw, double tol, int prec, int max_iter, const double *x0_or_null,
+                          double *solutions_host, a2a_solve_info *info);
+int a2a_solve_propagators_dev(a2a_ctx *ctx, int clover_h, const double *sources_dev, int nrhs, double kappa,
+                              double c_sw, double tol, int prec, int max_iter, const double *x0_dev_or_null,
+                              double *solutions_dev, a2a_solve_info *info);
+
+/* ---- contractions (Sec. 7, eq. stoop; Secs. 5 and 8 diagrams) ------------------------ */
+/* O[t][a][b] = sum_{y in t} eta_a(y)^dag gamma_5 X_b(y) (complex [T][nrhs][nrhs], optional)
+ * and corr[dt] (complex [T]) in the given mode.  nrhs >= 2 for the unbiased mode. */
+int a2a_contract_pion_2pt(a2a_ctx *ctx, const a2a_geom *geom, const double *sources_host,
+                          const double *solutions_host, int nrhs, int mode, double *corr, double *O_or_null);
+int a2a_contract_pion_2pt_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *sources_dev,
+                              const double *solutions_dev, int nrhs, int mode, double *corr_host,
+                              double *O_host_or_null);
+/* Zero-momentum pi-pi pieces from four disjoint noise groups (nrhs = 4m, 1 <= m <= 32):
+ * diagrams complex [4][T] = D0 (direct), D1 (vacuum, unsubtracted), D2, D3 (single quark
+ * loop through the four points, both orientations); vac_pieces complex [T] = the
+ * timeslice loop L(t, t) of groups 1 and 2.  The total is D0 + D1 - D2 - D3 (Sec. 8). */
+int a2a_contract_pipi_2pt(a2a_ctx *ctx, const a2a_geom *geom, const double *sources_host,
+                          const double *solutions_host, int nrhs, double *diagrams, double *vac_pieces);
+int a2a_contract_pipi_2pt_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *sources_dev,
+                              const double *solutions_dev, int nrhs, double *diagrams_host,
+                              double *vac_pieces_host);
+
+/* ---- synthetic inputs ---------------------------------------------------------------- */
+/* Complex-Z2 noise (Sec. 7 "Z2 noise", here (+-1 +- i)/sqrt 2) written to a canonical
+ * device array of nsrc sources: component k of the flattened array (global source index
+ * src_offset + s) uses h = splitmix64(seed * 2^48 + k), real sign from bit 0 and
+ * imaginary sign from bit 1 of h. */
+int a2a_z2_noise_dev(a2a_ctx *ctx, const a2a_geom *geom, unsigned long long seed, long long src_offset, int nsrc,
+                     double *out_dev);
+
+/* ---- serving engine: continuous batching of propagator requests ---------------------- */
+/* policy_json keys (all optional): "max_slots" (RHS resident at once), "max_queue",
+ * "check_every".  Requests of any resident lattice, kappa and precision share the device;
+ * a request is admitted when its memory fits the context's HBM budget, and its sources
+ * join the running batch at the next step.  sources_dev / solutions_dev must stay valid
+ * until a2a_engine_poll reports the ticket done. */
+int a2a_engine_create(a2a_ctx *ctx, const char *policy_json, a2a_engine **eng);
+int a2a_engine_submit(a2a_engine *eng, int clover_h, double kappa, const double *sources_dev, int nsrc, double tol,
+                      int prec, int max_iter, double *solutions_dev, long long *ticket);
+/* Run `iters` solver iterations for every active slot (all lattices and precisions), then
+ * admit queued requests and retire converged ones.  *active receives the number of active
+ * RHS after the step (may be NULL). */
+int a2a_engine_step(a2a_engine *eng, int iters, int *active);
+/* done: 0 queued or running, 1 finished (info filled, nsrc records), -1 failed */
+int a2a_engine_poll(a2a_engine *eng, long long ticket, int *done, a2a_solve_info *info);
+int a2a_engine_cancel(a2a_engine *eng, long long ticket);
+int a2a_engine_destroy(a2a_engine *eng);
+
+/* ---- instrumentation ------------------------------------------------------------------ */
+/* With option "kernel_timing" = 1 the solver brackets every inner-solver launch with HIP
+ * events on the context stream.  For kernel class `name` ("schur1": hop to even sites with
+ * the A_ee^{-1} epilogue; "schur2": hop to odd sites with the A_oo, axpy and dot-product
+ * epilogue; "blas": the BiCGStab vector updates) returns the launches, their total
+ * milliseconds and their total algorithmic bytes (links and clover once per site, each
+ * spinor stream once per right-hand side) since the last reset; resets if reset != 0. */
+int a2a_kernel_stats(a2a_ctx *ctx, const char *name, long long *launches, double *total_ms, double *alg_bytes,
+                     int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* A2A_H */

@@ -1,0 +1,334 @@
+"""ctypes binding of liba2a (C ABI in include/a2a.h): argument marshalling only.
+
+Every computation runs in the HIP library; if ``_build/liba2a.so`` is missing this module
+raises on first use (there is no fallback).  Method names follow the C functions without the
+``a2a_`` prefix.  Host-array methods take and return numpy complex128 arrays in the canonical
+layouts; ``*_dev`` methods take torch tensors on the GPU (complex128, or float64 with a
+trailing dimension of 2) and run on the stream the context was created with.
+
+    links    (T, Z, Y, X, 4, 3, 3)      spinors  (nsrc, T, Z, Y, X, 4, 3)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_build", "liba2a.so")
+
+OK, EINVAL, ENOMEM, ENOTCONV, EBREAKDOWN, ENAN, EHANDLE, EDEVICE, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7, -8
+F64, F32, F16_F32, BF16_F32 = 0, 1, 2, 3
+OP_FULL_D, OP_SCHUR, OP_HOP_EO, OP_HOP_OE = 0, 1, 2, 3
+PION_UNBIASED, PION_ALL_PAIRS = 0, 1
+PREC_NAMES = {F64: "f64", F32: "f32", F16_F32: "f16/f32", BF16_F32: "bf16/f32"}
+ERR_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOTCONV: "ENOTCONV", EBREAKDOWN: "EBREAKDOWN", ENAN: "ENAN",
+             EHANDLE: "EHANDLE", EDEVICE: "EDEVICE", EAGAIN: "EAGAIN"}
+
+
+class A2AError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4), ("t_bc", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("converged", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+P, I, D, SZ, LL, ULL = (ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_longlong,
+                        ctypes.c_ulonglong)
+_SIG = {
+    "a2a_init": (I, [ctypes.POINTER(P), I, SZ, P]),
+    "a2a_finalize": (I, [P]),
+    "a2a_last_error": (ctypes.c_char_p, [P]),
+    "a2a_set_option": (I, [P, ctypes.c_char_p, D]),
+    "a2a_mem_in_use": (SZ, [P]),
+    "a2a_load_gauge": (I, [P, ctypes.POINTER(Geom), P, ctypes.POINTER(I)]),
+    "a2a_load_gauge_dev": (I, [P, ctypes.POINTER(Geom), P, ctypes.POINTER(I)]),
+    "a2a_load_clover": (I, [P, I, D, ctypes.POINTER(I)]),
+    "a2a_unload": (I, [P, I]),
+    "a2a_dslash_clover": (I, [P, I, D, I, I, I, P, P, I]),
+    "a2a_dslash_clover_dev": (I, [P, I, D, I, I, I, P, P, I]),
+    "a2a_bench_stencil": (I, [P, I, D, I, I, I, I, ctypes.POINTER(D)]),
+    "a2a_solve_propagators": (I, [P, I, P, I, D, D, D, I, I, P, P, P]),
+    "a2a_solve_propagators_dev": (I, [P, I, P, I, D, D, D, I, I, P, P, P]),
+    "a2a_contract_pion_2pt": (I, [P, ctypes.POINTER(Geom), P, P, I, I, P, P]),
+    "a2a_contract_pion_2pt_dev": (I, [P, ctypes.POINTER(Geom), P, P, I, I, P, P]),
+    "a2a_contract_pipi_2pt": (I, [P, ctypes.POINTER(Geom), P, P, I, P, P]),
+    "a2a_contract_pipi_2pt_dev": (I, [P, ctypes.POINTER(Geom), P, P, I, P, P]),
+    "a2a_z2_noise_dev": (I, [P, ctypes.POINTER(Geom), ULL, LL, I, P]),
+    "a2a_engine_create": (I, [P, ctypes.c_char_p, ctypes.POINTER(P)]),
+    "a2a_engine_submit": (I, [P, I, D, P, I, D, I, I, P, ctypes.POINTER(LL)]),
+    "a2a_engine_step": (I, [P, I, ctypes.POINTER(I)]),
+    "a2a_engine_poll": (I, [P, LL, ctypes.POINTER(I), P]),
+    "a2a_engine_cancel": (I, [P, LL]),
+    "a2a_engine_destroy": (I, [P]),
+    "a2a_kernel_stats": (I, [P, ctypes.c_char_p, ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D), I]),
+}
+EXPORTS = tuple(_SIG)
+
+
+def lib():
+    """Load liba2a.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1405_4524_amd.build` first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIG.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _np_c128(a):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a, a.ctypes.data_as(P)
+
+
+def _tptr(t):
+    """data pointer of a contiguous torch tensor on the GPU (complex128 or float64)."""
+    import torch
+
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if t.dtype not in (torch.complex128, torch.float64):
+        raise ValueError("expected complex128 or float64")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def geom(dims, t_bc):
+    g = Geom()
+    for i in range(4):
+        g.dims[i] = int(dims[i])
+    g.t_bc = int(t_bc)
+    return g
+
+
+def dims_of_spinor(a):
+    """(X, Y, Z, T) of a (nsrc, T, Z, Y, X, 4, 3) array or tensor."""
+    s = tuple(a.shape)
+    if len(s) >= 7 and s[-1] == 2:
+        s = s[:-1]
+    return (s[-3], s[-4], s[-5], s[-6])
+
+
+class Engine:
+    """Continuous-batching engine of one context (a2a_engine_*)."""
+
+    def __init__(self, ctx, policy_json=""):
+        self.ctx = ctx
+        self._e = P()
+        ctx._chk(lib().a2a_engine_create(ctx._c, policy_json.encode(), ctypes.byref(self._e)))
+
+    def submit(self, clover_h, kappa, sources_dev, nsrc, tol, prec, max_iter, solutions_dev):
+        t = LL()
+        self.ctx._chk(lib().a2a_engine_submit(self._e, int(clover_h), float(kappa), _tptr(sources_dev), int(nsrc),
+                                              float(tol), int(prec), int(max_iter), _tptr(solutions_dev),
+                                              ctypes.byref(t)))
+        return t.value
+
+    def step(self, iters):
+        a = I()
+        self.ctx._chk(lib().a2a_engine_step(self._e, int(iters), ctypes.byref(a)))
+        return a.value
+
+    def poll(self, ticket, nsrc):
+        done = I()
+        info = (SolveInfo * max(1, nsrc))()
+        rc = lib().a2a_engine_poll(self._e, int(ticket), ctypes.byref(done), info)
+        return done.value, [x.as_dict() for x in info[:nsrc]], rc
+
+    def cancel(self, ticket):
+        self.ctx._chk(lib().a2a_engine_cancel(self._e, int(ticket)))
+
+    def destroy(self):
+        if self._e:
+            lib().a2a_engine_destroy(self._e)
+            self._e = P()
+
+
+class Context:
+    """An a2a context on one GPU (a2a_init ... a2a_finalize)."""
+
+    def __init__(self, device=0, hbm_budget=0, stream=None):
+        self._c = P()
+        s = P(stream) if stream else P()
+        rc = lib().a2a_init(ctypes.byref(self._c), int(device), ctypes.c_size_t(int(hbm_budget)), s)
+        if rc:
+            raise A2AError(rc, "a2a_init failed")
+
+    # ---- plumbing
+    def _chk(self, rc, allow=()):
+        if rc and rc not in allow:
+            raise A2AError(rc, self.last_error())
+        return rc
+
+    def finalize(self):
+        if self._c:
+            lib().a2a_finalize(self._c)
+            self._c = P()
+
+    close = finalize
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.finalize()
+
+    def last_error(self):
+        m = lib().a2a_last_error(self._c)
+        return m.decode() if m else ""
+
+    def set_option(self, key, value):
+        self._chk(lib().a2a_set_option(self._c, key.encode(), float(value)))
+
+    def mem_in_use(self):
+        return int(lib().a2a_mem_in_use(self._c))
+
+    # ---- fields
+    def load_gauge(self, links, t_bc):
+        links, p = _np_c128(links)
+        T, Z, Y, X = links.shape[:4]
+        g = geom((X, Y, Z, T), t_bc)
+        h = I()
+        self._chk(lib().a2a_load_gauge(self._c, ctypes.byref(g), p, ctypes.byref(h)))
+        return h.value
+
+    def load_gauge_dev(self, links_t, dims, t_bc):
+        g = geom(dims, t_bc)
+        h = I()
+        self._chk(lib().a2a_load_gauge_dev(self._c, ctypes.byref(g), _tptr(links_t), ctypes.byref(h)))
+        return h.value
+
+    def load_clover(self, gauge_h, csw):
+        h = I()
+        self._chk(lib().a2a_load_clover(self._c, int(gauge_h), float(csw), ctypes.byref(h)))
+        return h.value
+
+    def unload(self, handle):
+        self._chk(lib().a2a_unload(self._c, int(handle)))
+
+    # ---- operators
+    def dslash_clover(self, clover_h, kappa, psi, op=OP_FULL_D, dagger=False, prec=F64):
+        single = psi.ndim == 6
+        x, p = _np_c128(psi[None] if single else psi)
+        out = np.empty_like(x)
+        self._chk(lib().a2a_dslash_clover(self._c, int(clover_h), float(kappa), int(op), int(bool(dagger)), int(prec),
+                                          p, out.ctypes.data_as(P), x.shape[0]))
+        return out[0] if single else out
+
+    def dslash_clover_dev(self, clover_h, kappa, in_t, out_t, nrhs, op=OP_FULL_D, dagger=False, prec=F64):
+        self._chk(lib().a2a_dslash_clover_dev(self._c, int(clover_h), float(kappa), int(op), int(bool(dagger)),
+                                              int(prec), _tptr(in_t), _tptr(out_t), int(nrhs)))
+
+    def bench_stencil(self, clover_h, kappa, op, prec, nrhs, reps):
+        ms = D()
+        self._chk(lib().a2a_bench_stencil(self._c, int(clover_h), float(kappa), int(op), int(prec), int(nrhs),
+                                          int(reps), ctypes.byref(ms)))
+        return ms.value
+
+    # ---- solves
+    def solve_propagators(self, clover_h, sources, kappa, csw, tol=1e-10, prec=F64, max_iter=100000, x0=None,
+                          allow=(ENOTCONV,)):
+        single = sources.ndim == 6
+        s, ps = _np_c128(sources[None] if single else sources)
+        n = s.shape[0]
+        X = np.empty_like(s)
+        info = (SolveInfo * n)()
+        px0 = None
+        if x0 is not None:
+            x0a, px0 = _np_c128(x0[None] if single else x0)
+        rc = lib().a2a_solve_propagators(self._c, int(clover_h), ps, n, float(kappa), float(csw), float(tol),
+                                         int(prec), int(max_iter), px0, X.ctypes.data_as(P), info)
+        self._chk(rc, allow)
+        inf = [x.as_dict() for x in info]
+        return (X[0] if single else X), inf, rc
+
+    def solve_propagators_dev(self, clover_h, src_t, sol_t, nrhs, kappa, csw, tol=1e-10, prec=F64, max_iter=100000,
+                              x0_t=None, allow=(ENOTCONV,)):
+        info = (SolveInfo * nrhs)()
+        rc = lib().a2a_solve_propagators_dev(self._c, int(clover_h), _tptr(src_t), int(nrhs), float(kappa),
+                                             float(csw), float(tol), int(prec), int(max_iter),
+                                             _tptr(x0_t) if x0_t is not None else None, _tptr(sol_t), info)
+        self._chk(rc, allow)
+        return [x.as_dict() for x in info], rc
+
+    # ---- contractions
+    def contract_pion_2pt(self, sources, solutions, t_bc=-1, mode=PION_UNBIASED, want_O=True):
+        s, ps = _np_c128(sources)
+        x, px = _np_c128(solutions)
+        n = s.shape[0]
+        g = geom(dims_of_spinor(s), t_bc)
+        T = g.dims[3]
+        corr = np.empty(T, np.complex128)
+        O = np.empty((T, n, n), np.complex128) if want_O else None
+        self._chk(lib().a2a_contract_pion_2pt(self._c, ctypes.byref(g), ps, px, n, int(mode),
+                                              corr.ctypes.data_as(P), O.ctypes.data_as(P) if want_O else None))
+        return corr, O
+
+    def contract_pion_2pt_dev(self, src_t, sol_t, nrhs, dims, t_bc=-1, mode=PION_UNBIASED, want_O=False):
+        g = geom(dims, t_bc)
+        T = g.dims[3]
+        corr = np.empty(T, np.complex128)
+        O = np.empty((T, nrhs, nrhs), np.complex128) if want_O else None
+        self._chk(lib().a2a_contract_pion_2pt_dev(self._c, ctypes.byref(g), _tptr(src_t), _tptr(sol_t), int(nrhs),
+                                                  int(mode), corr.ctypes.data_as(P),
+                                                  O.ctypes.data_as(P) if want_O else None))
+        return corr, O
+
+    def contract_pipi_2pt(self, sources, solutions, t_bc=-1):
+        s, ps = _np_c128(sources)
+        x, px = _np_c128(solutions)
+        n = s.shape[0]
+        g = geom(dims_of_spinor(s), t_bc)
+        T = g.dims[3]
+        d = np.empty((4, T), np.complex128)
+        v = np.empty(T, np.complex128)
+        self._chk(lib().a2a_contract_pipi_2pt(self._c, ctypes.byref(g), ps, px, n, d.ctypes.data_as(P),
+                                              v.ctypes.data_as(P)))
+        return d, v
+
+    def contract_pipi_2pt_dev(self, src_t, sol_t, nrhs, dims, t_bc=-1):
+        g = geom(dims, t_bc)
+        T = g.dims[3]
+        d = np.empty((4, T), np.complex128)
+        v = np.empty(T, np.complex128)
+        self._chk(lib().a2a_contract_pipi_2pt_dev(self._c, ctypes.byref(g), _tptr(src_t), _tptr(sol_t), int(nrhs),
+                                                  d.ctypes.data_as(P), v.ctypes.data_as(P)))
+        return d, v
+
+    # ---- inputs
+    def z2_noise_dev(self, dims, seed, src_offset, nsrc, out_t):
+        g = geom(dims, 1)
+        self._chk(lib().a2a_z2_noise_dev(self._c, ctypes.byref(g), ctypes.c_ulonglong(int(seed)),
+                                         ctypes.c_longlong(int(src_offset)), int(nsrc), _tptr(out_t)))
+
+    # ---- engine / instrumentation
+    def engine_create(self, policy_json=""):
+        return Engine(self, policy_json)
+
+    def kernel_stats(self, name, reset=False):
+        """(launches, total ms, total algorithmic bytes) of a timed kernel class."""
+        n = LL()
+        ms = D()
+        by = D()
+        self._chk(lib().a2a_kernel_stats(self._c, name.encode(), ctypes.byref(n), ctypes.byref(ms),
+                                         ctypes.byref(by), int(bool(reset))))
+        return n.value, ms.value, by.value

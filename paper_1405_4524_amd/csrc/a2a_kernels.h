@@ -1,0 +1,94 @@
+// a2a_kernels.h -- host-side declarations of the kernel launchers (internal to liba2a).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "a2a_device.h"
+#include "a2a_reduce.h"
+
+namespace a2a {
+
+constexpr int BS = 256;  // threads per block; one site per thread
+
+// Fused stencil kernel (Sec. 7 "inversion"): for every output site of parity out_par and
+// every slot of a group
+//   o = gam * (H in) + ca * aux1 + cb * (A_out aux2);  if inv: o = A_out^{-1} o
+// with gam = gsign * kappa^gpow, then an optional reduction over o.
+struct HopArgs {
+  const OpDev* ops;
+  const SlotDev* slots;
+  const int* groups;  // [ngroups][R] slot ids, -1 = padding
+  const int2* tiles;  // {group, site block}
+  int out_par;
+  int psel;           // 0: inner precision fields/arena, 1: FP64
+  int vin, vout, vaux1, vaux2;
+  int vrhat;          // for RED_ALPHA: the shadow vector (inner arena)
+  double ca, cb, gsign;
+  int gpow;
+  int inv;
+  int red;
+  RedBuf rb;
+};
+
+// Site-local / vector kernels over per-slot tiles {slot, site block}.
+enum VecKind {
+  VK_BICG_S = 0,    // s = r - alpha v
+  VK_BICG_XR,       // x += alpha p + omega s; r = s - omega t; (rhat, r), |r|^2 -> RED_RHO
+  VK_BICG_P,        // p = r + beta (p - omega v)
+  VK_RU_ACCUM,      // x64 += sigma x_lo; x_lo = 0
+  VK_RU_RESCALE,    // r_lo = r64/sigma'; p, v *= sigma/sigma'; (rhat, r_lo) -> RED_RU
+  VK_INIT,          // r_lo = r64/sigma; rhat = p = r_lo; v = x_lo = 0 -> RED_INIT
+  VK_CLOVER,        // out = C in  (FP64 arena, C = A or A^{-1} of a parity)
+  VK_ZERO_HI,       // hi[vout] = 0
+  VK_ZERO_LO,       // lo[vout] = 0
+  VK_FILL_LO,       // lo[vout] = deterministic pseudo-random values (benchmarks)
+};
+
+struct VecArgs {
+  const OpDev* ops;
+  const SlotDev* slots;
+  const int2* tiles;
+  int kind;
+  int par;        // parity for VK_CLOVER
+  int use_inv;    // VK_CLOVER: 1 -> A^{-1}
+  int vin, vout;  // VK_CLOVER / VK_ZERO_HI
+  RedBuf rb;
+};
+
+// canonical complex128 [site][spin][colour] <-> even-odd chunked vectors
+struct LayoutArgs {
+  const OpDev* ops;
+  const SlotDev* slots;
+  const int2* tiles;
+  int which_in;    // layout_in: 0 reads the slot's source, 1 its initial guess
+  int psel;        // arena / precision of the eo vectors
+  int v_even, v_odd;
+  int gamma5;      // multiply by gamma_5 on the way
+  int red;         // RED_ETA or RED_NONE (|in|^2 over both parities)
+  RedBuf rb;
+};
+
+void launch_hop(int prec, int R, const HopArgs& a, int ntiles, hipStream_t s);
+void launch_vec(int prec, const VecArgs& a, int ntiles, hipStream_t s);
+void launch_layout_in(int prec, const LayoutArgs& a, int ntiles, hipStream_t s);
+void launch_layout_out(int prec, const LayoutArgs& a, int ntiles, hipStream_t s);
+
+// gauge field: canonical complex128 [site][mu][3][3] -> per-parity link fields
+void launch_gauge_to_eo(int prec, const Geo& g, const double* canon, void* const dst[2], hipStream_t s);
+// kappa-independent clover field G (FP64 packed, per parity) from canonical links
+void launch_clover_field(const Geo& g, const double* canon_links, double* G[2], hipStream_t s);
+// A = 1 + kappa c_sw G per parity in FP64, plus its per-block inverse (FP64)
+void launch_clover_make(const Geo& g, const double* G, double kcsw, double* A, double* Ainv, hipStream_t s);
+// precision conversion of a packed clover field
+void launch_clover_convert(int prec, long hv, const double* src, void* dst, hipStream_t s);
+
+// counter-hash complex Z2 noise into canonical layout
+void launch_z2_noise(long V, int nsrc, unsigned long long seed, long long src_offset, double* out, hipStream_t s);
+
+// stochastic operators O[t][a][b] (Sec. 7, eq. stoop) and the correlators built from them
+void launch_stoch_ops(const Geo& g, int n, const double* eta, const double* X, double* partial, int nchunk,
+                      double* O, hipStream_t s);
+void launch_pion_corr(int T, int n, const double* O, int mode, double* corr, hipStream_t s);
+void launch_pipi(int T, int n, const double* O, double* diag, double* vac, hipStream_t s);
+
+}  // namespace a2a

@@ -1,0 +1,973 @@
+// api.cpp -- the extern "C" entry points of liba2a (declared in include/a2a.h) and the
+// continuous-batching serving engine.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <deque>
+
+#include "runtime.h"
+
+using namespace a2a;
+
+struct a2a_ctx {
+  Ctx c;
+};
+
+namespace {
+
+constexpr int SID_CAP = 4096;
+
+int check_prec(int prec) { return (prec >= 0 && prec <= 3) ? A2A_OK : A2A_EINVAL; }
+
+long long volume_of(const Geo& g) { return 2LL * g.hv; }
+
+// allocate the arenas and stable id of one slot
+int slot_alloc(Ctx* c, Slot* s, int prec, long hv, int nblk, int nlo, int nhi) {
+  A2A_TRY(c->alloc_sid(nblk, &s->sid));
+  const size_t bl = [&] {
+    size_t b = prec == 0 ? SpinorF<double>::bytes(hv)
+               : prec == 1 ? SpinorF<float>::bytes(hv)
+               : prec == 2 ? SpinorF<_Float16>::bytes(hv)
+                           : SpinorF<bf16_t>::bytes(hv);
+    return (b + 255) & ~(size_t)255;
+  }();
+  const size_t bh = (SpinorF<double>::bytes(hv) + 255) & ~(size_t)255;
+  s->lo_stride = bl;
+  s->hi_stride = bh;
+  void* p = nullptr;
+  if (nlo) {
+    int rc = c->dalloc(&p, bl * nlo);
+    if (rc) {
+      c->free_sid(s->sid);
+      s->sid = -1;
+      return rc;
+    }
+    s->lo = (char*)p;
+  }
+  if (nhi) {
+    int rc = c->dalloc(&p, bh * nhi);
+    if (rc) {
+      c->dfree(s->lo);
+      s->lo = nullptr;
+      c->free_sid(s->sid);
+      s->sid = -1;
+      return rc;
+    }
+    s->hi = (char*)p;
+  }
+  return A2A_OK;
+}
+
+void slot_free(Ctx* c, Slot* s) {
+  c->dfree(s->lo);
+  c->dfree(s->hi);
+  s->lo = s->hi = nullptr;
+  if (s->sid >= 0) c->free_sid(s->sid);
+  s->sid = -1;
+}
+
+int effective_R(Ctx* c, int prec) {
+  int R = c->rhs_block;
+  if (R != 1 && R != 2 && R != 4) R = 1;
+  if (prec == 0 && R > 2) R = 2;
+  return R;
+}
+
+// resolve clover handle -> (gauge, clover, kappa op with prec fields, links in prec and FP64)
+int resolve_op(Ctx* c, int clover_h, double kappa, int prec, GaugeField** gf, CloverField** cf, KappaOp** kop) {
+  *cf = c->clover(clover_h);
+  if (!*cf) return c->fail(A2A_EHANDLE, "unknown clover handle " + std::to_string(clover_h));
+  *gf = c->gauge((*cf)->gauge);
+  if (!*gf) return c->fail(A2A_EHANDLE, "clover handle refers to an unloaded gauge field");
+  if (!(kappa > 0.0) || !std::isfinite(kappa)) return c->fail(A2A_EINVAL, "kappa must be positive and finite");
+  void *u0, *u1;
+  A2A_TRY(c->gauge_links(*gf, 0, &u0, &u1));
+  A2A_TRY(c->gauge_links(*gf, prec, &u0, &u1));
+  A2A_TRY(c->kappa_op(*cf, kappa, prec, kop));
+  return A2A_OK;
+}
+
+int solve_core(Ctx* c, int clover_h, const double* src, int nrhs, double kappa, double csw, double tol, int prec,
+               int max_iter, const double* x0, double* sol, a2a_solve_info* info) {
+  if (nrhs <= 0) return c->fail(A2A_EINVAL, "nrhs must be positive");
+  if (!(tol > 0.0)) return c->fail(A2A_EINVAL, "tol must be positive");
+  if (max_iter <= 0) return c->fail(A2A_EINVAL, "max_iter must be positive");
+  if (check_prec(prec)) return c->fail(A2A_EINVAL, "unknown precision mode");
+  if (!src || !sol) return c->fail(A2A_EINVAL, "null source or solution pointer");
+  GaugeField* gf;
+  CloverField* cf;
+  KappaOp* kop;
+  A2A_TRY(resolve_op(c, clover_h, kappa, prec, &gf, &cf, &kop));
+  if (std::fabs(csw - cf->csw) > 1e-12 * std::max(1.0, std::fabs(cf->csw)))
+    return c->fail(A2A_EINVAL, "c_sw does not match the clover handle");
+  const long hv = gf->g.hv;
+  const long long V = volume_of(gf->g);
+  Solver sv(c, prec, effective_R(c, prec));
+  const int op = sv.op_index(clover_h, kappa, kop, gf);
+  std::vector<Slot> slots(nrhs);
+  int rc = A2A_OK;
+  const double t0 = now_seconds();
+  for (int i = 0; i < nrhs && !rc; ++i) {
+    Slot& s = slots[i];
+    s.op = op;
+    s.src = src + (size_t)i * 24 * V;
+    s.sol = sol + (size_t)i * 24 * V;
+    s.x0 = x0 ? x0 + (size_t)i * 24 * V : nullptr;
+    s.tol = tol;
+    s.max_iter = max_iter;
+    s.t_submit = t0;
+    rc = slot_alloc(c, &s, prec, hv, sv.ops[op].nblk, NVEC_LO, NVEC_HI);
+  }
+  if (!rc) {
+    std::vector<int> idx;
+    for (int i = 0; i < nrhs; ++i) {
+      sv.add_slot(&slots[i]);
+      idx.push_back(i);
+    }
+    rc = sv.setup(idx);
+    if (!rc) {  // zero sources and good initial guesses finish without iterating
+      std::vector<int> early;
+      for (int i = 0; i < nrhs; ++i)
+        if (slots[i].state == SS_RUN && slots[i].last_r64 <= slots[i].target) early.push_back(i);
+      if (!early.empty()) {
+        rc = sv.finalize(early);
+        for (int i : early) slots[i].state = slots[i].info.converged ? SS_DONE : SS_RUN;
+      }
+    }
+    if (!rc) rc = sv.run_until_done(1 << 30);
+  }
+  int worst = A2A_OK;
+  for (int i = 0; i < nrhs; ++i) {
+    Slot& s = slots[i];
+    if (info) info[i] = s.info;
+    if (s.state == SS_FAIL && worst == A2A_OK) worst = s.err;
+    if (s.state == SS_FAIL && s.err == A2A_ENAN) worst = A2A_ENAN;
+  }
+  int rs = c->sync();
+  for (auto& s : slots) slot_free(c, &s);
+  if (rc) return rc;
+  if (rs) return rs;
+  if (worst == A2A_ENOTCONV) c->fail(A2A_ENOTCONV, "some sources did not converge within max_iter");
+  if (worst == A2A_EBREAKDOWN) c->fail(A2A_EBREAKDOWN, "BiCGStab broke down repeatedly");
+  if (worst == A2A_ENAN) c->fail(A2A_ENAN, "non-finite source");
+  return worst;
+}
+
+int dslash_core(Ctx* c, int clover_h, double kappa, int opk, int dagger, int prec, const double* in, double* out,
+                int nrhs) {
+  if (nrhs <= 0) return c->fail(A2A_EINVAL, "nrhs must be positive");
+  if (opk < 0 || opk > 3) return c->fail(A2A_EINVAL, "unknown operator");
+  if (check_prec(prec)) return c->fail(A2A_EINVAL, "unknown precision mode");
+  GaugeField* gf;
+  CloverField* cf;
+  KappaOp* kop;
+  A2A_TRY(resolve_op(c, clover_h, kappa, prec, &gf, &cf, &kop));
+  const long hv = gf->g.hv;
+  const long long V = volume_of(gf->g);
+  Solver sv(c, prec, effective_R(c, prec));
+  const int op = sv.op_index(clover_h, kappa, kop, gf);
+  std::vector<Slot> slots(nrhs);
+  int rc = A2A_OK;
+  for (int i = 0; i < nrhs && !rc; ++i) {
+    Slot& s = slots[i];
+    s.op = op;
+    s.src = in + (size_t)i * 24 * V;
+    s.sol = out + (size_t)i * 24 * V;
+    rc = slot_alloc(c, &s, prec, hv, sv.ops[op].nblk, 5, 0);
+    if (!rc) sv.add_slot(&s);
+  }
+  if (!rc) rc = sv.rebuild();
+  if (!rc) {
+    const int H = sv.n_hop_tiles, Vn = sv.n_vec_tiles, R = sv.R;
+    // vectors: 0 in_e, 1 in_o, 2 out_e, 3 out_o, 4 tmp
+    rc = sv.layout_in(false, Vn, 0, 0, prec, 0, 1, dagger, RED_NONE);
+    if (!rc) switch (opk) {
+        case A2A_OP_FULL_D:
+          rc = sv.hop(false, H, R, 0, prec, 0, 1, 2, -1, 0, -1, 0, 1.0, -1.0, 1, 0, RED_NONE, nullptr);
+          if (!rc) rc = sv.hop(false, H, R, 0, prec, 1, 0, 3, -1, 1, -1, 0, 1.0, -1.0, 1, 0, RED_NONE, nullptr);
+          break;
+        case A2A_OP_SCHUR:
+          rc = sv.hop(false, H, R, 0, prec, 0, 1, 4, -1, -1, -1, 0, 0, 1.0, 0, 1, RED_NONE, nullptr);
+          if (!rc) rc = sv.hop(false, H, R, 0, prec, 1, 4, 3, -1, 1, -1, 0, 1.0, -1.0, 2, 0, RED_NONE, nullptr);
+          if (!rc) rc = sv.vec(false, Vn, VK_ZERO_LO, 0, 0, -1, 2);
+          break;
+        case A2A_OP_HOP_EO:
+          rc = sv.hop(false, H, R, 0, prec, 0, 1, 2, -1, -1, -1, 0, 0, 1.0, 0, 0, RED_NONE, nullptr);
+          if (!rc) rc = sv.vec(false, Vn, VK_ZERO_LO, 0, 0, -1, 3);
+          break;
+        default:
+          rc = sv.hop(false, H, R, 0, prec, 1, 0, 3, -1, -1, -1, 0, 0, 1.0, 0, 0, RED_NONE, nullptr);
+          if (!rc) rc = sv.vec(false, Vn, VK_ZERO_LO, 0, 0, -1, 2);
+          break;
+      }
+    if (!rc) rc = sv.layout_out(false, Vn, 0, prec, 2, 3, dagger);
+  }
+  int rs = c->sync();
+  for (auto& s : slots) slot_free(c, &s);
+  return rc ? rc : rs;
+}
+
+int contract_ops(Ctx* c, const Geo& g, const double* src, const double* sol, int n, double** O_dev) {
+  const int V3 = g.X * g.Y * g.Z;
+  const long K = 12L * V3;
+  const int ntb = (n + 63) / 64;
+  long want = 4096 / std::max(1, g.T * ntb * ntb);
+  int nchunk = (int)std::max(1L, std::min(want, (K + 255) / 256));
+  void *part = nullptr, *O = nullptr;
+  A2A_TRY(c->dalloc(&part, sizeof(double) * 2 * (size_t)g.T * nchunk * n * n));
+  int rc = c->dalloc(&O, sizeof(double) * 2 * (size_t)g.T * n * n);
+  if (rc) {
+    c->dfree(part);
+    return rc;
+  }
+  launch_stoch_ops(g, n, src, sol, (double*)part, nchunk, (double*)O, c->stream);
+  hipError_t e = hipGetLastError();
+  rc = c->sync();
+  c->dfree(part);
+  if (e != hipSuccess) {
+    c->dfree(O);
+    return c->fail(A2A_EDEVICE, std::string("stochastic operators: ") + hipGetErrorString(e));
+  }
+  if (rc) {
+    c->dfree(O);
+    return rc;
+  }
+  *O_dev = (double*)O;
+  return A2A_OK;
+}
+
+int copy_to_host(Ctx* c, void* dst, const void* src, size_t n) {
+  A2A_HIP(c, hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, c->stream));
+  return c->sync();
+}
+
+// tiny JSON number lookup: "key": value
+double json_num(const char* js, const char* key, double dflt) {
+  if (!js) return dflt;
+  std::string k = std::string("\"") + key + "\"";
+  const char* p = std::strstr(js, k.c_str());
+  if (!p) return dflt;
+  p = std::strchr(p + k.size(), ':');
+  if (!p) return dflt;
+  return std::strtod(p + 1, nullptr);
+}
+
+}  // namespace
+
+// =========================================================================================
+// context
+// =========================================================================================
+extern "C" int a2a_init(a2a_ctx** out, int device, size_t budget, void* stream) {
+  if (!out) return A2A_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return A2A_EDEVICE;
+  if (device < 0 || device >= ndev) return A2A_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return A2A_EDEVICE;
+  auto* h = new a2a_ctx();
+  Ctx* c = &h->c;
+  c->device = device;
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      delete h;
+      return A2A_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    delete h;
+    return A2A_EDEVICE;
+  }
+  c->budget = budget ? budget : (size_t)(0.9 * (double)fr);
+  c->sid_cap = SID_CAP;
+  void* p = nullptr;
+  if (c->dalloc(&p, sizeof(double) * NSCAL * SID_CAP) ||
+      hipMemset(p, 0, sizeof(double) * NSCAL * SID_CAP) != hipSuccess) {
+    delete h;
+    return A2A_ENOMEM;
+  }
+  c->scal_pool = (double*)p;
+  if (c->dalloc(&p, sizeof(unsigned) * SID_CAP) || hipMemset(p, 0, sizeof(unsigned) * SID_CAP) != hipSuccess) {
+    delete h;
+    return A2A_ENOMEM;
+  }
+  c->counters = (unsigned*)p;
+  if (hipHostMalloc((void**)&c->scal_host, sizeof(double) * NSCAL * SID_CAP, hipHostMallocDefault) != hipSuccess) {
+    delete h;
+    return A2A_ENOMEM;
+  }
+  if (hipDeviceSynchronize() != hipSuccess) {
+    delete h;
+    return A2A_EDEVICE;
+  }
+  *out = h;
+  return A2A_OK;
+}
+
+extern "C" int a2a_finalize(a2a_ctx* h) {
+  if (!h) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  c->timing_collect();
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  std::vector<int> hs;
+  for (auto& kv : c->gauges) hs.push_back(kv.first);
+  for (int g : hs) a2a_unload(h, g);
+  for (auto& kv : c->sizes) (void)hipFree(kv.first);
+  c->sizes.clear();
+  if (c->scal_host) (void)hipHostFree(c->scal_host);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete h;
+  return A2A_OK;
+}
+
+extern "C" const char* a2a_last_error(const a2a_ctx* h) { return h ? h->c.err.c_str() : "null context"; }
+
+extern "C" int a2a_set_option(a2a_ctx* h, const char* key, double v) {
+  if (!h || !key) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  std::string k(key);
+  if (k == "rhs_block") {
+    int r = (int)v;
+    if (r != 1 && r != 2 && r != 4) return c->fail(A2A_EINVAL, "rhs_block must be 1, 2 or 4");
+    c->rhs_block = r;
+  } else if (k == "check_every") {
+    if (v < 1) return c->fail(A2A_EINVAL, "check_every must be >= 1");
+    c->check_every = (int)v;
+  } else if (k == "delta") {
+    if (!(v > 0 && v < 1)) return c->fail(A2A_EINVAL, "delta must be in (0, 1)");
+    c->delta_lo = v;
+  } else if (k == "delta64") {
+    if (!(v > 0 && v < 1)) return c->fail(A2A_EINVAL, "delta64 must be in (0, 1)");
+    c->delta_64 = v;
+  } else if (k == "xcd_order") {
+    c->xcd_order = v != 0;
+  } else if (k == "kernel_timing") {
+    c->timing = v != 0;
+  } else if (k == "hbm_budget") {
+    if (!(v > 0)) return c->fail(A2A_EINVAL, "hbm_budget must be positive");
+    c->budget = (size_t)v;
+  } else {
+    return c->fail(A2A_EINVAL, "unknown option " + k);
+  }
+  return A2A_OK;
+}
+
+extern "C" size_t a2a_mem_in_use(const a2a_ctx* h) { return h ? h->c.used : 0; }
+
+// =========================================================================================
+// resident fields
+// =========================================================================================
+static int load_gauge_impl(a2a_ctx* h, const a2a_geom* geom, const double* links, int* gauge_h, bool dev) {
+  if (!h || !links || !gauge_h) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  Geo g;
+  if (geom_to_geo(geom, &g)) return c->fail(A2A_EINVAL, "lattice extents must be even and >= 2, t_bc = +-1");
+  const size_t n = (size_t)2 * g.hv * 72;
+  if (!dev)
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(links[i])) return c->fail(A2A_ENAN, "non-finite gauge link");
+  auto gf = std::make_unique<GaugeField>();
+  gf->geom = *geom;
+  gf->g = g;
+  void* p = nullptr;
+  A2A_TRY(c->dalloc(&p, n * sizeof(double)));
+  gf->canon = (double*)p;
+  A2A_HIP(c, hipMemcpyAsync(gf->canon, links, n * sizeof(double), dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                            c->stream));
+  gf->handle = c->next_handle++;
+  GaugeField* raw = gf.get();
+  c->gauges[gf->handle] = std::move(gf);
+  void *u0, *u1;
+  int rc = c->gauge_links(raw, 0, &u0, &u1);
+  if (!rc) rc = c->sync();
+  if (rc) {
+    a2a_unload(h, raw->handle);
+    return rc;
+  }
+  *gauge_h = raw->handle;
+  return A2A_OK;
+}
+
+extern "C" int a2a_load_gauge(a2a_ctx* h, const a2a_geom* geom, const double* links, int* gauge_h) {
+  return load_gauge_impl(h, geom, links, gauge_h, false);
+}
+
+extern "C" int a2a_load_gauge_dev(a2a_ctx* h, const a2a_geom* geom, const double* links, int* gauge_h) {
+  return load_gauge_impl(h, geom, links, gauge_h, true);
+}
+
+extern "C" int a2a_load_clover(a2a_ctx* h, int gauge_h, double csw, int* clover_h) {
+  if (!h || !clover_h) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  GaugeField* gf = c->gauge(gauge_h);
+  if (!gf) return c->fail(A2A_EHANDLE, "unknown gauge handle");
+  if (!std::isfinite(csw)) return c->fail(A2A_EINVAL, "c_sw must be finite");
+  auto cf = std::make_unique<CloverField>();
+  cf->gauge = gauge_h;
+  cf->csw = csw;
+  const size_t cb = clover_bytes<double>(gf->g.hv);
+  void *p0 = nullptr, *p1 = nullptr;
+  A2A_TRY(c->dalloc(&p0, cb));
+  int rc = c->dalloc(&p1, cb);
+  if (rc) {
+    c->dfree(p0);
+    return rc;
+  }
+  cf->G[0] = (double*)p0;
+  cf->G[1] = (double*)p1;
+  launch_clover_field(gf->g, gf->canon, cf->G, c->stream);
+  A2A_HIP(c, hipGetLastError());
+  A2A_TRY(c->sync());
+  cf->handle = c->next_handle++;
+  *clover_h = cf->handle;
+  c->clovers[cf->handle] = std::move(cf);
+  return A2A_OK;
+}
+
+static void free_clover(Ctx* c, CloverField* cf) {
+  for (auto& k : cf->kops) {
+    for (int p = 0; p < 2; ++p) {
+      c->dfree(k->A64[p]);
+      c->dfree(k->Ai64[p]);
+      for (int q = 1; q < 4; ++q) {
+        c->dfree(k->Alo[q][p]);
+        c->dfree(k->Ailo[q][p]);
+      }
+    }
+  }
+  c->dfree(cf->G[0]);
+  c->dfree(cf->G[1]);
+}
+
+extern "C" int a2a_unload(a2a_ctx* h, int handle) {
+  if (!h) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipStreamSynchronize(c->stream);
+  if (auto* cf = c->clover(handle)) {
+    free_clover(c, cf);
+    c->clovers.erase(handle);
+    return A2A_OK;
+  }
+  if (auto* gf = c->gauge(handle)) {
+    std::vector<int> dead;
+    for (auto& kv : c->clovers)
+      if (kv.second->gauge == handle) dead.push_back(kv.first);
+    for (int d : dead) {
+      free_clover(c, c->clover(d));
+      c->clovers.erase(d);
+    }
+    c->dfree(gf->canon);
+    for (int q = 0; q < 4; ++q)
+      for (int p = 0; p < 2; ++p) c->dfree(gf->U[q][p]);
+    c->gauges.erase(handle);
+    return A2A_OK;
+  }
+  return c->fail(A2A_EHANDLE, "unknown handle");
+}
+
+// =========================================================================================
+// operator application
+// =========================================================================================
+extern "C" int a2a_dslash_clover_dev(a2a_ctx* h, int clover_h, double kappa, int op, int dagger, int prec,
+                                     const double* in, double* out, int nrhs) {
+  if (!h || !in || !out) return A2A_EINVAL;
+  (void)hipSetDevice(h->c.device);
+  return dslash_core(&h->c, clover_h, kappa, op, dagger ? 1 : 0, prec, in, out, nrhs);
+}
+
+extern "C" int a2a_dslash_clover(a2a_ctx* h, int clover_h, double kappa, int op, int dagger, int prec,
+                                 const double* in, double* out, int nrhs) {
+  if (!h || !in || !out) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  CloverField* cf = c->clover(clover_h);
+  if (!cf) return c->fail(A2A_EHANDLE, "unknown clover handle");
+  if (nrhs <= 0) return c->fail(A2A_EINVAL, "nrhs must be positive");
+  const size_t n = (size_t)nrhs * 24 * volume_of(c->gauge(cf->gauge)->g) * sizeof(double);
+  void *di = nullptr, *dout = nullptr;
+  A2A_TRY(c->dalloc(&di, n));
+  int rc = c->dalloc(&dout, n);
+  if (!rc) {
+    if (hipMemcpyAsync(di, in, n, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      rc = c->fail(A2A_EDEVICE, "host to device copy failed");
+  }
+  if (!rc) rc = dslash_core(c, clover_h, kappa, op, dagger ? 1 : 0, prec, (const double*)di, (double*)dout, nrhs);
+  if (!rc) rc = copy_to_host(c, out, dout, n);
+  c->sync();
+  c->dfree(di);
+  c->dfree(dout);
+  return rc;
+}
+
+extern "C" int a2a_bench_stencil(a2a_ctx* h, int clover_h, double kappa, int opk, int prec, int nrhs, int reps,
+                                 double* ms) {
+  if (!h || !ms || nrhs <= 0 || reps <= 0) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  if (check_prec(prec)) return c->fail(A2A_EINVAL, "unknown precision mode");
+  if (opk != A2A_OP_HOP_EO && opk != A2A_OP_SCHUR) return c->fail(A2A_EINVAL, "op must be HOP_EO or SCHUR");
+  GaugeField* gf;
+  CloverField* cf;
+  KappaOp* kop;
+  A2A_TRY(resolve_op(c, clover_h, kappa, prec, &gf, &cf, &kop));
+  Solver sv(c, prec, effective_R(c, prec));
+  const int op = sv.op_index(clover_h, kappa, kop, gf);
+  std::vector<Slot> slots(nrhs);
+  int rc = A2A_OK;
+  for (int i = 0; i < nrhs && !rc; ++i) {
+    slots[i].op = op;
+    rc = slot_alloc(c, &slots[i], prec, gf->g.hv, sv.ops[op].nblk, 5, 0);
+    if (!rc) sv.add_slot(&slots[i]);
+  }
+  if (!rc) rc = sv.rebuild();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!rc) {
+    const int H = sv.n_hop_tiles, Vn = sv.n_vec_tiles, R = sv.R;
+    rc = sv.vec(false, Vn, VK_FILL_LO, 0, 0, -1, 0);
+    if (!rc) rc = sv.vec(false, Vn, VK_FILL_LO, 0, 0, -1, 1);
+    auto once = [&]() -> int {
+      if (opk == A2A_OP_HOP_EO)
+        return sv.hop(false, H, R, 0, prec, 0, 1, 2, -1, -1, -1, 0, 0, 1.0, 0, 0, RED_NONE, nullptr);
+      int r = sv.hop(false, H, R, 0, prec, 0, 1, 4, -1, -1, -1, 0, 0, 1.0, 0, 1, RED_NONE, nullptr);
+      if (!r) r = sv.hop(false, H, R, 0, prec, 1, 4, 3, -1, 1, -1, 0, 1.0, -1.0, 2, 0, RED_NONE, nullptr);
+      return r;
+    };
+    for (int w = 0; w < 2 && !rc; ++w) rc = once();
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+      rc = c->fail(A2A_EDEVICE, "hipEventCreate failed");
+    if (!rc && hipEventRecord(e0, c->stream) != hipSuccess) rc = c->fail(A2A_EDEVICE, "hipEventRecord failed");
+    for (int w = 0; w < reps && !rc; ++w) rc = once();
+    if (!rc && hipEventRecord(e1, c->stream) != hipSuccess) rc = c->fail(A2A_EDEVICE, "hipEventRecord failed");
+    if (!rc) rc = c->sync();
+    float t = 0;
+    if (!rc && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = c->fail(A2A_EDEVICE, "hipEventElapsedTime failed");
+    if (!rc) *ms = t / reps;
+  }
+  c->sync();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (auto& s : slots) slot_free(c, &s);
+  return rc;
+}
+
+// =========================================================================================
+// solves
+// =========================================================================================
+extern "C" int a2a_solve_propagators_dev(a2a_ctx* h, int clover_h, const double* src, int nrhs, double kappa,
+                                         double csw, double tol, int prec, int max_iter, const double* x0,
+                                         double* sol, a2a_solve_info* info) {
+  if (!h) return A2A_EINVAL;
+  (void)hipSetDevice(h->c.device);
+  return solve_core(&h->c, clover_h, src, nrhs, kappa, csw, tol, prec, max_iter, x0, sol, info);
+}
+
+extern "C" int a2a_solve_propagators(a2a_ctx* h, int clover_h, const double* src, int nrhs, double kappa,
+                                     double csw, double tol, int prec, int max_iter, const double* x0,
+                                     double* sol, a2a_solve_info* info) {
+  if (!h || !src || !sol) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  CloverField* cf = c->clover(clover_h);
+  if (!cf) return c->fail(A2A_EHANDLE, "unknown clover handle");
+  if (nrhs <= 0) return c->fail(A2A_EINVAL, "nrhs must be positive");
+  const size_t n = (size_t)nrhs * 24 * volume_of(c->gauge(cf->gauge)->g);
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(src[i])) return c->fail(A2A_ENAN, "non-finite source");
+  void *ds = nullptr, *dx = nullptr, *d0 = nullptr;
+  A2A_TRY(c->dalloc(&ds, n * sizeof(double)));
+  int rc = c->dalloc(&dx, n * sizeof(double));
+  if (!rc && x0) rc = c->dalloc(&d0, n * sizeof(double));
+  if (!rc && hipMemcpyAsync(ds, src, n * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    rc = c->fail(A2A_EDEVICE, "host to device copy failed");
+  if (!rc && x0 && hipMemcpyAsync(d0, x0, n * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    rc = c->fail(A2A_EDEVICE, "host to device copy failed");
+  int solve_rc = A2A_OK;
+  if (!rc) {
+    solve_rc = solve_core(c, clover_h, (const double*)ds, nrhs, kappa, csw, tol, prec, max_iter, (const double*)d0,
+                          (double*)dx, info);
+    if (solve_rc == A2A_OK || solve_rc == A2A_ENOTCONV || solve_rc == A2A_EBREAKDOWN)
+      rc = copy_to_host(c, sol, dx, n * sizeof(double));
+    else
+      rc = solve_rc;
+  }
+  c->sync();
+  c->dfree(ds);
+  c->dfree(dx);
+  c->dfree(d0);
+  return rc ? rc : solve_rc;
+}
+
+// =========================================================================================
+// contractions
+// =========================================================================================
+static int pion_impl(a2a_ctx* h, const a2a_geom* geom, const double* src, const double* sol, int n, int mode,
+                     double* corr, double* O_host, bool dev) {
+  if (!h || !src || !sol || !corr) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  Geo g;
+  if (geom_to_geo(geom, &g)) return c->fail(A2A_EINVAL, "bad lattice geometry");
+  if (n < 1 || (mode == A2A_PION_UNBIASED && n < 2) || (mode != 0 && mode != 1))
+    return c->fail(A2A_EINVAL, "need nrhs >= 2 for the unbiased estimator and mode 0 or 1");
+  const size_t nel = (size_t)n * 24 * 2 * g.hv;
+  const double *ds = src, *dx = sol;
+  void *bs = nullptr, *bx = nullptr;
+  if (!dev) {
+    A2A_TRY(c->dalloc(&bs, nel * sizeof(double)));
+    int rc = c->dalloc(&bx, nel * sizeof(double));
+    if (rc) {
+      c->dfree(bs);
+      return rc;
+    }
+    (void)hipMemcpyAsync(bs, src, nel * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    (void)hipMemcpyAsync(bx, sol, nel * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    ds = (const double*)bs;
+    dx = (const double*)bx;
+  }
+  double* O = nullptr;
+  int rc = contract_ops(c, g, ds, dx, n, &O);
+  void* dc = nullptr;
+  if (!rc) rc = c->dalloc(&dc, sizeof(double) * 2 * g.T);
+  if (!rc) {
+    launch_pion_corr(g.T, n, O, mode, (double*)dc, c->stream);
+    rc = copy_to_host(c, corr, dc, sizeof(double) * 2 * g.T);
+  }
+  if (!rc && O_host) rc = copy_to_host(c, O_host, O, sizeof(double) * 2 * (size_t)g.T * n * n);
+  c->sync();
+  c->dfree(dc);
+  c->dfree(O);
+  c->dfree(bs);
+  c->dfree(bx);
+  return rc;
+}
+
+extern "C" int a2a_contract_pion_2pt(a2a_ctx* h, const a2a_geom* geom, const double* src, const double* sol, int n,
+                                     int mode, double* corr, double* O) {
+  return pion_impl(h, geom, src, sol, n, mode, corr, O, false);
+}
+
+extern "C" int a2a_contract_pion_2pt_dev(a2a_ctx* h, const a2a_geom* geom, const double* src, const double* sol,
+                                         int n, int mode, double* corr, double* O) {
+  return pion_impl(h, geom, src, sol, n, mode, corr, O, true);
+}
+
+static int pipi_impl(a2a_ctx* h, const a2a_geom* geom, const double* src, const double* sol, int n, double* diag,
+                     double* vac, bool dev) {
+  if (!h || !src || !sol || !diag) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  Geo g;
+  if (geom_to_geo(geom, &g)) return c->fail(A2A_EINVAL, "bad lattice geometry");
+  if (n < 4 || n % 4 || n / 4 > 32) return c->fail(A2A_EINVAL, "pi-pi needs nrhs = 4m with 1 <= m <= 32");
+  const size_t nel = (size_t)n * 24 * 2 * g.hv;
+  const double *ds = src, *dx = sol;
+  void *bs = nullptr, *bx = nullptr;
+  if (!dev) {
+    A2A_TRY(c->dalloc(&bs, nel * sizeof(double)));
+    int rc = c->dalloc(&bx, nel * sizeof(double));
+    if (rc) {
+      c->dfree(bs);
+      return rc;
+    }
+    (void)hipMemcpyAsync(bs, src, nel * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    (void)hipMemcpyAsync(bx, sol, nel * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    ds = (const double*)bs;
+    dx = (const double*)bx;
+  }
+  double* O = nullptr;
+  int rc = contract_ops(c, g, ds, dx, n, &O);
+  void *dd = nullptr, *dv = nullptr;
+  if (!rc) rc = c->dalloc(&dd, sizeof(double) * 2 * 4 * g.T);
+  if (!rc) rc = c->dalloc(&dv, sizeof(double) * 2 * g.T);
+  if (!rc) {
+    launch_pipi(g.T, n, O, (double*)dd, (double*)dv, c->stream);
+    rc = copy_to_host(c, diag, dd, sizeof(double) * 2 * 4 * g.T);
+    if (!rc && vac) rc = copy_to_host(c, vac, dv, sizeof(double) * 2 * g.T);
+  }
+  c->sync();
+  c->dfree(dd);
+  c->dfree(dv);
+  c->dfree(O);
+  c->dfree(bs);
+  c->dfree(bx);
+  return rc;
+}
+
+extern "C" int a2a_contract_pipi_2pt(a2a_ctx* h, const a2a_geom* geom, const double* src, const double* sol, int n,
+                                     double* diag, double* vac) {
+  return pipi_impl(h, geom, src, sol, n, diag, vac, false);
+}
+
+extern "C" int a2a_contract_pipi_2pt_dev(a2a_ctx* h, const a2a_geom* geom, const double* src, const double* sol,
+                                         int n, double* diag, double* vac) {
+  return pipi_impl(h, geom, src, sol, n, diag, vac, true);
+}
+
+extern "C" int a2a_z2_noise_dev(a2a_ctx* h, const a2a_geom* geom, unsigned long long seed, long long src_offset,
+                                int nsrc, double* out) {
+  if (!h || !out) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  Geo g;
+  if (geom_to_geo(geom, &g)) return c->fail(A2A_EINVAL, "bad lattice geometry");
+  if (nsrc <= 0 || src_offset < 0) return c->fail(A2A_EINVAL, "nsrc must be positive, src_offset >= 0");
+  launch_z2_noise(2L * g.hv, nsrc, seed, src_offset, out, c->stream);
+  A2A_HIP(c, hipGetLastError());
+  return c->sync();
+}
+
+extern "C" int a2a_kernel_stats(a2a_ctx* h, const char* name, long long* launches, double* total_ms,
+                                double* alg_bytes, int reset) {
+  if (!h || !name) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  A2A_TRY(c->timing_collect());
+  std::string n(name);
+  int k = n == "schur1" ? 0 : n == "schur2" ? 1 : n == "blas" ? 2 : -1;
+  if (k < 0) return c->fail(A2A_EINVAL, "kernel class must be schur1, schur2 or blas");
+  if (launches) *launches = c->t_launches[k];
+  if (total_ms) *total_ms = c->t_ms[k];
+  if (alg_bytes) *alg_bytes = c->t_bytes[k];
+  if (reset)
+    for (int i = 0; i < 3; ++i) {
+      c->t_launches[i] = 0;
+      c->t_ms[i] = 0;
+      c->t_bytes[i] = 0;
+    }
+  return A2A_OK;
+}
+
+// =========================================================================================
+// serving engine: continuous batching
+// =========================================================================================
+struct Request {
+  long long ticket;
+  int clover_h;
+  double kappa;
+  const double* src;
+  double* sol;
+  int nsrc;
+  double tol;
+  int prec;
+  int max_iter;
+  int state = 0;  // 0 queued, 1 running, 2 done, -1 failed
+  int err = A2A_OK;
+  double t_submit = 0;
+  std::vector<Slot> slots;
+};
+
+struct a2a_engine {
+  a2a_ctx* h;
+  int max_slots = 256;
+  int max_queue = 4096;
+  std::deque<Request*> queue;
+  std::map<long long, std::unique_ptr<Request>> reqs;
+  std::unique_ptr<Solver> solvers[4];
+  long long next_ticket = 1;
+  int active = 0;
+};
+
+extern "C" int a2a_engine_create(a2a_ctx* h, const char* policy, a2a_engine** out) {
+  if (!h || !out) return A2A_EINVAL;
+  auto* e = new a2a_engine();
+  e->h = h;
+  e->max_slots = (int)json_num(policy, "max_slots", 256);
+  e->max_queue = (int)json_num(policy, "max_queue", 4096);
+  int ce = (int)json_num(policy, "check_every", h->c.check_every);
+  if (e->max_slots < 1 || e->max_queue < 1 || ce < 1) {
+    delete e;
+    return h->c.fail(A2A_EINVAL, "bad engine policy");
+  }
+  h->c.check_every = ce;
+  *out = e;
+  return A2A_OK;
+}
+
+extern "C" int a2a_engine_submit(a2a_engine* e, int clover_h, double kappa, const double* src, int nsrc, double tol,
+                                 int prec, int max_iter, double* sol, long long* ticket) {
+  if (!e || !ticket) return A2A_EINVAL;
+  Ctx* c = &e->h->c;
+  if (!src || !sol || nsrc <= 0 || !(tol > 0) || check_prec(prec) || max_iter <= 0 || !(kappa > 0))
+    return c->fail(A2A_EINVAL, "bad request");
+  if (!c->clover(clover_h)) return c->fail(A2A_EHANDLE, "unknown clover handle");
+  if (nsrc > e->max_slots) return c->fail(A2A_EINVAL, "request larger than the engine's slot capacity");
+  if ((int)e->queue.size() >= e->max_queue) return c->fail(A2A_EAGAIN, "queue full");
+  auto r = std::make_unique<Request>();
+  r->ticket = e->next_ticket++;
+  r->clover_h = clover_h;
+  r->kappa = kappa;
+  r->src = src;
+  r->sol = sol;
+  r->nsrc = nsrc;
+  r->tol = tol;
+  r->prec = prec;
+  r->max_iter = max_iter;
+  r->t_submit = now_seconds();
+  e->queue.push_back(r.get());
+  *ticket = r->ticket;
+  e->reqs[r->ticket] = std::move(r);
+  return A2A_OK;
+}
+
+static void engine_release(a2a_engine* e, Request* r) {
+  Ctx* c = &e->h->c;
+  for (auto& s : r->slots) slot_free(c, &s);
+  e->active -= r->nsrc;
+}
+
+// try to admit one request; returns A2A_OK (admitted), A2A_ENOMEM (no room now), or an error
+static int engine_admit(a2a_engine* e, Request* r) {
+  Ctx* c = &e->h->c;
+  GaugeField* gf;
+  CloverField* cf;
+  KappaOp* kop;
+  int rc = resolve_op(c, r->clover_h, r->kappa, r->prec, &gf, &cf, &kop);
+  if (rc) return rc;
+  auto& sv = e->solvers[r->prec];
+  if (!sv) sv = std::make_unique<Solver>(c, r->prec, effective_R(c, r->prec));
+  const int op = sv->op_index(r->clover_h, r->kappa, kop, gf);
+  const long long V = volume_of(gf->g);
+  r->slots.assign(r->nsrc, Slot());
+  for (int i = 0; i < r->nsrc; ++i) {
+    Slot& s = r->slots[i];
+    s.op = op;
+    s.src = r->src + (size_t)i * 24 * V;
+    s.sol = r->sol + (size_t)i * 24 * V;
+    s.tol = r->tol;
+    s.max_iter = r->max_iter;
+    s.t_submit = r->t_submit;
+    s.req = r->ticket;
+    s.req_idx = i;
+    rc = slot_alloc(c, &s, r->prec, gf->g.hv, sv->ops[op].nblk, NVEC_LO, NVEC_HI);
+    if (rc) {
+      for (int j = 0; j <= i; ++j) slot_free(c, &r->slots[j]);
+      r->slots.clear();
+      return rc;
+    }
+  }
+  e->active += r->nsrc;
+  std::vector<int> idx;
+  for (auto& s : r->slots) {
+    idx.push_back((int)sv->live.size());
+    sv->add_slot(&s);
+  }
+  rc = sv->setup(idx);
+  if (rc) return rc;
+  std::vector<int> early;
+  for (int i : idx)
+    if (sv->live[i]->state == SS_RUN && sv->live[i]->last_r64 <= sv->live[i]->target) early.push_back(i);
+  if (!early.empty()) {
+    rc = sv->finalize(early);
+    for (int i : early) sv->live[i]->state = sv->live[i]->info.converged ? SS_DONE : SS_RUN;
+  }
+  r->state = 1;
+  return rc;
+}
+
+extern "C" int a2a_engine_step(a2a_engine* e, int iters, int* active) {
+  if (!e || iters < 0) return A2A_EINVAL;
+  Ctx* c = &e->h->c;
+  (void)hipSetDevice(c->device);
+  // admission, first come first served, by slot capacity and the HBM budget
+  while (!e->queue.empty()) {
+    Request* r = e->queue.front();
+    if (r->state == -1) {  // cancelled while queued
+      e->queue.pop_front();
+      continue;
+    }
+    if (e->active + r->nsrc > e->max_slots) break;
+    int rc = engine_admit(e, r);
+    if (rc == A2A_ENOMEM && e->active > 0) {  // wait for memory to free up
+      c->err.clear();
+      break;
+    }
+    e->queue.pop_front();
+    if (rc) {
+      r->state = -1;
+      r->err = rc;
+      for (auto& s : r->slots) s.state = SS_FAIL;
+    }
+  }
+  // iterate every active slot of every precision
+  for (int p = 0; p < 4; ++p) {
+    auto& sv = e->solvers[p];
+    if (!sv) continue;
+    A2A_TRY(sv->retire());
+    for (int k = 1; k <= iters && !sv->live.empty(); ++k) {
+      A2A_TRY(sv->rebuild());
+      A2A_TRY(sv->iteration());
+      if (k % c->check_every == 0 || k == iters) {
+        A2A_TRY(sv->check());
+        A2A_TRY(sv->retire());
+        A2A_TRY(sv->rebuild());
+        if (sv->live.empty()) break;
+      }
+      A2A_TRY(sv->vec(false, sv->n_vec_tiles, VK_BICG_P));
+    }
+  }
+  // retire finished requests
+  for (auto& kv : e->reqs) {
+    Request* r = kv.second.get();
+    if (r->state != 1) continue;
+    bool all = true, failed = false;
+    for (auto& s : r->slots) {
+      if (s.state != SS_DONE && s.state != SS_FAIL) all = false;
+      if (s.state == SS_FAIL) {
+        failed = true;
+        if (r->err == A2A_OK) r->err = s.err;
+      }
+    }
+    if (all) {
+      r->state = failed ? -1 : 2;
+      engine_release(e, r);
+    }
+  }
+  if (active) *active = e->active;
+  return A2A_OK;
+}
+
+extern "C" int a2a_engine_poll(a2a_engine* e, long long ticket, int* done, a2a_solve_info* info) {
+  if (!e || !done) return A2A_EINVAL;
+  auto it = e->reqs.find(ticket);
+  if (it == e->reqs.end()) return e->h->c.fail(A2A_EHANDLE, "unknown ticket");
+  Request* r = it->second.get();
+  *done = r->state == 2 ? 1 : (r->state == -1 ? -1 : 0);
+  if (info && (r->state == 2 || r->state == -1) && !r->slots.empty())
+    for (int i = 0; i < r->nsrc; ++i) info[i] = r->slots[i].info;
+  return r->state == -1 ? r->err : A2A_OK;
+}
+
+extern "C" int a2a_engine_cancel(a2a_engine* e, long long ticket) {
+  if (!e) return A2A_EINVAL;
+  auto it = e->reqs.find(ticket);
+  if (it == e->reqs.end()) return e->h->c.fail(A2A_EHANDLE, "unknown ticket");
+  Request* r = it->second.get();
+  if (r->state == 0) {
+    r->state = -1;
+    r->err = A2A_EINVAL;
+  } else if (r->state == 1) {
+    for (auto& s : r->slots)
+      if (s.state != SS_DONE) {
+        s.state = SS_FAIL;
+        s.err = A2A_EINVAL;
+      }
+  }
+  return A2A_OK;
+}
+
+extern "C" int a2a_engine_destroy(a2a_engine* e) {
+  if (!e) return A2A_EINVAL;
+  Ctx* c = &e->h->c;
+  (void)c->sync();
+  for (auto& kv : e->reqs)
+    if (kv.second->state == 1) engine_release(e, kv.second.get());
+  for (auto& s : e->solvers) s.reset();
+  delete e;
+  return A2A_OK;
+}

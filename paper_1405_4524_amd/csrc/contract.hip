@@ -1,0 +1,267 @@
+// contract.hip -- the stochastic-operator contraction (Sec. 7, eq. stoop) and the
+// zero-momentum pion / pi-pi correlators built from it (Sec. 7; Sec. 5 and 8 diagrams).
+//
+//   O_ab(t) = sum_{y in timeslice t} eta_a(y)^dag gamma_5 X_b(y)
+//
+// is, per timeslice, a complex matrix product E_t^dag (gamma_5 X_t) with inner dimension
+// K = 12 L^3 taken straight from the canonical [src][t][z][y][x][spin][colour] arrays, where
+// each (source, timeslice) column is contiguous.  Blocks own a K-chunk of one timeslice and
+// a 64x64 tile of (a, b); operand tiles are staged through LDS and each thread keeps a 4x4
+// register tile of FP64 accumulators.  Chunk partials are summed in fixed order.
+#include "a2a_kernels.h"
+
+namespace a2a {
+
+constexpr int CT = 64;   // output tile edge
+constexpr int KC = 16;   // complex elements per K step
+
+__global__ __launch_bounds__(256) void k_stoch_partial(int n, long V, int V3, int nchunk, int kchunk,
+                                                        const double* __restrict__ eta,
+                                                        const double* __restrict__ X, double* partial) {
+  __shared__ double2 Es[CT][KC + 1];
+  __shared__ double2 Xs[CT][KC + 1];
+  const int chunk = blockIdx.x, t = blockIdx.y;
+  const int ntb = (n + CT - 1) / CT;
+  const int ta = blockIdx.z / ntb, tb = blockIdx.z % ntb;
+  const int a0 = ta * CT, b0 = tb * CT;
+  const long K = 12L * V3;
+  const long k_begin = (long)chunk * kchunk;
+  const long k_end = min(K, k_begin + kchunk);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double accr[4][4], acci[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) accr[i][j] = acci[i][j] = 0.0;
+  const size_t src_stride = (size_t)12 * V;  // complex per source
+  const size_t tbase = (size_t)t * V3 * 12;
+  for (long k0 = k_begin; k0 < k_end; k0 += KC) {
+    // stage: 64 rows x 16 complex for each operand = 1024 complex each, 4 per thread
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + q * 256;
+      const int row = e / KC, kk = e % KC;
+      const long k = k0 + kk;
+      double2 ev = make_double2(0.0, 0.0), xv = make_double2(0.0, 0.0);
+      if (k < k_end) {
+        if (a0 + row < n) {
+          const double* p = eta + 2 * ((size_t)(a0 + row) * src_stride + tbase + k);
+          ev = make_double2(p[0], p[1]);
+        }
+        if (b0 + row < n) {
+          const double* p = X + 2 * ((size_t)(b0 + row) * src_stride + tbase + k);
+          const double sg = ((k % 12) >= 6) ? -1.0 : 1.0;  // gamma_5 = diag(1,1,-1,-1)
+          xv = make_double2(sg * p[0], sg * p[1]);
+        }
+      }
+      Es[row][kk] = ev;
+      Xs[row][kk] = xv;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < KC; ++kk) {
+      double2 e[4], x[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) e[i] = Es[ty * 4 + i][kk];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[j] = Xs[tx * 4 + j][kk];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {  // conj(e) * x
+          accr[i][j] += e[i].x * x[j].x + e[i].y * x[j].y;
+          acci[i][j] += e[i].x * x[j].y - e[i].y * x[j].x;
+        }
+    }
+    __syncthreads();
+  }
+  double* out = partial + (((size_t)t * nchunk + chunk) * n) * n * 2;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int a = a0 + ty * 4 + i, b = b0 + tx * 4 + j;
+      if (a < n && b < n) {
+        out[2 * ((size_t)a * n + b)] = accr[i][j];
+        out[2 * ((size_t)a * n + b) + 1] = acci[i][j];
+      }
+    }
+}
+
+__global__ void k_stoch_sum(int n, int T, int nchunk, const double* partial, double* O) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;  // over T*n*n complex
+  const long per = (long)n * n;
+  if (i >= (long)T * per) return;
+  const long t = i / per, ab = i % per;
+  double sr = 0.0, si = 0.0;
+  for (int c = 0; c < nchunk; ++c) {
+    const double* p = partial + (((size_t)t * nchunk + c) * per + ab) * 2;
+    sr += p[0];
+    si += p[1];
+  }
+  O[2 * i] = sr;
+  O[2 * i + 1] = si;
+}
+
+void launch_stoch_ops(const Geo& g, int n, const double* eta, const double* X, double* partial, int nchunk,
+                      double* O, hipStream_t s) {
+  const int V3 = g.X * g.Y * g.Z;
+  const long V = (long)V3 * g.T;
+  const long K = 12L * V3;
+  long kchunk = (K + nchunk - 1) / nchunk;
+  kchunk = ((kchunk + KC - 1) / KC) * KC;
+  const int ntb = (n + CT - 1) / CT;
+  dim3 grid(nchunk, g.T, ntb * ntb);
+  hipLaunchKernelGGL(k_stoch_partial, grid, dim3(256), 0, s, n, V, V3, nchunk, (int)kchunk, eta, X, partial);
+  const long tot = (long)g.T * n * n;
+  hipLaunchKernelGGL(k_stoch_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, g.T, nchunk, partial, O);
+}
+
+// ------------------------------------------------------------------------------------
+// pion correlator from O.  mode 0: unbiased a != b, 1/(T N (N-1)); 1: all pairs 1/(T N^2)
+// (the form printed with eq. stoop); 2, 3: the same two sums without normalisation.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pion(int T, int n, const double* O, int mode, double* corr) {
+  const int dt = blockIdx.x;
+  double sr = 0.0, si = 0.0;
+  const long per = (long)n * n;
+  for (long e = threadIdx.x; e < (long)T * per; e += 256) {
+    const int t0 = (int)(e / per);
+    const int a = (int)((e % per) / n), b = (int)(e % n);
+    if ((mode == 0 || mode == 2) && a == b) continue;
+    const int t1 = (t0 + dt) % T;
+    const double* x = O + 2 * ((size_t)t1 * per + (size_t)a * n + b);
+    const double* y = O + 2 * ((size_t)t0 * per + (size_t)b * n + a);
+    sr += x[0] * y[0] - x[1] * y[1];
+    si += x[0] * y[1] + x[1] * y[0];
+  }
+  double v[2] = {sr, si};
+  __shared__ double lds[2 * 4];
+  block_sum<2, 256>(v, lds);
+  if (threadIdx.x == 0) {
+    double norm = 1.0;
+    if (mode == 0) norm = (double)T * n * (n - 1);
+    if (mode == 1) norm = (double)T * n * n;
+    corr[2 * dt] = v[0] / norm;
+    corr[2 * dt + 1] = v[1] / norm;
+  }
+}
+
+void launch_pion_corr(int T, int n, const double* O, int mode, double* corr, hipStream_t s) {
+  hipLaunchKernelGGL(k_pion, dim3(T), dim3(256), 0, s, T, n, O, mode, corr);
+}
+
+// ------------------------------------------------------------------------------------
+// pi-pi zero-momentum pieces from four disjoint noise groups of m = N/4 sources
+// (Sec. 7: independent noise for each propagator of a diagram).  B^{gh}(t) is the m x m
+// block of O(t) with rows in group g and columns in group h.
+//   L^{gh}(t1,t2) = tr[B^{gh}(t1) B^{hg}(t2)] / m^2
+//   D0(dt) = 1/T sum_t0 L^{12}(t1,t0) L^{34}(t1,t0)          t1 = t0 + dt
+//   D1(dt) = 1/T sum_t0 L^{12}(t1,t1) L^{34}(t0,t0)          (no vacuum subtraction)
+//   D2(dt) = 1/T sum_t0 tr[B^{12}(t0) B^{23}(t1) B^{34}(t1) B^{41}(t0)] / m^4
+//   D3(dt) = 1/T sum_t0 tr[B^{12}(t1) B^{23}(t1) B^{34}(t0) B^{41}(t0)] / m^4
+//   vac(t) = L^{12}(t,t)
+// One block per dt; the 4-fold traces use two m x m products staged in LDS (m <= 32).
+// ------------------------------------------------------------------------------------
+constexpr int PIPI_MMAX = 32;
+
+__device__ __forceinline__ cx<double> oblk(const double* O, int N, int m, int t, int g, int h, int i, int j) {
+  const double* p = O + 2 * (((size_t)t * N + g * m + i) * N + h * m + j);
+  return mk(p[0], p[1]);
+}
+
+__device__ cx<double> loop2_block(const double* O, int N, int m, int g, int h, int t1, int t2, double* lds) {
+  double sr = 0.0, si = 0.0;
+  for (int e = threadIdx.x; e < m * m; e += 256) {
+    const int i = e / m, j = e % m;
+    cx<double> p = oblk(O, N, m, t1, g, h, i, j) * oblk(O, N, m, t2, h, g, j, i);
+    sr += p.re;
+    si += p.im;
+  }
+  double v[2] = {sr, si};
+  block_sum<2, 256>(v, lds);
+  __shared__ cx<double> res;
+  if (threadIdx.x == 0) res = mk(v[0], v[1]);
+  __syncthreads();
+  cx<double> r = res;
+  __syncthreads();
+  return r;
+}
+
+__device__ cx<double> loop4_block(const double* O, int N, int m, int ta, int tb, int tc, int td, cx<double>* M1,
+                                  cx<double>* M2, double* lds) {
+  for (int e = threadIdx.x; e < m * m; e += 256) {  // M1 = B12(ta) B23(tb)
+    const int i = e / m, k = e % m;
+    cx<double> acc = mk(0.0, 0.0);
+    for (int j = 0; j < m; ++j) acc = acc + oblk(O, N, m, ta, 0, 1, i, j) * oblk(O, N, m, tb, 1, 2, j, k);
+    M1[e] = acc;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < m * m; e += 256) {  // M2 = M1 B34(tc)
+    const int i = e / m, l = e % m;
+    cx<double> acc = mk(0.0, 0.0);
+    for (int k = 0; k < m; ++k) acc = acc + M1[i * m + k] * oblk(O, N, m, tc, 2, 3, k, l);
+    M2[e] = acc;
+  }
+  __syncthreads();
+  double sr = 0.0, si = 0.0;
+  for (int e = threadIdx.x; e < m * m; e += 256) {  // tr(M2 B41(td))
+    const int i = e / m, l = e % m;
+    cx<double> p = M2[i * m + l] * oblk(O, N, m, td, 3, 0, l, i);
+    sr += p.re;
+    si += p.im;
+  }
+  double v[2] = {sr, si};
+  block_sum<2, 256>(v, lds);
+  __shared__ cx<double> res;
+  if (threadIdx.x == 0) res = mk(v[0], v[1]);
+  __syncthreads();
+  cx<double> r = res;
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_pipi(int T, int N, const double* O, double* diag, double* vac) {
+  __shared__ cx<double> M1[PIPI_MMAX * PIPI_MMAX];
+  __shared__ cx<double> M2[PIPI_MMAX * PIPI_MMAX];
+  __shared__ double lds[8];
+  const int dt = blockIdx.x;
+  const int m = N / 4;
+  const double m2 = (double)m * m, m4 = m2 * m2;
+  cx<double> d0 = mk(0.0, 0.0), d1 = d0, d2 = d0, d3 = d0;
+  for (int t0 = 0; t0 < T; ++t0) {
+    const int t1 = (t0 + dt) % T;
+    cx<double> l12 = loop2_block(O, N, m, 0, 1, t1, t0, lds);
+    cx<double> l34 = loop2_block(O, N, m, 2, 3, t1, t0, lds);
+    d0 = d0 + (1.0 / (m2 * m2)) * (l12 * l34);
+    cx<double> v12 = loop2_block(O, N, m, 0, 1, t1, t1, lds);
+    cx<double> v34 = loop2_block(O, N, m, 2, 3, t0, t0, lds);
+    d1 = d1 + (1.0 / (m2 * m2)) * (v12 * v34);
+    d2 = d2 + (1.0 / m4) * loop4_block(O, N, m, t0, t1, t1, t0, M1, M2, lds);
+    d3 = d3 + (1.0 / m4) * loop4_block(O, N, m, t1, t1, t0, t0, M1, M2, lds);
+  }
+  if (threadIdx.x == 0) {
+    const double it = 1.0 / T;
+    diag[2 * (0 * T + dt)] = it * d0.re;
+    diag[2 * (0 * T + dt) + 1] = it * d0.im;
+    diag[2 * (1 * T + dt)] = it * d1.re;
+    diag[2 * (1 * T + dt) + 1] = it * d1.im;
+    diag[2 * (2 * T + dt)] = it * d2.re;
+    diag[2 * (2 * T + dt) + 1] = it * d2.im;
+    diag[2 * (3 * T + dt)] = it * d3.re;
+    diag[2 * (3 * T + dt) + 1] = it * d3.im;
+  }
+  if (vac) {
+    cx<double> v = loop2_block(O, N, m, 0, 1, dt, dt, lds);
+    if (threadIdx.x == 0) {
+      vac[2 * dt] = v.re / m2;
+      vac[2 * dt + 1] = v.im / m2;
+    }
+  }
+}
+
+void launch_pipi(int T, int n, const double* O, double* diag, double* vac, hipStream_t s) {
+  hipLaunchKernelGGL(k_pipi, dim3(T), dim3(256), 0, s, T, n, O, diag, vac);
+}
+
+}  // namespace a2a

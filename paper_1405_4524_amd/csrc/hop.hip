@@ -1,0 +1,219 @@
+// hop.hip -- the Wilson hopping stencil with fused clover / axpy / reduction epilogues.
+//
+// One thread owns one output site of one parity and R right-hand sides (a "group"), so
+// each link is loaded once per thread and applied to R spinors: the multi-RHS blocks of
+// the batched solver share link and clover traffic.  Neighbours are found from the
+// site's coordinates (no index tables), and the fermion time-boundary sign is applied
+// on the hops that wrap in t.  Blocks come from a tile list {group, site block} that the
+// host orders so that each XCD sweeps a contiguous slab of the lattice for all groups.
+#include "a2a_kernels.h"
+
+namespace a2a {
+
+enum { EPI_PLAIN = 0, EPI_CLOV = 1, EPI_INV = 2 };
+
+template <class P, int R, int EPI>
+__global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
+  using S = typename P::S;
+  using A = typename P::A;
+  const int2 tile = a.tiles[blockIdx.x];
+  const int* grp = a.groups + (size_t)tile.x * R;
+  const int slot0 = grp[0];
+  const OpDev& op = a.ops[a.slots[slot0].op];
+  const Geo g = op.g;
+  const int hv = g.hv;
+  const int site = tile.y * BS + (int)threadIdx.x;
+  const bool valid = site < hv;
+  const int sel = a.psel;
+  const int po = a.out_par, pi = 1 - po;
+
+  const char* base[R];
+  long long vs[R];
+  bool on[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int sl = grp[r];
+    on[r] = sl >= 0;
+    const SlotDev& sd = a.slots[on[r] ? sl : slot0];
+    base[r] = sd.arena[sel];
+    vs[r] = sd.vstride[sel];
+  }
+
+  Spinor<A> acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[r].v[k] = mk((A)0, (A)0);
+
+  if (valid) {
+    int c[4];
+    cb_coords(g, site, po, c);
+    const char* Uo = (const char*)op.U[sel][po];
+    const char* Ui = (const char*)op.U[sel][pi];
+    const size_t lb = LinkF<S>::bytes(hv);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      {  // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
+        const int nf = neighbor(g, c, mu, +1);
+        const A ph = (mu == 3 && c[3] == g.T - 1) ? (A)g.tbc : (A)1;
+        Su3<A> U;
+        LinkF<S>::template load<A>(Uo + mu * lb, hv, site, (A*)U.m);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (!on[r]) continue;
+          Spinor<A> p;
+          load_spinor<S, A>(base[r] + (size_t)a.vin * vs[r], hv, nf, p);
+          cx<A> h[6], uh[6];
+          project(mu, 1, p, h);
+          su3_mul_half(U, h, uh);
+          reconstruct_acc(mu, 1, uh, ph, acc[r]);
+        }
+      }
+      {  // backward: (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)
+        const int nb = neighbor(g, c, mu, -1);
+        const A ph = (mu == 3 && c[3] == 0) ? (A)g.tbc : (A)1;
+        Su3<A> U;
+        LinkF<S>::template load<A>(Ui + mu * lb, hv, nb, (A*)U.m);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (!on[r]) continue;
+          Spinor<A> p;
+          load_spinor<S, A>(base[r] + (size_t)a.vin * vs[r], hv, nb, p);
+          cx<A> h[6], uh[6];
+          project(mu, 0, p, h);
+          su3_dag_mul_half(U, h, uh);
+          reconstruct_acc(mu, 0, uh, ph, acc[r]);
+        }
+      }
+    }
+  }
+
+  // ---- epilogue: acc <- gam * acc + ca * aux1 (+ cb * A aux2) (then A^{-1} .)
+  double kp = 1.0;
+  for (int i = 0; i < a.gpow; ++i) kp *= op.kappa;
+  const A gam = (A)(a.gsign * kp);
+  const A ca = (A)a.ca, cbv = (A)a.cb;
+  if (valid) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!on[r]) continue;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[r].v[k] = gam * acc[r].v[k];
+      if (a.vaux1 >= 0) {
+        Spinor<A> x1;
+        load_spinor<S, A>(base[r] + (size_t)a.vaux1 * vs[r], hv, site, x1);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[r].v[k] = acc[r].v[k] + ca * x1.v[k];
+      }
+    }
+    if (EPI != EPI_PLAIN) {
+      const void* cbase = (EPI == EPI_CLOV) ? op.A[sel][po] : op.Ai[sel][po];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        A blk[36];
+        CloverBlkF<S>::template load<A>((const char*)cbase + b * CloverBlkF<S>::bytes(hv), hv, site, blk);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (!on[r]) continue;
+          cx<A> i6[6], o6[6];
+          if (EPI == EPI_CLOV) {
+            Spinor<A> x2;
+            load_spinor<S, A>(base[r] + (size_t)a.vaux2 * vs[r], hv, site, x2);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) i6[k] = x2.v[b * 6 + k];
+            clover_apply_block(blk, i6, o6);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc[r].v[b * 6 + k] = acc[r].v[b * 6 + k] + cbv * o6[k];
+          } else {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) i6[k] = acc[r].v[b * 6 + k];
+            clover_apply_block(blk, i6, o6);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc[r].v[b * 6 + k] = o6[k];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (on[r]) store_spinor<S, A>((char*)base[r] + (size_t)a.vout * vs[r], hv, site, acc[r]);
+  }
+
+  // ---- reductions over the values as stored
+  const int nv = red_nv(a.red);
+  if (!nv) return;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (grp[r] < 0) continue;  // uniform across the block
+    const SlotDev& sd = a.slots[grp[r]];
+    double v[3] = {0.0, 0.0, 0.0};
+    if (valid) {
+      Spinor<A> o;
+      load_spinor<S, A>(base[r] + (size_t)a.vout * vs[r], hv, site, o);
+      if (a.red == RED_ALPHA) {  // (rhat, o)
+        Spinor<A> rh;
+        load_spinor<S, A>(base[r] + (size_t)a.vrhat * vs[r], hv, site, rh);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          v[0] += (double)rh.v[k].re * o.v[k].re + (double)rh.v[k].im * o.v[k].im;
+          v[1] += (double)rh.v[k].re * o.v[k].im - (double)rh.v[k].im * o.v[k].re;
+        }
+      } else if (a.red == RED_OMEGA) {  // (o, aux2), |o|^2
+        Spinor<A> x2;
+        load_spinor<S, A>(base[r] + (size_t)a.vaux2 * vs[r], hv, site, x2);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          v[0] += (double)o.v[k].re * x2.v[k].re + (double)o.v[k].im * x2.v[k].im;
+          v[1] += (double)o.v[k].re * x2.v[k].im - (double)o.v[k].im * x2.v[k].re;
+          v[2] += (double)o.v[k].re * o.v[k].re + (double)o.v[k].im * o.v[k].im;
+        }
+      } else {  // |o|^2
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[0] += (double)o.v[k].re * o.v[k].re + (double)o.v[k].im * o.v[k].im;
+      }
+    }
+    if (nv == 3) {
+      reduce_slot<3, BS>(v, a.red, sd.sid, tile.y, sd.nblk, sd.scal, hv, a.rb);
+    } else if (nv == 2) {
+      double w[2] = {v[0], v[1]};
+      reduce_slot<2, BS>(w, a.red, sd.sid, tile.y, sd.nblk, sd.scal, hv, a.rb);
+    } else {
+      double w[1] = {v[0]};
+      reduce_slot<1, BS>(w, a.red, sd.sid, tile.y, sd.nblk, sd.scal, hv, a.rb);
+    }
+  }
+}
+
+template <class P, int R>
+static void launch_hop_r(const HopArgs& a, int ntiles, hipStream_t s) {
+  const bool clov = (a.vaux2 >= 0 && a.cb != 0.0);
+  if (a.inv)
+    hipLaunchKernelGGL((k_hop<P, R, EPI_INV>), dim3(ntiles), dim3(BS), 0, s, a);
+  else if (clov)
+    hipLaunchKernelGGL((k_hop<P, R, EPI_CLOV>), dim3(ntiles), dim3(BS), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_hop<P, R, EPI_PLAIN>), dim3(ntiles), dim3(BS), 0, s, a);
+}
+
+template <class P>
+static void launch_hop_p(int R, const HopArgs& a, int ntiles, hipStream_t s) {
+  switch (R) {
+    case 1: launch_hop_r<P, 1>(a, ntiles, s); break;
+    case 2: launch_hop_r<P, 2>(a, ntiles, s); break;
+    case 4: launch_hop_r<P, 4>(a, ntiles, s); break;
+    default: break;
+  }
+}
+
+void launch_hop(int prec, int R, const HopArgs& a, int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return;
+  switch (prec) {
+    case 0: launch_hop_p<PrecF64>(R, a, ntiles, s); break;
+    case 1: launch_hop_p<PrecF32>(R, a, ntiles, s); break;
+    case 2: launch_hop_p<PrecF16>(R, a, ntiles, s); break;
+    case 3: launch_hop_p<PrecB16>(R, a, ntiles, s); break;
+    default: break;
+  }
+}
+
+}  // namespace a2a

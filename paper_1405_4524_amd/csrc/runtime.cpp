@@ -1,0 +1,770 @@
+// runtime.cpp -- context, resident fields and the batched mixed-precision BiCGStab driver.
+//
+// Solve (Sec. 7: X_i = D^{-1} eta_i for every noise source) with even-odd preconditioning:
+//   b_o = eta_o + kappa H_oe A_ee^{-1} eta_e,   M = A_oo - kappa^2 H_oe A_ee^{-1} H_eo,
+//   M x_o = b_o,   x_e = A_ee^{-1} (eta_e + kappa H_eo x_o).
+// The odd system is solved by BiCGStab on all right-hand sides in lock step (one launch
+// per step for the whole batch) in the working precision, and corrected by FP64 reliable
+// updates: when the iterated residual has dropped by `delta` since the last update, x is
+// folded into the FP64 solution and the residual is recomputed from it with FP64 fields.
+// A source is done when the FP64 residual of the full system, ||eta - D X|| / ||eta||,
+// recomputed after reconstruction, is at most tol.
+#include "runtime.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+
+namespace a2a {
+
+double now_seconds() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int geom_to_geo(const a2a_geom* geom, Geo* g) {
+  if (!geom) return A2A_EINVAL;
+  for (int m = 0; m < 4; ++m)
+    if (geom->dims[m] < 2 || (geom->dims[m] & 1)) return A2A_EINVAL;
+  if (geom->t_bc != 1 && geom->t_bc != -1) return A2A_EINVAL;
+  long long V = 1;
+  for (int m = 0; m < 4; ++m) V *= geom->dims[m];
+  if (V / 2 > (1LL << 30)) return A2A_EINVAL;
+  g->X = geom->dims[0];
+  g->Y = geom->dims[1];
+  g->Z = geom->dims[2];
+  g->T = geom->dims[3];
+  g->Xh = g->X / 2;
+  g->hv = (int)(V / 2);
+  g->tbc = geom->t_bc;
+  g->pad = 0;
+  return A2A_OK;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (dispatch index i -> XCD i % 8).
+// Reorder a tile list so that XCD k receives the k-th contiguous eighth of the logical
+// order: neighbouring lattice slabs (and all RHS groups of one slab) share an L2.
+void xcd_order(std::vector<int2>& tiles, bool enable) {
+  const int n = (int)tiles.size();
+  if (!enable || n < 16) return;
+  std::vector<int2> out(n);
+  int start[8], cnt[8];
+  int acc = 0;
+  for (int k = 0; k < 8; ++k) {
+    cnt[k] = n / 8 + (k < n % 8 ? 1 : 0);
+    start[k] = acc;
+    acc += cnt[k];
+  }
+  for (int i = 0; i < n; ++i) out[i] = tiles[start[i % 8] + i / 8];
+  tiles.swap(out);
+}
+
+// ------------------------------------------------------------------------------------------
+// context memory
+// ------------------------------------------------------------------------------------------
+int Ctx::dalloc(void** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) return A2A_OK;
+  n = (n + 255) & ~(size_t)255;
+  if (used + n > budget)
+    return fail(A2A_ENOMEM, "HBM budget exceeded: need " + std::to_string(n) + " B, " +
+                                std::to_string(budget - std::min(budget, used)) + " B left");
+  hipError_t e = hipMalloc(p, n);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(A2A_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  used += n;
+  sizes[*p] = n;
+  return A2A_OK;
+}
+
+void Ctx::dfree(void* p) {
+  if (!p) return;
+  auto it = sizes.find(p);
+  if (it != sizes.end()) {
+    used -= it->second;
+    sizes.erase(it);
+  }
+  (void)hipFree(p);
+}
+
+int Ctx::alloc_sid(int nblk, int* sid) {
+  int s = -1;
+  for (int i = 0; i < (int)sid_used.size(); ++i)
+    if (!sid_used[i]) {
+      s = i;
+      break;
+    }
+  if (s < 0) {
+    if ((int)sid_used.size() >= sid_cap) return fail(A2A_ENOMEM, "too many concurrent right-hand sides");
+    s = (int)sid_used.size();
+    sid_used.push_back(0);
+  }
+  sid_used[s] = 1;
+  sid_max = std::max(sid_max, s);
+  A2A_TRY(ensure_partials(sid_max + 1, nblk));
+  *sid = s;
+  return A2A_OK;
+}
+
+void Ctx::free_sid(int sid) {
+  if (sid >= 0 && sid < (int)sid_used.size()) sid_used[sid] = 0;
+  while (sid_max >= 0 && !sid_used[sid_max]) --sid_max;
+}
+
+int Ctx::ensure_partials(int nslots, int nblk) {
+  if (nslots <= partial_slots && nblk <= partial_blk) return A2A_OK;
+  int ns = std::max(nslots, partial_slots);
+  ns = std::max(ns, 64);
+  int nb = std::max(nblk, partial_blk);
+  A2A_TRY(sync());
+  dfree(partials);
+  partials = nullptr;
+  void* p;
+  A2A_TRY(dalloc(&p, sizeof(double) * 4 * (size_t)ns * nb));
+  partials = (double*)p;
+  partial_slots = ns;
+  partial_blk = nb;
+  return A2A_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// kernel timing (HIP events on the context stream)
+// ------------------------------------------------------------------------------------------
+static hipEvent_t take_event(Ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int Ctx::timing_begin(int cls, hipEvent_t* a) {
+  (void)cls;
+  *a = nullptr;
+  if (!timing) return A2A_OK;
+  *a = take_event(this);
+  if (*a) A2A_HIP(this, hipEventRecord(*a, stream));
+  return A2A_OK;
+}
+
+int Ctx::timing_end(int cls, hipEvent_t a, double alg_bytes) {
+  if (!timing || !a) return A2A_OK;
+  hipEvent_t b = take_event(this);
+  if (!b) return A2A_OK;
+  A2A_HIP(this, hipEventRecord(b, stream));
+  pending.push_back({cls, a, b, alg_bytes});
+  if (pending.size() > 4096) return timing_collect();
+  return A2A_OK;
+}
+
+int Ctx::timing_collect() {
+  if (pending.empty()) return A2A_OK;
+  A2A_TRY(sync());
+  for (auto& r : pending) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      t_launches[r.cls]++;
+      t_ms[r.cls] += ms;
+      t_bytes[r.cls] += r.bytes;
+    }
+    ev_pool.push_back(r.a);
+    ev_pool.push_back(r.b);
+  }
+  pending.clear();
+  return A2A_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// resident fields
+// ------------------------------------------------------------------------------------------
+static size_t link_bytes(int prec, long hv) {
+  switch (prec) {
+    case 0: return 4 * LinkF<double>::bytes(hv);
+    case 1: return 4 * LinkF<float>::bytes(hv);
+    case 2: return 4 * LinkF<_Float16>::bytes(hv);
+    default: return 4 * LinkF<bf16_t>::bytes(hv);
+  }
+}
+
+static size_t clov_bytes(int prec, long hv) {
+  switch (prec) {
+    case 0: return clover_bytes<double>(hv);
+    case 1: return clover_bytes<float>(hv);
+    case 2: return clover_bytes<_Float16>(hv);
+    default: return clover_bytes<bf16_t>(hv);
+  }
+}
+
+static size_t spinor_bytes(int prec, long hv) {
+  size_t b;
+  switch (prec) {
+    case 0: b = SpinorF<double>::bytes(hv); break;
+    case 1: b = SpinorF<float>::bytes(hv); break;
+    case 2: b = SpinorF<_Float16>::bytes(hv); break;
+    default: b = SpinorF<bf16_t>::bytes(hv); break;
+  }
+  return (b + 255) & ~(size_t)255;
+}
+
+int Ctx::gauge_links(GaugeField* gf, int prec, void** out0, void** out1) {
+  if (!gf->U[prec][0]) {
+    void* d[2] = {nullptr, nullptr};
+    for (int p = 0; p < 2; ++p) {
+      int rc = dalloc(&d[p], link_bytes(prec, gf->g.hv));
+      if (rc) {
+        dfree(d[0]);
+        return rc;
+      }
+    }
+    launch_gauge_to_eo(prec, gf->g, gf->canon, d, stream);
+    A2A_HIP(this, hipGetLastError());
+    gf->U[prec][0] = d[0];
+    gf->U[prec][1] = d[1];
+  }
+  *out0 = gf->U[prec][0];
+  *out1 = gf->U[prec][1];
+  return A2A_OK;
+}
+
+static void free_kop(Ctx* c, KappaOp* k) {
+  for (int p = 0; p < 2; ++p) {
+    c->dfree(k->A64[p]);
+    c->dfree(k->Ai64[p]);
+    for (int q = 1; q < 4; ++q) {
+      c->dfree(k->Alo[q][p]);
+      c->dfree(k->Ailo[q][p]);
+    }
+    k->A64[p] = k->Ai64[p] = nullptr;
+  }
+}
+
+// A(kappa), A^{-1}(kappa) for a clover field, FP64 always and `prec` on demand; cached.
+int Ctx::kappa_op(CloverField* cf, double kappa, int prec, KappaOp** out) {
+  KappaOp* k = nullptr;
+  for (auto& kp : cf->kops)
+    if (kp->kappa == kappa) k = kp.get();
+  GaugeField* gf = gauge(cf->gauge);
+  const long hv = gf->g.hv;
+  if (!k) {
+    auto nk = std::make_unique<KappaOp>();
+    nk->kappa = kappa;
+    const size_t cb = clov_bytes(0, hv);
+    for (int p = 0; p < 2; ++p) {
+      void *a = nullptr, *ai = nullptr;
+      int rc = dalloc(&a, cb);
+      if (!rc) rc = dalloc(&ai, cb);
+      if (rc) {
+        dfree(a);
+        free_kop(this, nk.get());
+        return rc;
+      }
+      nk->A64[p] = (double*)a;
+      nk->Ai64[p] = (double*)ai;
+      Geo g = gf->g;
+      launch_clover_make(g, cf->G[p], kappa * cf->csw, nk->A64[p], nk->Ai64[p], stream);
+      A2A_HIP(this, hipGetLastError());
+    }
+    k = nk.get();
+    cf->kops.push_back(std::move(nk));
+  }
+  if (prec != 0 && !k->Alo[prec][0]) {
+    const size_t cb = clov_bytes(prec, hv);
+    for (int p = 0; p < 2; ++p) {
+      void *a = nullptr, *ai = nullptr;
+      int rc = dalloc(&a, cb);
+      if (!rc) rc = dalloc(&ai, cb);
+      if (rc) {
+        dfree(a);
+        return rc;
+      }
+      launch_clover_convert(prec, hv, k->A64[p], a, stream);
+      launch_clover_convert(prec, hv, k->Ai64[p], ai, stream);
+      A2A_HIP(this, hipGetLastError());
+      k->Alo[prec][p] = a;
+      k->Ailo[prec][p] = ai;
+    }
+  }
+  k->last_use = ++use_clock;
+  *out = k;
+  return A2A_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Solver
+// ------------------------------------------------------------------------------------------
+Solver::~Solver() {
+  ctx->dfree(d_ops);
+  ctx->dfree(d_slots);
+  ctx->dfree(d_groups);
+  ctx->dfree(d_hop_tiles);
+  ctx->dfree(d_vec_tiles);
+  ctx->dfree(d_sub_groups);
+  ctx->dfree(d_sub_tiles);
+  for (auto& o : ops)
+    if (o.kop) o.kop->refs--;
+}
+
+static int grow(Ctx* c, void** p, size_t* cap, size_t need) {
+  if (need <= *cap && *p) return A2A_OK;
+  size_t n = std::max(need, (size_t)2 * *cap);
+  n = std::max(n, (size_t)4096);
+  c->dfree(*p);
+  *p = nullptr;
+  *cap = 0;
+  A2A_TRY(c->dalloc(p, n));
+  *cap = n;
+  return A2A_OK;
+}
+
+int Solver::op_index(int clover_h, double kappa, KappaOp* kop, const GaugeField* gf) {
+  for (int i = 0; i < (int)ops.size(); ++i)
+    if (ops[i].clover_h == clover_h && ops[i].kappa == kappa) return i;
+  OpEntry e{};
+  e.clover_h = clover_h;
+  e.kappa = kappa;
+  e.kop = kop;
+  kop->refs++;
+  e.dev.g = gf->g;
+  e.dev.kappa = kappa;
+  for (int p = 0; p < 2; ++p) {
+    e.dev.U[0][p] = gf->U[prec][p];
+    e.dev.U[1][p] = gf->U[0][p];
+    e.dev.A[1][p] = kop->A64[p];
+    e.dev.Ai[1][p] = kop->Ai64[p];
+    e.dev.A[0][p] = prec == 0 ? kop->A64[p] : kop->Alo[prec][p];
+    e.dev.Ai[0][p] = prec == 0 ? kop->Ai64[p] : kop->Ailo[prec][p];
+  }
+  e.nblk = (gf->g.hv + BS - 1) / BS;
+  ops.push_back(e);
+  dirty = true;
+  return (int)ops.size() - 1;
+}
+
+int Solver::add_slot(Slot* s) {
+  live.push_back(s);
+  dirty = true;
+  return A2A_OK;
+}
+
+static int upload(Ctx* c, void* dst, const void* src, size_t n) {
+  if (!n) return A2A_OK;
+  A2A_HIP(c, hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, c->stream));
+  return c->sync();
+}
+
+int Solver::rebuild() {
+  if (!dirty) return A2A_OK;
+  // ops and slots
+  A2A_TRY(grow(ctx, (void**)&d_ops, &cap_ops, sizeof(OpDev) * std::max<size_t>(1, ops.size())));
+  std::vector<OpDev> hops(ops.size());
+  for (size_t i = 0; i < ops.size(); ++i) hops[i] = ops[i].dev;
+  A2A_TRY(upload(ctx, d_ops, hops.data(), sizeof(OpDev) * hops.size()));
+  const size_t n = live.size();
+  A2A_TRY(grow(ctx, (void**)&d_slots, &cap_slots, sizeof(SlotDev) * std::max<size_t>(1, n)));
+  std::vector<SlotDev> hs(n);
+  for (size_t i = 0; i < n; ++i) {
+    Slot* s = live[i];
+    SlotDev& d = hs[i];
+    d.op = s->op;
+    d.nblk = ops[s->op].nblk;
+    d.sid = s->sid;
+    d.pad = 0;
+    d.arena[0] = s->lo;
+    d.arena[1] = s->hi;
+    d.vstride[0] = (long long)s->lo_stride;
+    d.vstride[1] = (long long)s->hi_stride;
+    d.scal = ctx->scal_pool + (size_t)s->sid * NSCAL;
+    d.src = s->src;
+    d.sol = s->sol;
+    d.x0 = s->x0;
+  }
+  A2A_TRY(upload(ctx, d_slots, hs.data(), sizeof(SlotDev) * n));
+  // groups of R slots sharing an operator, and tile lists
+  std::vector<int> groups;
+  std::vector<int2> htiles, vtiles;
+  for (int o = 0; o < (int)ops.size(); ++o) {
+    std::vector<int> mine;
+    for (size_t i = 0; i < n; ++i)
+      if (live[i]->op == o) mine.push_back((int)i);
+    if (mine.empty()) continue;
+    const int g0 = (int)(groups.size() / R);
+    const int ng = (int)((mine.size() + R - 1) / R);
+    for (int gi = 0; gi < ng; ++gi)
+      for (int r = 0; r < R; ++r) {
+        size_t k = (size_t)gi * R + r;
+        groups.push_back(k < mine.size() ? mine[k] : -1);
+      }
+    for (int b = 0; b < ops[o].nblk; ++b)
+      for (int gi = 0; gi < ng; ++gi) htiles.push_back(make_int2(g0 + gi, b));
+    for (int b = 0; b < ops[o].nblk; ++b)
+      for (int i : mine) vtiles.push_back(make_int2(i, b));
+  }
+  xcd_order(htiles, ctx->xcd_order);
+  xcd_order(vtiles, ctx->xcd_order);
+  A2A_TRY(grow(ctx, (void**)&d_groups, &cap_groups, sizeof(int) * std::max<size_t>(1, groups.size())));
+  A2A_TRY(grow(ctx, (void**)&d_hop_tiles, &cap_hop, sizeof(int2) * std::max<size_t>(1, htiles.size())));
+  A2A_TRY(grow(ctx, (void**)&d_vec_tiles, &cap_vec, sizeof(int2) * std::max<size_t>(1, vtiles.size())));
+  A2A_TRY(upload(ctx, d_groups, groups.data(), sizeof(int) * groups.size()));
+  A2A_TRY(upload(ctx, d_hop_tiles, htiles.data(), sizeof(int2) * htiles.size()));
+  A2A_TRY(upload(ctx, d_vec_tiles, vtiles.data(), sizeof(int2) * vtiles.size()));
+  n_hop_tiles = (int)htiles.size();
+  n_vec_tiles = (int)vtiles.size();
+  dirty = false;
+  return A2A_OK;
+}
+
+// groups of one slot each (R_sub = 1) or R for a subset of live slots
+int Solver::upload_subset(const std::vector<int>& idx, int R_sub) {
+  std::vector<int> groups;
+  std::vector<int2> htiles, vtiles;
+  for (int o = 0; o < (int)ops.size(); ++o) {
+    std::vector<int> mine;
+    for (int i : idx)
+      if (live[i]->op == o) mine.push_back(i);
+    if (mine.empty()) continue;
+    const int g0 = (int)(groups.size() / R_sub);
+    const int ng = (int)((mine.size() + R_sub - 1) / R_sub);
+    for (int gi = 0; gi < ng; ++gi)
+      for (int r = 0; r < R_sub; ++r) {
+        size_t k = (size_t)gi * R_sub + r;
+        groups.push_back(k < mine.size() ? mine[k] : -1);
+      }
+    for (int b = 0; b < ops[o].nblk; ++b) {
+      for (int gi = 0; gi < ng; ++gi) htiles.push_back(make_int2(g0 + gi, b));
+      for (int i : mine) vtiles.push_back(make_int2(i, b));
+    }
+  }
+  xcd_order(htiles, ctx->xcd_order);
+  xcd_order(vtiles, ctx->xcd_order);
+  // one buffer holds [hop tiles | vec tiles]
+  A2A_TRY(grow(ctx, (void**)&d_sub_groups, &cap_subg, sizeof(int) * std::max<size_t>(1, groups.size())));
+  A2A_TRY(grow(ctx, (void**)&d_sub_tiles, &cap_subt, sizeof(int2) * std::max<size_t>(1, htiles.size() + vtiles.size())));
+  std::vector<int2> all(htiles);
+  all.insert(all.end(), vtiles.begin(), vtiles.end());
+  A2A_TRY(upload(ctx, d_sub_groups, groups.data(), sizeof(int) * groups.size()));
+  A2A_TRY(upload(ctx, d_sub_tiles, all.data(), sizeof(int2) * all.size()));
+  sub_nh = (int)htiles.size();
+  sub_nv = (int)vtiles.size();
+  return A2A_OK;
+}
+
+int Solver::hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par, int vin, int vout, int vaux1,
+                int vaux2, int vrhat, double ca, double cb, double gsign, int gpow, int inv, int red,
+                const char* cls) {
+  HopArgs a{};
+  a.ops = d_ops;
+  a.slots = d_slots;
+  a.groups = sub ? d_sub_groups : d_groups;
+  a.tiles = sub ? d_sub_tiles : d_hop_tiles;
+  a.out_par = out_par;
+  a.psel = psel;
+  a.vin = vin;
+  a.vout = vout;
+  a.vaux1 = vaux1;
+  a.vaux2 = vaux2;
+  a.vrhat = vrhat;
+  a.ca = ca;
+  a.cb = cb;
+  a.gsign = gsign;
+  a.gpow = gpow;
+  a.inv = inv;
+  a.red = red;
+  a.rb = ctx->redbuf();
+  const int c = (cls && cls[0] == '1') ? 0 : 1;
+  hipEvent_t ev = nullptr;
+  if (cls) A2A_TRY(ctx->timing_begin(c, &ev));
+  launch_hop(kprec, Rk, a, n_tiles, ctx->stream);
+  A2A_HIP(ctx, hipGetLastError());
+  if (cls && ctx->timing) {
+    // compulsory bytes: links and clover once per site, every spinor stream once per RHS
+    const double sz = kprec == 0 ? 8.0 : kprec == 1 ? 4.0 : 2.0;
+    const bool epi = inv || (vaux2 >= 0 && cb != 0.0);
+    const int nvec = 2 + (vaux1 >= 0) + (vaux2 >= 0) + (red == RED_ALPHA && vrhat >= 0);
+    double bytes = 0;
+    for (int o = 0; o < (int)ops.size(); ++o) {
+      int n = 0;
+      for (Slot* s : live) n += (s->op == o);
+      if (!n) continue;
+      bytes += (double)ops[o].dev.g.hv * (8 * 18 * sz + (epi ? 72 * sz : 0.0) + (double)n * nvec * 24 * sz);
+    }
+    A2A_TRY(ctx->timing_end(c, ev, bytes));
+  } else if (cls) {
+    A2A_TRY(ctx->timing_end(c, ev, 0.0));
+  }
+  return A2A_OK;
+}
+
+int Solver::vec(bool sub, int n_tiles, int kind, int par, int use_inv, int vin, int vout) {
+  VecArgs a{};
+  a.ops = d_ops;
+  a.slots = d_slots;
+  a.tiles = sub ? d_sub_tiles + sub_nh : d_vec_tiles;
+  a.kind = kind;
+  a.par = par;
+  a.use_inv = use_inv;
+  a.vin = vin;
+  a.vout = vout;
+  a.rb = ctx->redbuf();
+  const bool timed = !sub && (kind == VK_BICG_S || kind == VK_BICG_XR || kind == VK_BICG_P);
+  hipEvent_t ev = nullptr;
+  if (timed) A2A_TRY(ctx->timing_begin(2, &ev));
+  launch_vec(prec, a, n_tiles, ctx->stream);
+  A2A_HIP(ctx, hipGetLastError());
+  if (timed) {
+    const double sz = prec == 0 ? 8.0 : prec == 1 ? 4.0 : 2.0;
+    const int nvec = kind == VK_BICG_S ? 3 : kind == VK_BICG_XR ? 7 : 4;
+    double bytes = 0;
+    for (Slot* s : live) bytes += (double)ops[s->op].dev.g.hv * nvec * 24 * sz;
+    A2A_TRY(ctx->timing_end(2, ev, bytes));
+  }
+  return A2A_OK;
+}
+
+int Solver::layout_in(bool sub, int n_tiles, int which_in, int psel, int kprec, int ve, int vo, int g5, int red) {
+  LayoutArgs a{};
+  a.ops = d_ops;
+  a.slots = d_slots;
+  a.tiles = sub ? d_sub_tiles + sub_nh : d_vec_tiles;
+  a.which_in = which_in;
+  a.psel = psel;
+  a.v_even = ve;
+  a.v_odd = vo;
+  a.gamma5 = g5;
+  a.red = red;
+  a.rb = ctx->redbuf();
+  launch_layout_in(kprec, a, n_tiles, ctx->stream);
+  A2A_HIP(ctx, hipGetLastError());
+  return A2A_OK;
+}
+
+int Solver::layout_out(bool sub, int n_tiles, int psel, int kprec, int ve, int vo, int g5) {
+  LayoutArgs a{};
+  a.ops = d_ops;
+  a.slots = d_slots;
+  a.tiles = sub ? d_sub_tiles + sub_nh : d_vec_tiles;
+  a.psel = psel;
+  a.v_even = ve;
+  a.v_odd = vo;
+  a.gamma5 = g5;
+  a.red = RED_NONE;
+  a.rb = ctx->redbuf();
+  launch_layout_out(kprec, a, n_tiles, ctx->stream);
+  A2A_HIP(ctx, hipGetLastError());
+  return A2A_OK;
+}
+
+// One BiCGStab step for every live slot, up to and including the x / r update.
+int Solver::iteration() {
+  const int H = n_hop_tiles, Vn = n_vec_tiles;
+  // v = M p
+  A2A_TRY(hop(false, H, R, 0, prec, 0, VL_P, VL_TE, -1, -1, -1, 0, 0, 1.0, 0, 1, RED_NONE, "1"));
+  A2A_TRY(hop(false, H, R, 0, prec, 1, VL_TE, VL_V, -1, VL_P, VL_RHAT, 0, 1.0, -1.0, 2, 0, RED_ALPHA, "2"));
+  A2A_TRY(vec(false, Vn, VK_BICG_S));
+  // t = M s
+  A2A_TRY(hop(false, H, R, 0, prec, 0, VL_S, VL_TE, -1, -1, -1, 0, 0, 1.0, 0, 1, RED_NONE, "1"));
+  A2A_TRY(hop(false, H, R, 0, prec, 1, VL_TE, VL_T, -1, VL_S, -1, 0, 1.0, -1.0, 2, 0, RED_OMEGA, "2"));
+  A2A_TRY(vec(false, Vn, VK_BICG_XR));
+  for (Slot* s : live) s->iters++;
+  return A2A_OK;
+}
+
+// FP64: x64 is current; r64 = b - M x64 and |r64|^2 for a subset (uploaded by the caller).
+int Solver::true_residual(const std::vector<int>& idx) {
+  (void)idx;
+  A2A_TRY(hop(true, sub_nh, 1, 1, 0, 0, VH_X, VH_TE, -1, -1, -1, 0, 0, 1.0, 0, 1, RED_NONE, nullptr));
+  A2A_TRY(hop(true, sub_nh, 1, 1, 0, 1, VH_TE, VH_R, VH_BHAT, VH_X, -1, 1.0, -1.0, 1.0, 2, 0, RED_R64, nullptr));
+  return A2A_OK;
+}
+
+// Prepare new slots: eta -> even-odd FP64, b = eta_o + kappa H_oe A_ee^{-1} eta_e, x64 = x0 or 0,
+// r64 = b - M x64, inner state.  Marks zero / non-finite sources.
+int Solver::setup(const std::vector<int>& idx) {
+  if (idx.empty()) return A2A_OK;
+  A2A_TRY(rebuild());
+  std::vector<int> with_x0;
+  for (int i : idx)
+    if (live[i]->x0) with_x0.push_back(i);
+  A2A_TRY(upload_subset(idx, 1));
+  int nh = sub_nh, nv = sub_nv;
+  A2A_TRY(layout_in(true, nv, 0, 1, 0, VH_ETA_E, VH_ETA_O, 0, RED_ETA));
+  A2A_TRY(vec(true, nv, VK_CLOVER, 0, 1, VH_ETA_E, VH_TE));
+  A2A_TRY(hop(true, nh, 1, 1, 0, 1, VH_TE, VH_BHAT, VH_ETA_O, -1, -1, 1.0, 0, 1.0, 1, 0, RED_NONE, nullptr));
+  A2A_TRY(vec(true, nv, VK_ZERO_HI, 0, 0, -1, VH_X));
+  if (!with_x0.empty()) {
+    A2A_TRY(upload_subset(with_x0, 1));
+    A2A_TRY(layout_in(true, sub_nv, 1, 1, 0, VH_TE, VH_X, 0, RED_NONE));
+    A2A_TRY(upload_subset(idx, 1));
+  }
+  A2A_TRY(true_residual(idx));
+  A2A_TRY(vec(true, nv, VK_INIT));
+  A2A_TRY(ctx->read_scal());
+  for (int i : idx) {
+    Slot* s = live[i];
+    const double* sc = ctx->scal_host + (size_t)s->sid * NSCAL;
+    const double e2 = sc[SC_ETAN2], r2 = sc[SC_R64N2];
+    if (!std::isfinite(e2) || !std::isfinite(r2)) {
+      s->state = SS_FAIL;
+      s->err = A2A_ENAN;
+      continue;
+    }
+    s->eta_norm = std::sqrt(e2);
+    s->target = 0.5 * s->tol * s->eta_norm;
+    s->last_r64 = std::sqrt(r2);
+    s->state = SS_RUN;
+  }
+  return A2A_OK;
+}
+
+// Reconstruct x_e, compute the FP64 residual of the full system, write the canonical
+// solution.  Fills info; returns through slot state.
+int Solver::finalize(const std::vector<int>& idx) {
+  if (idx.empty()) return A2A_OK;
+  A2A_TRY(upload_subset(idx, 1));
+  const int nh = sub_nh, nv = sub_nv;
+  // x_e = A_ee^{-1} (eta_e + kappa H_eo x_o)  -> VH_TE
+  A2A_TRY(hop(true, nh, 1, 1, 0, 0, VH_X, VH_TE, VH_ETA_E, -1, -1, 1.0, 0, 1.0, 1, 1, RED_NONE, nullptr));
+  // r_e = eta_e - A_ee x_e + kappa H_eo x_o
+  A2A_TRY(hop(true, nh, 1, 1, 0, 0, VH_X, VH_R, VH_ETA_E, VH_TE, -1, 1.0, -1.0, 1.0, 1, 0, RED_RES_E, nullptr));
+  // r_o = eta_o - A_oo x_o + kappa H_oe x_e
+  A2A_TRY(hop(true, nh, 1, 1, 0, 1, VH_TE, VH_R, VH_ETA_O, VH_X, -1, 1.0, -1.0, 1.0, 1, 0, RED_RES_O, nullptr));
+  A2A_TRY(layout_out(true, nv, 1, 0, VH_TE, VH_X, 0));
+  A2A_TRY(ctx->read_scal());
+  const double t = now_seconds();
+  for (int i : idx) {
+    Slot* s = live[i];
+    const double* sc = ctx->scal_host + (size_t)s->sid * NSCAL;
+    const double res = std::sqrt(sc[SC_RES_E] + sc[SC_RES_O]);
+    s->info.true_rel_residual = s->eta_norm > 0 ? res / s->eta_norm : 0.0;
+    s->info.iters = s->iters;
+    s->info.reliable_updates = s->rus;
+    s->info.restarts = s->restarts;
+    s->info.converged = (s->info.true_rel_residual <= s->tol) ? 1 : 0;
+    s->info.seconds = t - s->t_submit;
+  }
+  return A2A_OK;
+}
+
+// Residual checks, reliable updates, restarts, convergence and retirement.
+int Solver::check() {
+  A2A_TRY(ctx->read_scal());
+  std::vector<int> ru, restart;
+  const double delta = prec == 0 ? ctx->delta_64 : ctx->delta_lo;
+  for (int i = 0; i < (int)live.size(); ++i) {
+    Slot* s = live[i];
+    if (s->state != SS_RUN) continue;
+    const double* sc = ctx->scal_host + (size_t)s->sid * NSCAL;
+    const double est = std::sqrt(sc[SC_RNORM2]) * sc[SC_SIGMA];
+    if (sc[SC_FLAGS] != 0.0 || !std::isfinite(est)) {
+      restart.push_back(i);
+    } else if (est <= s->target || est <= delta * s->last_r64 || s->iters >= s->max_iter) {
+      ru.push_back(i);
+    }
+  }
+  if (ru.empty() && restart.empty()) return A2A_OK;
+  std::vector<int> all(ru);
+  all.insert(all.end(), restart.begin(), restart.end());
+  A2A_TRY(upload_subset(all, 1));
+  A2A_TRY(vec(true, sub_nv, VK_RU_ACCUM));
+  A2A_TRY(true_residual(all));
+  A2A_TRY(ctx->read_scal());
+  std::vector<int> done, rescale, reinit;
+  for (int i : all) {
+    Slot* s = live[i];
+    s->rus++;
+    const double* sc = ctx->scal_host + (size_t)s->sid * NSCAL;
+    const double r = std::sqrt(sc[SC_R64N2]);
+    const bool was_restart = std::find(restart.begin(), restart.end(), i) != restart.end();
+    if (!std::isfinite(r)) {
+      s->state = SS_FAIL;
+      s->err = A2A_EBREAKDOWN;
+      done.push_back(i);
+      continue;
+    }
+    if (r <= s->target || s->iters >= s->max_iter) {
+      done.push_back(i);
+      s->last_r64 = r;
+      continue;
+    }
+    if (was_restart || r > 0.9 * s->last_r64) {
+      s->stagn++;
+      s->restarts++;
+      if (s->restarts > 50) {
+        s->state = SS_FAIL;
+        s->err = A2A_EBREAKDOWN;
+        done.push_back(i);
+        continue;
+      }
+      reinit.push_back(i);
+    } else {
+      rescale.push_back(i);
+    }
+    s->last_r64 = r;
+  }
+  if (!rescale.empty()) {
+    A2A_TRY(upload_subset(rescale, 1));
+    A2A_TRY(vec(true, sub_nv, VK_RU_RESCALE));
+  }
+  if (!reinit.empty()) {
+    A2A_TRY(upload_subset(reinit, 1));
+    A2A_TRY(vec(true, sub_nv, VK_INIT));
+  }
+  if (!done.empty()) {
+    A2A_TRY(finalize(done));
+    std::vector<int> again;
+    for (int i : done) {
+      Slot* s = live[i];
+      if (s->state == SS_FAIL) continue;
+      if (s->info.converged) {
+        s->state = SS_DONE;
+      } else if (s->iters >= s->max_iter) {
+        s->state = SS_FAIL;
+        s->err = A2A_ENOTCONV;
+      } else {  // reconstruction rounding: tighten and continue from the current x
+        s->target *= 0.1;
+        again.push_back(i);
+      }
+    }
+    if (!again.empty()) {
+      A2A_TRY(upload_subset(again, 1));
+      A2A_TRY(vec(true, sub_nv, VK_INIT));
+    }
+  }
+  return A2A_OK;
+}
+
+// Drop finished slots from the device tables.
+int Solver::retire() {
+  size_t before = live.size();
+  live.erase(std::remove_if(live.begin(), live.end(),
+                            [](Slot* s) { return s->state == SS_DONE || s->state == SS_FAIL; }),
+             live.end());
+  if (live.size() != before) dirty = true;
+  return A2A_OK;
+}
+
+// Iterate every live slot until all are done (or fail).
+int Solver::run_until_done(int max_outer_iters) {
+  int k = 0;
+  A2A_TRY(retire());
+  while (!live.empty()) {
+    A2A_TRY(rebuild());
+    A2A_TRY(iteration());
+    ++k;
+    if (k % ctx->check_every == 0 || k >= max_outer_iters) {
+      A2A_TRY(check());
+      A2A_TRY(retire());
+      A2A_TRY(rebuild());
+      if (live.empty()) break;
+    }
+    A2A_TRY(vec(false, n_vec_tiles, VK_BICG_P));
+    if (k >= max_outer_iters) break;
+  }
+  return A2A_OK;
+}
+
+}  // namespace a2a

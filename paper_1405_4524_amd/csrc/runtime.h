@@ -1,0 +1,226 @@
+// runtime.h -- host runtime of liba2a: context, resident fields, batched solver, engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/a2a.h"
+#include "a2a_kernels.h"
+
+namespace a2a {
+
+struct Ctx;
+
+// status carrying the ABI error code and a message
+struct Err {
+  int code = A2A_OK;
+};
+
+#define A2A_HIP(ctx, call)                                                                  \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return (ctx)->fail(A2A_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define A2A_TRY(expr)        \
+  do {                       \
+    int rc_ = (expr);        \
+    if (rc_ != A2A_OK) return rc_; \
+  } while (0)
+
+// ---- resident fields --------------------------------------------------------------------
+struct GaugeField {
+  int handle = 0;
+  a2a_geom geom{};
+  Geo g{};
+  double* canon = nullptr;        // canonical FP64 links on the device
+  void* U[4][2] = {};              // [precision][parity], built on first use
+};
+
+struct KappaOp {
+  double kappa = 0;
+  double* A64[2] = {};
+  double* Ai64[2] = {};
+  void* Alo[4][2] = {};
+  void* Ailo[4][2] = {};
+  int refs = 0;
+  unsigned long long last_use = 0;
+};
+
+struct CloverField {
+  int handle = 0;
+  int gauge = 0;
+  double csw = 0;
+  double* G[2] = {};
+  std::vector<std::unique_ptr<KappaOp>> kops;
+};
+
+// ---- batched solver -----------------------------------------------------------------------
+struct OpEntry {
+  int clover_h;
+  double kappa;
+  KappaOp* kop;
+  OpDev dev;
+  int nblk;
+};
+
+enum SlotState { SS_NEW = 0, SS_RUN, SS_DONE, SS_FAIL };
+
+struct Slot {
+  int sid = -1;
+  int op = -1;  // index into Solver::ops
+  const double* src = nullptr;
+  double* sol = nullptr;
+  const double* x0 = nullptr;
+  char* lo = nullptr;
+  char* hi = nullptr;
+  size_t lo_stride = 0, hi_stride = 0;
+  double tol = 1e-10, target = 0, eta_norm = 0, last_r64 = INFINITY;
+  int max_iter = 10000;
+  int iters = 0, rus = 0, restarts = 0, stagn = 0;
+  int state = SS_NEW;
+  int err = A2A_OK;
+  double t_submit = 0, t_done = 0;
+  a2a_solve_info info{};
+  long long req = -1;
+  int req_idx = 0;
+};
+
+struct Solver {
+  Ctx* ctx;
+  int prec;
+  int R;  // RHS per thread in the stencil
+  std::vector<OpEntry> ops;
+  std::vector<Slot*> live;  // slots in the device tables (running)
+  // device tables
+  OpDev* d_ops = nullptr;
+  SlotDev* d_slots = nullptr;
+  int* d_groups = nullptr;
+  int2* d_hop_tiles = nullptr;
+  int2* d_vec_tiles = nullptr;
+  int* d_sub_groups = nullptr;
+  int2* d_sub_tiles = nullptr;
+  size_t cap_ops = 0, cap_slots = 0, cap_groups = 0, cap_hop = 0, cap_vec = 0, cap_subg = 0, cap_subt = 0;
+  int n_hop_tiles = 0, n_vec_tiles = 0;
+  int sub_nh = 0, sub_nv = 0;  // tile counts of the last uploaded subset
+  bool dirty = true;
+  bool with_hi = true;
+
+  Solver(Ctx* c, int p, int r) : ctx(c), prec(p), R(r) {}
+  ~Solver();
+  int op_index(int clover_h, double kappa, KappaOp* kop, const GaugeField* gf);
+  int add_slot(Slot* s);
+  int rebuild();
+  // subset helpers (indices into live)
+  int upload_subset(const std::vector<int>& idx, int R_sub);
+  // kernel sequences
+  int hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par, int vin, int vout, int vaux1, int vaux2,
+          int vrhat, double ca, double cb, double gsign, int gpow, int inv, int red, const char* cls);
+  int vec(bool sub, int n_tiles, int kind, int par = 0, int use_inv = 0, int vin = -1, int vout = -1);
+  int layout_in(bool sub, int n_tiles, int which_in, int psel, int kprec, int ve, int vo, int g5, int red);
+  int layout_out(bool sub, int n_tiles, int psel, int kprec, int ve, int vo, int g5);
+  int iteration();
+  int setup(const std::vector<int>& idx);
+  int check();
+  int true_residual(const std::vector<int>& idx);
+  int finalize(const std::vector<int>& idx);
+  int run_until_done(int max_outer_iters);
+  int retire();
+};
+
+// ---- context ------------------------------------------------------------------------------
+struct EventRec {
+  int cls;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0, used = 0;
+  std::unordered_map<void*, size_t> sizes;
+  std::string err;
+  int next_handle = 1;
+  std::map<int, std::unique_ptr<GaugeField>> gauges;
+  std::map<int, std::unique_ptr<CloverField>> clovers;
+  unsigned long long use_clock = 0;
+  // options
+  int rhs_block = 4;
+  int check_every = 4;
+  double delta_lo = 0.1, delta_64 = 1e-3;
+  int xcd_order = 1;
+  int timing = 0;
+  // reduction scratch
+  double* scal_pool = nullptr;
+  double* scal_host = nullptr;
+  unsigned* counters = nullptr;
+  double* partials = nullptr;
+  int partial_slots = 0, partial_blk = 0;
+  std::vector<int> sid_free;
+  int sid_cap = 0;
+  int sid_max = -1;
+  std::vector<char> sid_used;
+  // kernel timing
+  std::vector<EventRec> pending;
+  std::vector<hipEvent_t> ev_pool;
+  long long t_launches[3] = {0, 0, 0};
+  double t_ms[3] = {0, 0, 0};
+  double t_bytes[3] = {0, 0, 0};  // algorithmic bytes of the timed launches
+
+  int fail(int code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+  int dalloc(void** p, size_t n);
+  void dfree(void* p);
+  int alloc_sid(int nblk, int* sid);
+  void free_sid(int sid);
+  int ensure_partials(int nslots, int nblk);
+  RedBuf redbuf() const {
+    RedBuf r;
+    r.partials = partials;
+    r.counters = counters;
+    r.maxblk = partial_blk;
+    return r;
+  }
+  int sync() {
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(A2A_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    return A2A_OK;
+  }
+  int read_scal() {  // whole used range of the scalar pool into host memory
+    if (sid_max < 0) return A2A_OK;
+    A2A_HIP(this, hipMemcpyAsync(scal_host, scal_pool, sizeof(double) * NSCAL * (sid_max + 1),
+                                 hipMemcpyDeviceToHost, stream));
+    return sync();
+  }
+  // resident fields
+  GaugeField* gauge(int h) {
+    auto it = gauges.find(h);
+    return it == gauges.end() ? nullptr : it->second.get();
+  }
+  CloverField* clover(int h) {
+    auto it = clovers.find(h);
+    return it == clovers.end() ? nullptr : it->second.get();
+  }
+  int gauge_links(GaugeField* gf, int prec, void** out0, void** out1);
+  int kappa_op(CloverField* cf, double kappa, int prec, KappaOp** out);
+  int timing_begin(int cls, hipEvent_t* a);
+  int timing_end(int cls, hipEvent_t a, double alg_bytes);
+  int timing_collect();
+};
+
+double now_seconds();
+int geom_to_geo(const a2a_geom* geom, Geo* g);
+void xcd_order(std::vector<int2>& tiles, bool enable);
+
+}  // namespace a2a

@@ -1,0 +1,146 @@
+"""GPU tests of batching and of the continuous-batching engine: results of each source are the
+same alone, in a batch and in a mixed-lattice / mixed-kappa / mixed-precision stream, within
+the solve tolerance (every one is also checked against the oracle's D)."""
+import numpy as np
+import pytest
+
+from paper_1405_4524_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1405_4524_amd import a2a
+
+    c = a2a.Context(0)
+    yield c
+    c.finalize()
+
+
+LATS = [((4, 4, 4, 8), 0.35, 11), ((6, 4, 4, 10), 0.35, 12)]
+
+
+@pytest.fixture(scope="module")
+def fields(ctx, orc):
+    out = []
+    for dims, eps, seed in LATS:
+        U = inputs.gauge_field(dims, eps, seed)
+        g = ctx.load_gauge(U, -1)
+        c = ctx.load_clover(g, 1.5)
+        out.append(dict(dims=dims, U=U, g=g, c=c))
+    return out
+
+
+def test_batch_equals_alone(ctx, orc, fields):
+    f = fields[0]
+    print("[gpu] batch vs alone", flush=True)
+    eta = inputs.z2_noise(f["dims"], 6, seed=21)
+    Xb, infb, rc = ctx.solve_propagators(f["c"], eta, 0.125, 1.5, tol=1e-10, prec=2)
+    assert rc == 0
+    for i in (0, 3, 5):
+        Xa, infa, rc = ctx.solve_propagators(f["c"], eta[i:i + 1], 0.125, 1.5, tol=1e-10, prec=2)
+        assert rc == 0
+        assert rel(Xa[0], Xb[i]) < 1e-8
+    A = orc.clover(f["U"], 0.125, 1.5)
+    for i in range(6):
+        r = eta[i] - orc.apply_D(f["U"], A, 0.125, Xb[i], -1)
+        assert np.linalg.norm(r) / np.linalg.norm(eta[i]) <= 1e-10
+
+
+def test_engine_mixed_stream_matches_alone(ctx, orc, fields):
+    import torch
+
+    print("[gpu] engine mixed stream", flush=True)
+    eng = ctx.engine_create('{"max_slots": 24, "check_every": 4}')
+    reqs = []
+    rng = np.random.default_rng(5)
+    for k in range(7):
+        f = fields[k % 2]
+        kappa = float(rng.uniform(0.120, 0.130))
+        nsrc = int(rng.integers(1, 6))
+        prec = [2, 1, 3, 0][k % 4]
+        eta = inputs.z2_noise(f["dims"], nsrc, seed=100 + k)
+        src = torch.from_numpy(eta).cuda()
+        sol = torch.zeros_like(src)
+        reqs.append(dict(f=f, kappa=kappa, nsrc=nsrc, prec=prec, eta=eta, src=src, sol=sol, ticket=None))
+    # staggered arrivals: two at first, then one more per step
+    pending = list(reqs)
+    for r in pending[:2]:
+        r["ticket"] = eng.submit(r["f"]["c"], r["kappa"], r["src"], r["nsrc"], 1e-10, r["prec"], 20000, r["sol"])
+    pending = pending[2:]
+    for step in range(2000):
+        if pending:
+            r = pending.pop(0)
+            r["ticket"] = eng.submit(r["f"]["c"], r["kappa"], r["src"], r["nsrc"], 1e-10, r["prec"], 20000, r["sol"])
+        eng.step(8)
+        if not pending and all(eng.poll(r["ticket"], r["nsrc"])[0] != 0 for r in reqs):
+            break
+    for r in reqs:
+        done, info, rc = eng.poll(r["ticket"], r["nsrc"])
+        assert done == 1 and rc == 0, (done, rc, info)
+        X = r["sol"].cpu().numpy()
+        A = orc.clover(r["f"]["U"], r["kappa"], 1.5)
+        for i in range(r["nsrc"]):
+            res = np.linalg.norm(r["eta"][i] - orc.apply_D(r["f"]["U"], A, r["kappa"], X[i], -1))
+            assert res / np.linalg.norm(r["eta"][i]) <= 1e-10
+            assert info[i]["converged"] == 1
+        Xa, _, rc = ctx.solve_propagators(r["f"]["c"], r["eta"], r["kappa"], 1.5, tol=1e-10, prec=r["prec"])
+        assert rel(X, Xa) < 1e-8
+    eng.destroy()
+
+
+def test_engine_admission_by_budget_and_cancel(orc, fields):
+    """A context whose HBM budget fits one request at a time still serves all of them, one
+    after another; a cancelled queued request is reported failed and never runs."""
+    import torch
+
+    from paper_1405_4524_amd import a2a
+
+    print("[gpu] engine budget admission", flush=True)
+    f = fields[0]
+    dims = f["dims"]
+    c2 = a2a.Context(0)
+    try:
+        g = c2.load_gauge(f["U"], -1)
+        cl = c2.load_clover(g, 1.5)
+        warm = inputs.z2_noise(dims, 1, seed=299)
+        c2.dslash_clover(cl, 0.124, warm, prec=a2a.F32)  # builds the FP32 fields of this kappa
+        hv = int(np.prod(dims)) // 2
+        r256 = lambda b: (b + 255) // 256 * 256
+        per_req = 12 * (8 * r256(hv * 24 * 4) + 7 * r256(hv * 24 * 8))
+        c2.set_option("hbm_budget", c2.mem_in_use() + int(1.6 * per_req) + (256 << 10))
+        eng = c2.engine_create('{"max_slots": 64}')
+        tickets = []
+        sols = []
+        etas = []
+        for k in range(3):
+            eta = inputs.z2_noise(dims, 12, seed=300 + k)
+            src = torch.from_numpy(eta).cuda()
+            sol = torch.zeros_like(src)
+            etas.append(eta)
+            sols.append((src, sol))
+            tickets.append(eng.submit(cl, 0.124, src, 12, 1e-10, 1, 20000, sol))
+        eng.cancel(tickets[2])
+        max_active = 0
+        for _ in range(3000):
+            act = eng.step(8)
+            max_active = max(max_active, act)
+            states = [eng.poll(t, 12)[0] for t in tickets[:2]]
+            if all(s != 0 for s in states):
+                break
+        assert [eng.poll(t, 12)[0] for t in tickets] == [1, 1, -1]
+        assert max_active == 12  # the budget admitted one request at a time
+        A = orc.clover(f["U"], 0.124, 1.5)
+        for k in range(2):
+            X = sols[k][1].cpu().numpy()
+            for i in range(12):
+                r = etas[k][i] - orc.apply_D(f["U"], A, 0.124, X[i], -1)
+                assert np.linalg.norm(r) / np.linalg.norm(etas[k][i]) <= 1e-10
+        eng.destroy()
+    finally:
+        c2.finalize()
