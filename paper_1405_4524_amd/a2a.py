@@ -85,6 +85,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1405_4524_amd.build` first")
+        # torch ships its own HIP runtime (soname libamdhip64.so.7); loading it first makes
+        # liba2a bind to that same runtime, so the process has one HIP runtime and torch's
+        # device memory and streams are usable by the library.
+        import torch  # noqa: F401
+
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIG.items():
             f = getattr(L, name)

@@ -209,6 +209,16 @@ def test_solve_errors(ctx, orc, tiny_ref):
     ctx.unload(g)
 
 
+def test_single_hip_runtime_and_native_library_loaded(ctx):
+    """The HIP library is what runs (no fallback), and torch and liba2a share one HIP runtime."""
+    from paper_1405_4524_amd import a2a
+
+    maps = open("/proc/self/maps").read()
+    hip = {l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l}
+    assert len(hip) == 1, hip
+    assert a2a.LIB_PATH in maps
+
+
 # ---------------------------------------------------------------------------------------
 # contractions and noise
 # ---------------------------------------------------------------------------------------
