@@ -68,6 +68,12 @@ struct LayoutArgs {
   RedBuf rb;
 };
 
+// Sum the block partials of `kind` for n slots (slot table indices from `list`, or 0..n-1
+// when list is null) in block order and apply the scalar update.  Must follow the reducing
+// launch on the same stream.
+void launch_finalize(int kind, const OpDev* ops, const SlotDev* slots, const int* list, int n, RedBuf rb,
+                     hipStream_t s);
+
 void launch_hop(int prec, int R, const HopArgs& a, int ntiles, hipStream_t s);
 void launch_vec(int prec, const VecArgs& a, int ntiles, hipStream_t s);
 void launch_layout_in(int prec, const LayoutArgs& a, int ntiles, hipStream_t s);

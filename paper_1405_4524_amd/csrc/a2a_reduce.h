@@ -1,12 +1,13 @@
 // a2a_reduce.h -- deterministic per-slot global reductions in FP64 and the BiCGStab scalar
 // updates that consume them.
 //
-// Every block of a reducing kernel works on one slot (right-hand side) and one block of
-// sites.  It reduces its per-thread FP64 values with a fixed shuffle tree, writes the block
-// partial to partials[slot][block], and counts itself in on the slot's counter.  The block
-// that arrives last sums the partials in block order (fixed, independent of scheduling),
-// applies the scalar update for that slot and re-arms the counter.  Results are therefore
-// bitwise reproducible run to run and independent of what else shares the launch.
+// A reducing kernel block works on one site block of one or more slots (right-hand sides).
+// It reduces its per-thread FP64 values with a fixed shuffle tree and stores the block
+// partial to partials[slot][block] with plain stores.  A separate finalize launch (one
+// block per slot, ordered after the kernel on the same stream, so no fences or atomics
+// are needed across the per-XCD L2 caches) sums the partials in block order and applies
+// the scalar update.  Results are bitwise reproducible and independent of what else
+// shares the launch.
 #pragma once
 
 #include "a2a_device.h"
@@ -27,18 +28,10 @@ enum RedKind {
   RED_NORM,    // v = |out|^2 into SC_TMP
 };
 
-HD int red_nv(int kind) {
-  switch (kind) {
-    case RED_NONE: return 0;
-    case RED_ALPHA: return 2;
-    case RED_OMEGA: case RED_RHO: case RED_INIT: case RED_RU: return 3;
-    default: return 1;
-  }
-}
+constexpr int RED_NV = 3;  // values stored per block partial
 
 struct RedBuf {
-  double* partials;    // [slot][maxblk][4]
-  unsigned* counters;  // [slot]
+  double* partials;  // [slot id][maxblk][RED_NV]
   int maxblk;
 };
 
@@ -48,24 +41,52 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// block-wide sum of NV values per thread for BS threads; result valid on thread 0
-template <int NV, int BS>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* NV * BS/64 */) {
+// Block-wide sums of N values per thread (BS threads).  On return thread k < N holds the
+// block total of value k in v[k] (other entries unspecified).
+template <int N, int BS>
+__device__ __forceinline__ void block_sum_n(double (&v)[N]) {
+  __shared__ double lds[N * (BS / 64)];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) lds[k * (BS / 64) + w] = v[k];
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < BS / 64; ++j) s += lds[threadIdx.x * (BS / 64) + j];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+      if (k == (int)threadIdx.x) v[k] = s;
+  }
+}
+
+// Block-wide sums of N values per thread; thread 0 receives all N totals in v.
+template <int N, int BS>
+__device__ __forceinline__ void block_sum_all(double (&v)[N]) {
+  __shared__ double lds[N * (BS / 64)];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
   __syncthreads();
   if (lane == 0)
 #pragma unroll
-    for (int k = 0; k < NV; ++k) lds[k * (BS / 64) + w] = v[k];
+    for (int k = 0; k < N; ++k) lds[k * (BS / 64) + w] = v[k];
   __syncthreads();
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double s = 0;
+    for (int k = 0; k < N; ++k) {
+      double s = 0.0;
       for (int j = 0; j < BS / 64; ++j) s += lds[k * (BS / 64) + j];
       v[k] = s;
     }
+}
+
+// store the block partial of value k (thread k) for slot `sid`, block `blk`
+__device__ __forceinline__ void store_partial(const RedBuf& rb, int sid, int blk, int k, double val) {
+  rb.partials[((size_t)sid * rb.maxblk + blk) * RED_NV + k] = val;
 }
 
 __device__ __forceinline__ void cdiv(double ar, double ai, double br, double bi, double& cr, double& ci) {
@@ -160,40 +181,6 @@ __device__ inline void finalize_slot(int kind, double* sc, const double* v, int 
     case RED_RES_O: sc[SC_RES_O] = v[0]; break;
     case RED_NORM: sc[SC_TMP] = v[0]; break;
     default: break;
-  }
-}
-
-// Block-level epilogue of a reducing kernel: v[] holds this thread's contribution for one
-// slot.  Must be called by every thread of the block (BS threads).
-template <int NV, int BS>
-__device__ inline void reduce_slot(double (&v)[NV], int kind, int slot /* stable id */, int blk, int nblk,
-                                   double* scal, int hv, const RedBuf& rb) {
-  __shared__ double lds[4 * (BS / 64)];
-  __shared__ int is_last;
-  block_sum<NV, BS>(v, lds);
-  if (threadIdx.x == 0) {
-    double* p = rb.partials + ((size_t)slot * rb.maxblk + blk) * 4;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) p[k] = v[k];
-    __threadfence();
-    unsigned prev = atomicAdd(rb.counters + slot, 1u);
-    is_last = (prev == (unsigned)(nblk - 1));
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  double acc[NV];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-  const volatile double* p = rb.partials + (size_t)slot * rb.maxblk * 4;
-  for (int b = threadIdx.x; b < nblk; b += BS)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] += p[(size_t)b * 4 + k];
-  block_sum<NV, BS>(acc, lds);
-  if (threadIdx.x == 0) {
-    finalize_slot(kind, scal, acc, hv);
-    rb.counters[slot] = 0u;
-    __threadfence();
   }
 }
 

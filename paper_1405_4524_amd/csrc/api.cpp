@@ -290,11 +290,6 @@ extern "C" int a2a_init(a2a_ctx** out, int device, size_t budget, void* stream) 
     return A2A_ENOMEM;
   }
   c->scal_pool = (double*)p;
-  if (c->dalloc(&p, sizeof(unsigned) * SID_CAP) || hipMemset(p, 0, sizeof(unsigned) * SID_CAP) != hipSuccess) {
-    delete h;
-    return A2A_ENOMEM;
-  }
-  c->counters = (unsigned*)p;
   if (hipHostMalloc((void**)&c->scal_host, sizeof(double) * NSCAL * SID_CAP, hipHostMallocDefault) != hipSuccess) {
     delete h;
     return A2A_ENOMEM;

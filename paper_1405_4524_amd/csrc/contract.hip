@@ -136,8 +136,7 @@ __global__ __launch_bounds__(256) void k_pion(int T, int n, const double* O, int
     si += x[0] * y[1] + x[1] * y[0];
   }
   double v[2] = {sr, si};
-  __shared__ double lds[2 * 4];
-  block_sum<2, 256>(v, lds);
+  block_sum_all<2, 256>(v);
   if (threadIdx.x == 0) {
     double norm = 1.0;
     if (mode == 0) norm = (double)T * n * (n - 1);
@@ -179,7 +178,7 @@ __device__ cx<double> loop2_block(const double* O, int N, int m, int g, int h, i
     si += p.im;
   }
   double v[2] = {sr, si};
-  block_sum<2, 256>(v, lds);
+  block_sum_all<2, 256>(v);
   __shared__ cx<double> res;
   if (threadIdx.x == 0) res = mk(v[0], v[1]);
   __syncthreads();
@@ -212,7 +211,7 @@ __device__ cx<double> loop4_block(const double* O, int N, int m, int ta, int tb,
     si += p.im;
   }
   double v[2] = {sr, si};
-  block_sum<2, 256>(v, lds);
+  block_sum_all<2, 256>(v);
   __shared__ cx<double> res;
   if (threadIdx.x == 0) res = mk(v[0], v[1]);
   __syncthreads();

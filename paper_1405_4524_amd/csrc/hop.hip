@@ -139,47 +139,47 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
       if (on[r]) store_spinor<S, A>((char*)base[r] + (size_t)a.vout * vs[r], hv, site, acc[r]);
   }
 
-  // ---- reductions over the values as stored
-  const int nv = red_nv(a.red);
-  if (!nv) return;
+  // ---- reductions over the values as stored: one block partial per slot of the group
+  if (a.red == RED_NONE) return;
+  double v[R * RED_NV];
+#pragma unroll
+  for (int k = 0; k < R * RED_NV; ++k) v[k] = 0.0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    if (grp[r] < 0) continue;  // uniform across the block
-    const SlotDev& sd = a.slots[grp[r]];
-    double v[3] = {0.0, 0.0, 0.0};
-    if (valid) {
-      Spinor<A> o;
-      load_spinor<S, A>(base[r] + (size_t)a.vout * vs[r], hv, site, o);
-      if (a.red == RED_ALPHA) {  // (rhat, o)
-        Spinor<A> rh;
-        load_spinor<S, A>(base[r] + (size_t)a.vrhat * vs[r], hv, site, rh);
+    if (!valid || !on[r]) continue;
+    Spinor<A> o;
+    load_spinor<S, A>(base[r] + (size_t)a.vout * vs[r], hv, site, o);
+    if (a.red == RED_ALPHA) {  // (rhat, o)
+      Spinor<A> rh;
+      load_spinor<S, A>(base[r] + (size_t)a.vrhat * vs[r], hv, site, rh);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          v[0] += (double)rh.v[k].re * o.v[k].re + (double)rh.v[k].im * o.v[k].im;
-          v[1] += (double)rh.v[k].re * o.v[k].im - (double)rh.v[k].im * o.v[k].re;
-        }
-      } else if (a.red == RED_OMEGA) {  // (o, aux2), |o|^2
-        Spinor<A> x2;
-        load_spinor<S, A>(base[r] + (size_t)a.vaux2 * vs[r], hv, site, x2);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          v[0] += (double)o.v[k].re * x2.v[k].re + (double)o.v[k].im * x2.v[k].im;
-          v[1] += (double)o.v[k].re * x2.v[k].im - (double)o.v[k].im * x2.v[k].re;
-          v[2] += (double)o.v[k].re * o.v[k].re + (double)o.v[k].im * o.v[k].im;
-        }
-      } else {  // |o|^2
-#pragma unroll
-        for (int k = 0; k < 12; ++k) v[0] += (double)o.v[k].re * o.v[k].re + (double)o.v[k].im * o.v[k].im;
+      for (int k = 0; k < 12; ++k) {
+        v[r * 3 + 0] += (double)rh.v[k].re * o.v[k].re + (double)rh.v[k].im * o.v[k].im;
+        v[r * 3 + 1] += (double)rh.v[k].re * o.v[k].im - (double)rh.v[k].im * o.v[k].re;
       }
+    } else if (a.red == RED_OMEGA) {  // (o, aux2), |o|^2
+      Spinor<A> x2;
+      load_spinor<S, A>(base[r] + (size_t)a.vaux2 * vs[r], hv, site, x2);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        v[r * 3 + 0] += (double)o.v[k].re * x2.v[k].re + (double)o.v[k].im * x2.v[k].im;
+        v[r * 3 + 1] += (double)o.v[k].re * x2.v[k].im - (double)o.v[k].im * x2.v[k].re;
+        v[r * 3 + 2] += (double)o.v[k].re * o.v[k].re + (double)o.v[k].im * o.v[k].im;
+      }
+    } else {  // |o|^2
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v[r * 3] += (double)o.v[k].re * o.v[k].re + (double)o.v[k].im * o.v[k].im;
     }
-    if (nv == 3) {
-      reduce_slot<3, BS>(v, a.red, sd.sid, tile.y, sd.nblk, sd.scal, hv, a.rb);
-    } else if (nv == 2) {
-      double w[2] = {v[0], v[1]};
-      reduce_slot<2, BS>(w, a.red, sd.sid, tile.y, sd.nblk, sd.scal, hv, a.rb);
-    } else {
-      double w[1] = {v[0]};
-      reduce_slot<1, BS>(w, a.red, sd.sid, tile.y, sd.nblk, sd.scal, hv, a.rb);
+  }
+  block_sum_n<R * RED_NV, BS>(v);
+  if ((int)threadIdx.x < R * RED_NV) {
+    const int r = threadIdx.x / RED_NV, k = threadIdx.x % RED_NV;
+    if (grp[r] >= 0) {
+      double val = 0.0;
+#pragma unroll
+      for (int q = 0; q < R * RED_NV; ++q)
+        if (q == (int)threadIdx.x) val = v[q];
+      store_partial(a.rb, a.slots[grp[r]].sid, tile.y, k, val);
     }
   }
 }

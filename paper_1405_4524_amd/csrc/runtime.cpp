@@ -305,6 +305,7 @@ Solver::~Solver() {
   ctx->dfree(d_vec_tiles);
   ctx->dfree(d_sub_groups);
   ctx->dfree(d_sub_tiles);
+  ctx->dfree(d_sub_list);
   for (auto& o : ops)
     if (o.kop) o.kop->refs--;
 }
@@ -446,10 +447,20 @@ int Solver::upload_subset(const std::vector<int>& idx, int R_sub) {
   A2A_TRY(grow(ctx, (void**)&d_sub_tiles, &cap_subt, sizeof(int2) * std::max<size_t>(1, htiles.size() + vtiles.size())));
   std::vector<int2> all(htiles);
   all.insert(all.end(), vtiles.begin(), vtiles.end());
+  A2A_TRY(grow(ctx, (void**)&d_sub_list, &cap_subl, sizeof(int) * std::max<size_t>(1, idx.size())));
   A2A_TRY(upload(ctx, d_sub_groups, groups.data(), sizeof(int) * groups.size()));
   A2A_TRY(upload(ctx, d_sub_tiles, all.data(), sizeof(int2) * all.size()));
+  A2A_TRY(upload(ctx, d_sub_list, idx.data(), sizeof(int) * idx.size()));
   sub_nh = (int)htiles.size();
   sub_nv = (int)vtiles.size();
+  sub_n = (int)idx.size();
+  return A2A_OK;
+}
+
+int Solver::finalize_red(bool sub, int kind) {
+  launch_finalize(kind, d_ops, d_slots, sub ? d_sub_list : nullptr, sub ? sub_n : (int)live.size(), ctx->redbuf(),
+                  ctx->stream);
+  A2A_HIP(ctx, hipGetLastError());
   return A2A_OK;
 }
 
@@ -496,6 +507,7 @@ int Solver::hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par,
   } else if (cls) {
     A2A_TRY(ctx->timing_end(c, ev, 0.0));
   }
+  if (red != RED_NONE) A2A_TRY(finalize_red(sub, red));
   return A2A_OK;
 }
 
@@ -522,6 +534,8 @@ int Solver::vec(bool sub, int n_tiles, int kind, int par, int use_inv, int vin, 
     for (Slot* s : live) bytes += (double)ops[s->op].dev.g.hv * nvec * 24 * sz;
     A2A_TRY(ctx->timing_end(2, ev, bytes));
   }
+  const int red = kind == VK_BICG_XR ? RED_RHO : kind == VK_RU_RESCALE ? RED_RU : kind == VK_INIT ? RED_INIT : RED_NONE;
+  if (red != RED_NONE) A2A_TRY(finalize_red(sub, red));
   return A2A_OK;
 }
 
@@ -539,6 +553,7 @@ int Solver::layout_in(bool sub, int n_tiles, int which_in, int psel, int kprec, 
   a.rb = ctx->redbuf();
   launch_layout_in(kprec, a, n_tiles, ctx->stream);
   A2A_HIP(ctx, hipGetLastError());
+  if (red != RED_NONE) A2A_TRY(finalize_red(sub, red));
   return A2A_OK;
 }
 

@@ -107,9 +107,11 @@ struct Solver {
   int2* d_vec_tiles = nullptr;
   int* d_sub_groups = nullptr;
   int2* d_sub_tiles = nullptr;
-  size_t cap_ops = 0, cap_slots = 0, cap_groups = 0, cap_hop = 0, cap_vec = 0, cap_subg = 0, cap_subt = 0;
+  int* d_sub_list = nullptr;
+  size_t cap_ops = 0, cap_slots = 0, cap_groups = 0, cap_hop = 0, cap_vec = 0, cap_subg = 0, cap_subt = 0,
+         cap_subl = 0;
   int n_hop_tiles = 0, n_vec_tiles = 0;
-  int sub_nh = 0, sub_nv = 0;  // tile counts of the last uploaded subset
+  int sub_nh = 0, sub_nv = 0, sub_n = 0;  // tile and slot counts of the last uploaded subset
   bool dirty = true;
   bool with_hi = true;
 
@@ -120,6 +122,7 @@ struct Solver {
   int rebuild();
   // subset helpers (indices into live)
   int upload_subset(const std::vector<int>& idx, int R_sub);
+  int finalize_red(bool sub, int kind);
   // kernel sequences
   int hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par, int vin, int vout, int vaux1, int vaux2,
           int vrhat, double ca, double cb, double gsign, int gpow, int inv, int red, const char* cls);
@@ -162,7 +165,6 @@ struct Ctx {
   // reduction scratch
   double* scal_pool = nullptr;
   double* scal_host = nullptr;
-  unsigned* counters = nullptr;
   double* partials = nullptr;
   int partial_slots = 0, partial_blk = 0;
   std::vector<int> sid_free;
@@ -188,7 +190,6 @@ struct Ctx {
   RedBuf redbuf() const {
     RedBuf r;
     r.partials = partials;
-    r.counters = counters;
     r.maxblk = partial_blk;
     return r;
   }

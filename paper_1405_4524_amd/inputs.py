@@ -115,7 +115,7 @@ def z2_noise(dims, nsrc, seed, src_offset=0, out=None):
     flat = out.reshape(nsrc, per)
     base = np.uint64(int(seed) << 48)
     idx = np.arange(per, dtype=np.uint64)
-    inv = 1.0 / np.sqrt(2.0)
+    inv = np.sqrt(0.5)  # 1/sqrt(2) correctly rounded
     for s in range(nsrc):
         with np.errstate(over="ignore"):
             k = np.uint64((int(src_offset) + s) * per) + idx

@@ -41,7 +41,9 @@ def test_noise_bit_layout():
     for k, hv in zip(ks, h):
         re = -1 if int(hv) & 1 else 1
         im = -1 if int(hv) & 2 else 1
-        assert eta[int(k)] == (re + 1j * im) / np.sqrt(2)
+        assert eta[int(k)] == (re + 1j * im) * np.sqrt(0.5)
+    # the modulus factor is 1/sqrt(2) correctly rounded (the same double every generator uses)
+    assert np.sqrt(0.5) == float.fromhex("0x1.6a09e667f3bcdp-1")
 
 
 def test_gauge_links_are_su3_and_chunking_is_exact():
