@@ -283,6 +283,8 @@ extern "C" int a2a_init(a2a_ctx** out, int device, size_t budget, void* stream) 
   }
   c->budget = budget ? budget : (size_t)(0.9 * (double)fr);
   c->sid_cap = SID_CAP;
+  const char* dbg = std::getenv("A2A_DEBUG");
+  c->debug = dbg && dbg[0] == '1';
   void* p = nullptr;
   if (c->dalloc(&p, sizeof(double) * NSCAL * SID_CAP) ||
       hipMemset(p, 0, sizeof(double) * NSCAL * SID_CAP) != hipSuccess) {

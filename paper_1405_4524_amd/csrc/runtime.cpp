@@ -694,6 +694,10 @@ int Solver::check() {
     const double* sc = ctx->scal_host + (size_t)s->sid * NSCAL;
     const double r = std::sqrt(sc[SC_R64N2]);
     const bool was_restart = std::find(restart.begin(), restart.end(), i) != restart.end();
+    if (ctx->debug)
+      std::fprintf(stderr, "[a2a] slot %d iter %d: est %.3e true %.3e last %.3e target %.3e flags %g%s\n", s->sid,
+                   s->iters, std::sqrt(sc[SC_RNORM2]) * sc[SC_SIGMA], r, s->last_r64, s->target, sc[SC_FLAGS],
+                   was_restart ? " (breakdown)" : "");
     if (!std::isfinite(r)) {
       s->state = SS_FAIL;
       s->err = A2A_EBREAKDOWN;

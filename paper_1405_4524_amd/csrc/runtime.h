@@ -162,6 +162,7 @@ struct Ctx {
   double delta_lo = 0.1, delta_64 = 1e-3;
   int xcd_order = 1;
   int timing = 0;
+  int debug = 0;  // A2A_DEBUG=1 in the environment: residual trace on stderr
   // reduction scratch
   double* scal_pool = nullptr;
   double* scal_host = nullptr;

@@ -167,6 +167,30 @@ def test_solve_tiny_residual_and_error(ctx, orc, tiny_ref, prec):
     ctx.unload(g)
 
 
+@pytest.mark.parametrize("R", [1, 2, 4])
+@pytest.mark.parametrize("prec", [1, 2])
+def test_solve_rhs_block_widths(ctx, orc, R, prec):
+    """Every stencil RHS-block width solves to the tolerance (the binding criterion, checked
+    with the oracle's D) on a lattice of several site blocks per parity."""
+    dims, tbc, kappa, csw = (8, 8, 8, 16), -1, 0.13, 1.5
+    print(f"[gpu] solve rhs_block={R} prec={prec}", flush=True)
+    U = inputs.gauge_field(dims, 0.35, 1)
+    A = orc.clover(U, kappa, csw)
+    eta = inputs.z2_noise(dims, 5, seed=6)
+    g = ctx.load_gauge(U, tbc)
+    c = ctx.load_clover(g, csw)
+    ctx.set_option("rhs_block", R)
+    try:
+        X, info, rc = ctx.solve_propagators(c, eta, kappa, csw, tol=1e-10, prec=prec, max_iter=5000)
+    finally:
+        ctx.set_option("rhs_block", 4)
+    assert rc == 0, info
+    for i in range(5):
+        r = eta[i] - orc.apply_D(U, A, kappa, X[i], tbc)
+        assert np.linalg.norm(r) / np.linalg.norm(eta[i]) <= 1e-10
+    ctx.unload(g)
+
+
 def test_solve_zero_source_and_initial_guess(ctx, orc, tiny_ref):
     w, U, A, eta, Xo = tiny_ref
     print("[gpu] zero source / x0", flush=True)
