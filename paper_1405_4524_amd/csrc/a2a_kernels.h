@@ -42,6 +42,7 @@ enum VecKind {
   VK_ZERO_HI,       // hi[vout] = 0
   VK_ZERO_LO,       // lo[vout] = 0
   VK_FILL_LO,       // lo[vout] = deterministic pseudo-random values (benchmarks)
+  VK_ZERO_X,        // inner x = 0
 };
 
 struct VecArgs {

@@ -99,6 +99,16 @@ __device__ __forceinline__ void cmul(double ar, double ai, double br, double bi,
   ci = ar * bi + ai * br;
 }
 
+// New inner-vector scale at a reliable update.  The residual is brought back to unit RMS
+// per component, but the scale may shrink by at most RU_MAX_RATIO per update: the search
+// directions p, v are carried over multiplied by sigma_old / sigma_new, and an unbounded
+// ratio (after a fast drop of the residual) would push FP16 intermediates past 65504.
+constexpr double RU_MAX_RATIO = 16.0;
+__host__ __device__ inline double ru_scale(double r64n2, double sigma_old, int hv) {
+  const double s = sqrt(r64n2 / (12.0 * hv));
+  return fmax(s, sigma_old / RU_MAX_RATIO);
+}
+
 // scalar update for one slot from the fully reduced values v[]; hv = sites per parity
 __device__ inline void finalize_slot(int kind, double* sc, const double* v, int hv) {
   switch (kind) {
@@ -157,7 +167,7 @@ __device__ inline void finalize_slot(int kind, double* sc, const double* v, int 
       sc[SC_FLAGS] = 0.0;
     } break;
     case RED_RU: {
-      double snew = sqrt(sc[SC_R64N2] / (12.0 * hv));
+      double snew = ru_scale(sc[SC_R64N2], sc[SC_SIGMA], hv);
       double ratio = sc[SC_SIGMA] / snew;  // old units -> new units
       double pr = sc[SC_RHOPREV] * ratio, pi = sc[SC_RHOPREV + 1] * ratio;
       double qr, qi, ar, ai, br, bi;

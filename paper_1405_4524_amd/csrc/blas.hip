@@ -31,6 +31,7 @@ __device__ __forceinline__ void dot3(const Spinor<A>& a, const Spinor<A>& b, dou
 template <class P, int KIND>
 __global__ __launch_bounds__(BS) void k_vec(VecArgs a) {
   using S = typename P::S;
+  using SX = typename P::SX;
   using A = typename P::A;
   const int2 tile = a.tiles[blockIdx.x];
   const SlotDev& sd = a.slots[tile.x];
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(BS) void k_vec(VecArgs a) {
     if (valid) {
       const cx<A> al = scal_c<A>(sc, SC_ALPHA), om = scal_c<A>(sc, SC_OMEGA);
       Spinor<A> x, p, s, t;
-      load_spinor<S, A>(LO(VL_X), hv, site, x);
+      load_spinor<SX, A>(LO(VL_X), hv, site, x);
       load_spinor<S, A>(LO(VL_P), hv, site, p);
       load_spinor<S, A>(LO(VL_S), hv, site, s);
       load_spinor<S, A>(LO(VL_T), hv, site, t);
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(BS) void k_vec(VecArgs a) {
         x.v[k] = x.v[k] + al * p.v[k] + om * s.v[k];
         s.v[k] = s.v[k] - om * t.v[k];
       }
-      store_spinor<S, A>(LO(VL_X), hv, site, x);
+      store_spinor<SX, A>(LO(VL_X), hv, site, x);
       store_spinor<S, A>(LO(VL_R), hv, site, s);
       load_spinor<S, A>(LO(VL_R), hv, site, s);  // reduce the stored values
       Spinor<A> rh;
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(BS) void k_vec(VecArgs a) {
     const double sg = sc[SC_SIGMA];
     Spinor<A> xl;
     Spinor<double> xh;
-    load_spinor<S, A>(LO(VL_X), hv, site, xl);
+    load_spinor<SX, A>(LO(VL_X), hv, site, xl);
     load_spinor<double, double>(HI(VH_X), hv, site, xh);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -101,10 +102,11 @@ __global__ __launch_bounds__(BS) void k_vec(VecArgs a) {
       xl.v[k] = mk((A)0, (A)0);
     }
     store_spinor<double, double>(HI(VH_X), hv, site, xh);
-    store_spinor<S, A>(LO(VL_X), hv, site, xl);
+    store_spinor<SX, A>(LO(VL_X), hv, site, xl);
   } else if (KIND == VK_RU_RESCALE || KIND == VK_INIT) {
     double v3[3] = {0.0, 0.0, 0.0};
-    const double snew = sqrt(sc[SC_R64N2] / (12.0 * hv));
+    const double snew =
+        KIND == VK_INIT ? sqrt(sc[SC_R64N2] / (12.0 * hv)) : ru_scale(sc[SC_R64N2], sc[SC_SIGMA], hv);
     const double inv = (snew > 0.0) ? 1.0 / snew : 0.0;
     if (valid) {
       Spinor<double> rh64;
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(BS) void k_vec(VecArgs a) {
         store_spinor<S, A>(LO(VL_RHAT), hv, site, r);
         store_spinor<S, A>(LO(VL_P), hv, site, r);
         store_spinor<S, A>(LO(VL_V), hv, site, z);
-        store_spinor<S, A>(LO(VL_X), hv, site, z);
+        store_spinor<SX, A>(LO(VL_X), hv, site, z);
         rh = r;
       } else {
         const A ratio = (A)(sc[SC_SIGMA] * inv);
@@ -151,6 +153,12 @@ __global__ __launch_bounds__(BS) void k_vec(VecArgs a) {
     load_spinor<double, double>(HI(a.vin), hv, site, in);
     clover_apply_mem<double, double>(C, hv, site, in, out);
     store_spinor<double, double>(HI(a.vout), hv, site, out);
+  } else if (KIND == VK_ZERO_X) {
+    if (!valid) return;
+    Spinor<A> z;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) z.v[k] = mk((A)0, (A)0);
+    store_spinor<SX, A>(LO(VL_X), hv, site, z);
   } else if (KIND == VK_ZERO_HI) {
     if (!valid) return;
     Spinor<double> z;
@@ -191,6 +199,7 @@ static void launch_vec_p(const VecArgs& a, int n, hipStream_t s) {
     case VK_INIT: hipLaunchKernelGGL((k_vec<P, VK_INIT>), g, b, 0, s, a); break;
     case VK_CLOVER: hipLaunchKernelGGL((k_vec<P, VK_CLOVER>), g, b, 0, s, a); break;
     case VK_ZERO_HI: hipLaunchKernelGGL((k_vec<P, VK_ZERO_HI>), g, b, 0, s, a); break;
+    case VK_ZERO_X: hipLaunchKernelGGL((k_vec<P, VK_ZERO_X>), g, b, 0, s, a); break;
     case VK_ZERO_LO: hipLaunchKernelGGL((k_vec<P, VK_ZERO_LO>), g, b, 0, s, a); break;
     case VK_FILL_LO: hipLaunchKernelGGL((k_vec<P, VK_FILL_LO>), g, b, 0, s, a); break;
     default: break;

@@ -683,8 +683,15 @@ int Solver::check() {
   if (ru.empty() && restart.empty()) return A2A_OK;
   std::vector<int> all(ru);
   all.insert(all.end(), restart.begin(), restart.end());
+  if (!restart.empty()) {  // a broken-down inner iterate may hold inf/NaN: drop it, keep x64
+    A2A_TRY(upload_subset(restart, 1));
+    A2A_TRY(vec(true, sub_nv, VK_ZERO_X));
+  }
+  if (!ru.empty()) {
+    A2A_TRY(upload_subset(ru, 1));
+    A2A_TRY(vec(true, sub_nv, VK_RU_ACCUM));
+  }
   A2A_TRY(upload_subset(all, 1));
-  A2A_TRY(vec(true, sub_nv, VK_RU_ACCUM));
   A2A_TRY(true_residual(all));
   A2A_TRY(ctx->read_scal());
   std::vector<int> done, rescale, reinit;
