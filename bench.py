@@ -40,7 +40,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="l32t64")
     ap.add_argument("--prec", default="f16", choices=list(PREC))
-    ap.add_argument("--rhs-block", type=int, default=4)
+    ap.add_argument("--rhs-block", type=int, default=2)
     ap.add_argument("--check-every", type=int, default=4)
     ap.add_argument("--fp64-sources", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
