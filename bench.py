@@ -45,6 +45,9 @@ def main():
     ap.add_argument("--fp64-sources", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and stencil side measurements")
+    ap.add_argument("--stencil-only", action="store_true",
+                    help="time only the one-parity hopping stencil and a plain copy (for counter runs)")
+    ap.add_argument("--stencil-reps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
@@ -77,15 +80,21 @@ def main():
     ctx.set_option("rhs_block", args.rhs_block)
     ctx.set_option("check_every", args.check_every)
 
+    if args.stencil_only:
+        stencil_only(args, ctx, links, dims, tbc, kappa, csw, V)
+        return
+
     infos = []
 
     def step():
         g = ctx.load_gauge_dev(links, dims, tbc)
         c = ctx.load_clover(g, csw)
         info, rc = ctx.solve_propagators_dev(c, src, sol, nsrc, kappa, csw, tol=tol, prec=prec, allow=())
-        corr, _ = ctx.contract_pion_2pt_dev(src, sol, nsrc, dims, tbc)
-        diag, vac = ctx.contract_pipi_2pt_dev(src, sol, nsrc, dims, tbc) if nsrc % 4 == 0 and nsrc <= 128 \
-            else (None, None)
+        if nsrc % 4 == 0 and nsrc <= 128:  # one pass over (eta, X): pi-pi pieces and the pion
+            diag, vac, corr = ctx.contract_pipi_2pt_dev(src, sol, nsrc, dims, tbc, want_pion=True)
+        else:
+            corr, _ = ctx.contract_pion_2pt_dev(src, sol, nsrc, dims, tbc)
+            diag = None
         ctx.unload(g)
         infos.append(info)
         return corr, diag
@@ -181,6 +190,41 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, links_np)
     print(json.dumps(out), flush=True)
+
+
+def stencil_only(args, ctx, links, dims, tbc, kappa, csw, V):
+    """H_eo alone in each precision, plus a plain device copy of 1 GiB whose counters calibrate
+    FETCH_SIZE / WRITE_SIZE (a copy reads and writes exactly its size)."""
+    import torch
+
+    from paper_1405_4524_amd import a2a
+
+    g = ctx.load_gauge_dev(links, dims, tbc)
+    c = ctx.load_clover(g, csw)
+    res = {}
+    for p_name, p, n, rb in (("f64", 0, 1, 1), ("f32", 1, 1, 1), ("f16", 2, 1, 1), ("f16", 2, 16, 2)):
+        ctx.set_option("rhs_block", rb)
+        ms = ctx.bench_stencil(c, kappa, a2a.OP_HOP_EO, p, n, args.stencil_reps)
+        sb = STORAGE_BYTES[p]
+        byts = (V // 2) * (8 * 18 * sb + 2 * n * 24 * sb)
+        res[f"{p_name}_n{n}"] = {"ms": round(ms, 4), "alg_bytes": byts, "GBps": round(byts / (ms * 1e-3) / 1e9, 1)}
+        log(f"stencil {p_name} n={n}: {ms:.4f} ms, {res[f'{p_name}_n{n}']['GBps']} GB/s")
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.stencil_reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.stencil_reps
+    res["copy_1GiB"] = {"ms": round(ms, 4), "GBps": round(2 * (1 << 30) / (ms * 1e-3) / 1e9, 1)}
+    log(f"copy 1 GiB: {ms:.4f} ms")
+    ctx.unload(g)
+    ctx.finalize()
+    print(json.dumps({"stencil_only": res, "workload": args.workload}), flush=True)
 
 
 def cpu_baseline(w, links_np):

@@ -159,12 +159,15 @@ int a2a_contract_pion_2pt_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *
 /* Zero-momentum pi-pi pieces from four disjoint noise groups (nrhs = 4m, 1 <= m <= 32):
  * diagrams complex [4][T] = D0 (direct), D1 (vacuum, unsubtracted), D2, D3 (single quark
  * loop through the four points, both orientations); vac_pieces complex [T] = the
- * timeslice loop L(t, t) of groups 1 and 2.  The total is D0 + D1 - D2 - D3 (Sec. 8). */
+ * timeslice loop L(t, t) of groups 1 and 2.  The total is D0 + D1 - D2 - D3 (Sec. 8).
+ * pion_or_null (complex [T]): the unbiased pion correlator from the same O, so one pass
+ * over (eta, X) serves both. */
 int a2a_contract_pipi_2pt(a2a_ctx *ctx, const a2a_geom *geom, const double *sources_host,
-                          const double *solutions_host, int nrhs, double *diagrams, double *vac_pieces);
+                          const double *solutions_host, int nrhs, double *diagrams, double *vac_pieces,
+                          double *pion_or_null);
 int a2a_contract_pipi_2pt_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *sources_dev,
                               const double *solutions_dev, int nrhs, double *diagrams_host,
-                              double *vac_pieces_host);
+                              double *vac_pieces_host, double *pion_or_null);
 
 /* ---- synthetic inputs ---------------------------------------------------------------- */
 /* Complex-Z2 noise (Sec. 7 "Z2 noise", here (+-1 +- i)/sqrt 2) written to a canonical

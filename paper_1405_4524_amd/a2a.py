@@ -65,8 +65,8 @@ _SIG = {
     "a2a_solve_propagators_dev": (I, [P, I, P, I, D, D, D, I, I, P, P, P]),
     "a2a_contract_pion_2pt": (I, [P, ctypes.POINTER(Geom), P, P, I, I, P, P]),
     "a2a_contract_pion_2pt_dev": (I, [P, ctypes.POINTER(Geom), P, P, I, I, P, P]),
-    "a2a_contract_pipi_2pt": (I, [P, ctypes.POINTER(Geom), P, P, I, P, P]),
-    "a2a_contract_pipi_2pt_dev": (I, [P, ctypes.POINTER(Geom), P, P, I, P, P]),
+    "a2a_contract_pipi_2pt": (I, [P, ctypes.POINTER(Geom), P, P, I, P, P, P]),
+    "a2a_contract_pipi_2pt_dev": (I, [P, ctypes.POINTER(Geom), P, P, I, P, P, P]),
     "a2a_z2_noise_dev": (I, [P, ctypes.POINTER(Geom), ULL, LL, I, P]),
     "a2a_engine_create": (I, [P, ctypes.c_char_p, ctypes.POINTER(P)]),
     "a2a_engine_submit": (I, [P, I, D, P, I, D, I, I, P, ctypes.POINTER(LL)]),
@@ -298,7 +298,8 @@ class Context:
                                                   O.ctypes.data_as(P) if want_O else None))
         return corr, O
 
-    def contract_pipi_2pt(self, sources, solutions, t_bc=-1):
+    def contract_pipi_2pt(self, sources, solutions, t_bc=-1, want_pion=False):
+        """(diagrams[4, T], vac[T]) and, with want_pion, also the unbiased pion correlator."""
         s, ps = _np_c128(sources)
         x, px = _np_c128(solutions)
         n = s.shape[0]
@@ -306,18 +307,21 @@ class Context:
         T = g.dims[3]
         d = np.empty((4, T), np.complex128)
         v = np.empty(T, np.complex128)
+        pc = np.empty(T, np.complex128) if want_pion else None
         self._chk(lib().a2a_contract_pipi_2pt(self._c, ctypes.byref(g), ps, px, n, d.ctypes.data_as(P),
-                                              v.ctypes.data_as(P)))
-        return d, v
+                                              v.ctypes.data_as(P), pc.ctypes.data_as(P) if want_pion else None))
+        return (d, v, pc) if want_pion else (d, v)
 
-    def contract_pipi_2pt_dev(self, src_t, sol_t, nrhs, dims, t_bc=-1):
+    def contract_pipi_2pt_dev(self, src_t, sol_t, nrhs, dims, t_bc=-1, want_pion=False):
         g = geom(dims, t_bc)
         T = g.dims[3]
         d = np.empty((4, T), np.complex128)
         v = np.empty(T, np.complex128)
+        pc = np.empty(T, np.complex128) if want_pion else None
         self._chk(lib().a2a_contract_pipi_2pt_dev(self._c, ctypes.byref(g), _tptr(src_t), _tptr(sol_t), int(nrhs),
-                                                  d.ctypes.data_as(P), v.ctypes.data_as(P)))
-        return d, v
+                                                  d.ctypes.data_as(P), v.ctypes.data_as(P),
+                                                  pc.ctypes.data_as(P) if want_pion else None))
+        return (d, v, pc) if want_pion else (d, v)
 
     # ---- inputs
     def z2_noise_dev(self, dims, seed, src_offset, nsrc, out_t):

@@ -656,7 +656,7 @@ extern "C" int a2a_contract_pion_2pt_dev(a2a_ctx* h, const a2a_geom* geom, const
 }
 
 static int pipi_impl(a2a_ctx* h, const a2a_geom* geom, const double* src, const double* sol, int n, double* diag,
-                     double* vac, bool dev) {
+                     double* vac, double* pion, bool dev) {
   if (!h || !src || !sol || !diag) return A2A_EINVAL;
   Ctx* c = &h->c;
   (void)hipSetDevice(c->device);
@@ -680,17 +680,21 @@ static int pipi_impl(a2a_ctx* h, const a2a_geom* geom, const double* src, const 
   }
   double* O = nullptr;
   int rc = contract_ops(c, g, ds, dx, n, &O);
-  void *dd = nullptr, *dv = nullptr;
+  void *dd = nullptr, *dv = nullptr, *dp = nullptr;
   if (!rc) rc = c->dalloc(&dd, sizeof(double) * 2 * 4 * g.T);
   if (!rc) rc = c->dalloc(&dv, sizeof(double) * 2 * g.T);
+  if (!rc && pion) rc = c->dalloc(&dp, sizeof(double) * 2 * g.T);
   if (!rc) {
     launch_pipi(g.T, n, O, (double*)dd, (double*)dv, c->stream);
+    if (pion) launch_pion_corr(g.T, n, O, A2A_PION_UNBIASED, (double*)dp, c->stream);
     rc = copy_to_host(c, diag, dd, sizeof(double) * 2 * 4 * g.T);
     if (!rc && vac) rc = copy_to_host(c, vac, dv, sizeof(double) * 2 * g.T);
+    if (!rc && pion) rc = copy_to_host(c, pion, dp, sizeof(double) * 2 * g.T);
   }
   c->sync();
   c->dfree(dd);
   c->dfree(dv);
+  c->dfree(dp);
   c->dfree(O);
   c->dfree(bs);
   c->dfree(bx);
@@ -698,13 +702,13 @@ static int pipi_impl(a2a_ctx* h, const a2a_geom* geom, const double* src, const 
 }
 
 extern "C" int a2a_contract_pipi_2pt(a2a_ctx* h, const a2a_geom* geom, const double* src, const double* sol, int n,
-                                     double* diag, double* vac) {
-  return pipi_impl(h, geom, src, sol, n, diag, vac, false);
+                                     double* diag, double* vac, double* pion) {
+  return pipi_impl(h, geom, src, sol, n, diag, vac, pion, false);
 }
 
 extern "C" int a2a_contract_pipi_2pt_dev(a2a_ctx* h, const a2a_geom* geom, const double* src, const double* sol,
-                                         int n, double* diag, double* vac) {
-  return pipi_impl(h, geom, src, sol, n, diag, vac, true);
+                                         int n, double* diag, double* vac, double* pion) {
+  return pipi_impl(h, geom, src, sol, n, diag, vac, pion, true);
 }
 
 extern "C" int a2a_z2_noise_dev(a2a_ctx* h, const a2a_geom* geom, unsigned long long seed, long long src_offset,

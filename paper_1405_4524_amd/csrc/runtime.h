@@ -159,7 +159,7 @@ struct Ctx {
   // options
   int rhs_block = 4;
   int check_every = 4;
-  double delta_lo = 0.1, delta_64 = 1e-3;
+  double delta_lo = 0.01, delta_64 = 1e-3;
   int xcd_order = 1;
   int timing = 0;
   int debug = 0;  // A2A_DEBUG=1 in the environment: residual trace on stderr

@@ -280,11 +280,13 @@ def test_contraction_pipi(ctx, orc):
     rng = np.random.default_rng(4)
     eta = inputs.z2_noise(dims, n, seed=13)
     sol = rng.standard_normal(eta.shape) + 1j * rng.standard_normal(eta.shape)
-    d, v = ctx.contract_pipi_2pt(eta, sol)
+    d, v, pc = ctx.contract_pipi_2pt(eta, sol, want_pion=True)
     dw, vw = orc.contract_pipi(eta, sol)
     for k in range(4):
         assert rel(d[k], dw[k]) < 1e-11, k
     assert rel(v, vw) < 1e-12
+    pw, _ = orc.contract_pion(eta, sol)
+    assert rel(pc, pw) < 1e-12
 
 
 def test_tiny_end_to_end_correlator(ctx, orc, tiny_ref):
