@@ -48,6 +48,12 @@ def main():
     ap.add_argument("--stencil-only", action="store_true",
                     help="time only the one-parity hopping stencil and a plain copy (for counter runs)")
     ap.add_argument("--stencil-reps", type=int, default=20)
+    ap.add_argument("--serve", action="store_true",
+                    help="serving run: Poisson request streams on resident 8^3x16, 16^3x32, 24^3x48 fields")
+    ap.add_argument("--serve-rates", default="1,2,5,10,20,50")
+    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--mixed", action="store_true",
+                    help="mixed-lattice batch: 8^3x16, 16^3x32, 24^3x48 with 8-32 sources each in one batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
@@ -58,6 +64,10 @@ def main():
     import torch
 
     from paper_1405_4524_amd import a2a, inputs
+
+    if args.serve or args.mixed:
+        serve_or_mixed(args)
+        return
 
     w = inputs.WORKLOADS[args.workload]
     dims, tbc, kappa, csw, nsrc, tol = w["dims"], w["tbc"], w["kappa"], w["csw"], w["nsrc"], w["tol"]
@@ -189,6 +199,123 @@ def main():
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, links_np)
+    print(json.dumps(out), flush=True)
+
+
+SERVE_LATTICES = [((8, 8, 8, 16), 11), ((16, 16, 16, 32), 12), ((24, 24, 24, 48), 13)]
+
+
+def serve_or_mixed(args):
+    """Continuous batching through the engine (a2a_engine_*).
+
+    --mixed: one batch of the three lattices with 8-32 sources each (seed 4), all submitted
+    at once, against the same sources solved lattice by lattice with solve_propagators.
+    --serve: for each Poisson rate, N requests (seed 3 + rate): lattice uniform over the
+    three resident fields, kappa ~ U[0.120, 0.130], 1-64 sources, tol 1e-10, FP16/FP32 +
+    FP64 reliable updates.  Requests are submitted at their arrival times while the engine
+    steps; latency = completion - arrival on the host clock; p50/p99 and RHS/s per rate."""
+    import numpy as np
+    import torch
+
+    from paper_1405_4524_amd import a2a, inputs
+
+    csw, tbc, eps, prec = 1.5, -1, 0.35, PREC[args.prec]
+    ctx = a2a.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+    ctx.set_option("rhs_block", args.rhs_block)
+    fields = []
+    for dims, seed in SERVE_LATTICES:
+        g = ctx.load_gauge(inputs.gauge_field(dims, eps, seed), tbc)
+        fields.append(dict(dims=dims, c=ctx.load_clover(g, csw), V=int(np.prod(dims))))
+    log("resident fields loaded")
+    next_src = [0]
+
+    def make_sources(f, n):
+        X, Y, Z, T = f["dims"]
+        src = torch.empty((n, T, Z, Y, X, 4, 3, 2), dtype=torch.float64, device="cuda")
+        ctx.z2_noise_dev(f["dims"], 7, next_src[0], n, src)
+        next_src[0] += n
+        return src, torch.zeros_like(src)
+
+    out = {"mode": "mixed" if args.mixed else "serve", "precision": args.prec, "rhs_block": args.rhs_block}
+    if args.mixed:
+        rng = np.random.default_rng(4)
+        jobs = []
+        for f in fields:
+            n = int(rng.integers(8, 33))
+            src, sol = make_sources(f, n)
+            jobs.append((f, n, src, sol))
+        kappa = 0.13
+        # lattice by lattice
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for f, n, src, sol in jobs:
+            ctx.solve_propagators_dev(f["c"], src, sol, n, kappa, csw, tol=1e-10, prec=prec)
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t
+        ref = [sol.clone() for _, _, _, sol in jobs]
+        # one batch through the engine
+        eng = ctx.engine_create('{"max_slots": 256}')
+        for _, _, _, sol in jobs:
+            sol.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        tickets = [eng.submit(f["c"], kappa, src, n, 1e-10, prec, 100000, sol) for f, n, src, sol in jobs]
+        while True:
+            eng.step(8)
+            if all(eng.poll(tk, n)[0] != 0 for tk, (_, n, _, _) in zip(tickets, jobs)):
+                break
+        torch.cuda.synchronize()
+        t_mix = time.perf_counter() - t
+        ntot = sum(n for _, n, _, _ in jobs)
+        diff = max(float(torch.linalg.vector_norm(sol - r) / torch.linalg.vector_norm(r))
+                   for (_, _, _, sol), r in zip(jobs, ref))
+        eng.destroy()
+        out.update({"lattices": [list(f["dims"]) for f, _, _, _ in jobs], "sources": [n for _, n, _, _ in jobs],
+                    "rhs_per_s_one_batch": round(ntot / t_mix, 2), "rhs_per_s_lattice_by_lattice": round(ntot / t_seq, 2),
+                    "max_rel_diff_batch_vs_alone": diff})
+        log(f"mixed batch {ntot / t_mix:.1f} RHS/s vs lattice by lattice {ntot / t_seq:.1f} RHS/s, diff {diff:.2e}")
+    else:
+        eng = ctx.engine_create('{"max_slots": 256, "check_every": 4}')
+        results = []
+        for rate in [float(x) for x in args.serve_rates.split(",")]:
+            rng = np.random.default_rng(3 + int(rate))
+            nreq = args.serve_requests
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
+            spec = [(int(rng.integers(0, 3)), float(rng.uniform(0.120, 0.130)), int(rng.integers(1, 65)))
+                    for _ in range(nreq)]
+            live, lat, nrhs_done = {}, [], 0
+            k = 0
+            t0 = time.perf_counter()
+            while k < nreq or live:
+                now = time.perf_counter() - t0
+                while k < nreq and arrivals[k] <= now:
+                    li, kappa, n = spec[k]
+                    f = fields[li]
+                    src, sol = make_sources(f, n)
+                    tk = eng.submit(f["c"], kappa, src, n, 1e-10, prec, 100000, sol)
+                    live[tk] = (arrivals[k], n, src, sol)
+                    k += 1
+                if live:
+                    eng.step(4)
+                else:
+                    time.sleep(max(0.0, min(0.01, arrivals[k] - now)))
+                for tk in list(live):
+                    done, info, rc = eng.poll(tk, live[tk][1])
+                    if done:
+                        if done < 0 or not all(x["converged"] for x in info):
+                            raise RuntimeError(f"request {tk} failed: {rc}")
+                        lat.append(time.perf_counter() - t0 - live[tk][0])
+                        nrhs_done += live[tk][1]
+                        del live[tk]
+            span = time.perf_counter() - t0
+            r = {"rate_req_per_s": rate, "requests": nreq, "p50_s": round(float(np.percentile(lat, 50)), 4),
+                 "p99_s": round(float(np.percentile(lat, 99)), 4), "rhs_per_s": round(nrhs_done / span, 2),
+                 "makespan_s": round(span, 2), "hbm_in_use_GB": round(ctx.mem_in_use() / 1e9, 2)}
+            results.append(r)
+            log(f"serve {r}")
+        eng.destroy()
+        out["rates"] = results
+    ctx.finalize()
     print(json.dumps(out), flush=True)
 
 

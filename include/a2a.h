@@ -102,8 +102,8 @@ int a2a_finalize(a2a_ctx *ctx);
 const char *a2a_last_error(const a2a_ctx *ctx);
 /* Tuning knobs: "rhs_block" (1, 2, 4: RHS per thread in the stencil), "check_every"
  * (iterations between residual checks), "delta" (reliable-update reduction factor),
- * "xcd_order" (0/1), "kernel_timing" (0/1), "hbm_budget" (bytes; resets the budget given at
- * a2a_init).  Returns A2A_EINVAL for an unknown key. */
+ * "xcd_order" (0/1), "kernel_timing" (0/1), "autotune" (0/1), "hbm_budget" (bytes; resets
+ * the budget given at a2a_init).  Returns A2A_EINVAL for an unknown key. */
 int a2a_set_option(a2a_ctx *ctx, const char *key, double value);
 /* Bytes of device memory currently held by the context. */
 size_t a2a_mem_in_use(const a2a_ctx *ctx);
@@ -132,6 +132,14 @@ int a2a_dslash_clover_dev(a2a_ctx *ctx, int clover_h, double kappa, int op, int 
  * kernel milliseconds per application measured with HIP events on the context stream. */
 int a2a_bench_stencil(a2a_ctx *ctx, int clover_h, double kappa, int op, int prec, int nrhs, int reps,
                       double *ms_per_apply);
+
+/* Autotune the stencil's RHS-block width (right-hand sides per thread sharing each link and
+ * clover load: 1, 2 or 4) for this lattice, precision and number of sources: times the
+ * Schur operator on min(nrhs, 16) fields for each width, stores the fastest in the context
+ * (and in the JSON file named by the environment variable A2A_TUNE_CACHE, keyed by arch,
+ * lattice, precision and RHS bucket).  ms_per_width (optional, [3]) receives the times for
+ * widths 1, 2, 4 (-1 where not tried).  With option "autotune" = 1 solves tune on first use. */
+int a2a_autotune(a2a_ctx *ctx, int clover_h, double kappa, int prec, int nrhs, int *best_R, double *ms_per_width);
 
 /* ---- solves (Sec. 7: X_i = D^{-1} eta_i) --------------------------------------------- */
 /* Solve D X_i = eta_i for nrhs sources with even-odd preconditioning (odd-site Schur

@@ -61,6 +61,7 @@ _SIG = {
     "a2a_dslash_clover": (I, [P, I, D, I, I, I, P, P, I]),
     "a2a_dslash_clover_dev": (I, [P, I, D, I, I, I, P, P, I]),
     "a2a_bench_stencil": (I, [P, I, D, I, I, I, I, ctypes.POINTER(D)]),
+    "a2a_autotune": (I, [P, I, D, I, I, ctypes.POINTER(I), P]),
     "a2a_solve_propagators": (I, [P, I, P, I, D, D, D, I, I, P, P, P]),
     "a2a_solve_propagators_dev": (I, [P, I, P, I, D, D, D, I, I, P, P, P]),
     "a2a_contract_pion_2pt": (I, [P, ctypes.POINTER(Geom), P, P, I, I, P, P]),
@@ -248,6 +249,14 @@ class Context:
         self._chk(lib().a2a_bench_stencil(self._c, int(clover_h), float(kappa), int(op), int(prec), int(nrhs),
                                           int(reps), ctypes.byref(ms)))
         return ms.value
+
+    def autotune(self, clover_h, kappa, prec, nrhs):
+        """(best RHS-block width, {width: ms of one Schur application})."""
+        r = I()
+        ms = (D * 3)()
+        self._chk(lib().a2a_autotune(self._c, int(clover_h), float(kappa), int(prec), int(nrhs), ctypes.byref(r),
+                                     ms))
+        return r.value, {w: ms[k] for k, w in enumerate((1, 2, 4)) if ms[k] >= 0}
 
     # ---- solves
     def solve_propagators(self, clover_h, sources, kappa, csw, tol=1e-10, prec=F64, max_iter=100000, x0=None,

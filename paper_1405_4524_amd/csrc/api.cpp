@@ -13,6 +13,9 @@ struct a2a_ctx {
   Ctx c;
 };
 
+static int autotune_R(Ctx* c, int clover_h, double kappa, int prec, int nrhs, int* R, double* ms_out);
+static void tune_load(Ctx* c);
+
 namespace {
 
 constexpr int SID_CAP = 4096;
@@ -102,7 +105,9 @@ int solve_core(Ctx* c, int clover_h, const double* src, int nrhs, double kappa, 
     return c->fail(A2A_EINVAL, "c_sw does not match the clover handle");
   const long hv = gf->g.hv;
   const long long V = volume_of(gf->g);
-  Solver sv(c, prec, effective_R(c, prec));
+  int R = effective_R(c, prec);
+  if (c->autotune) A2A_TRY(autotune_R(c, clover_h, kappa, prec, nrhs, &R, nullptr));
+  Solver sv(c, prec, R);
   const int op = sv.op_index(clover_h, kappa, kop, gf);
   std::vector<Slot> slots(nrhs);
   int rc = A2A_OK;
@@ -285,6 +290,11 @@ extern "C" int a2a_init(a2a_ctx** out, int device, size_t budget, void* stream) 
   c->sid_cap = SID_CAP;
   const char* dbg = std::getenv("A2A_DEBUG");
   c->debug = dbg && dbg[0] == '1';
+  const char* tc = std::getenv("A2A_TUNE_CACHE");
+  if (tc && tc[0]) {
+    c->tune_path = tc;
+    tune_load(c);
+  }
   void* p = nullptr;
   if (c->dalloc(&p, sizeof(double) * NSCAL * SID_CAP) ||
       hipMemset(p, 0, sizeof(double) * NSCAL * SID_CAP) != hipSuccess) {
@@ -345,6 +355,8 @@ extern "C" int a2a_set_option(a2a_ctx* h, const char* key, double v) {
     c->xcd_order = v != 0;
   } else if (k == "kernel_timing") {
     c->timing = v != 0;
+  } else if (k == "autotune") {
+    c->autotune = v != 0;
   } else if (k == "hbm_budget") {
     if (!(v > 0)) return c->fail(A2A_EINVAL, "hbm_budget must be positive");
     c->budget = (size_t)v;
@@ -503,18 +515,15 @@ extern "C" int a2a_dslash_clover(a2a_ctx* h, int clover_h, double kappa, int op,
   return rc;
 }
 
-extern "C" int a2a_bench_stencil(a2a_ctx* h, int clover_h, double kappa, int opk, int prec, int nrhs, int reps,
-                                 double* ms) {
-  if (!h || !ms || nrhs <= 0 || reps <= 0) return A2A_EINVAL;
-  Ctx* c = &h->c;
-  (void)hipSetDevice(c->device);
-  if (check_prec(prec)) return c->fail(A2A_EINVAL, "unknown precision mode");
-  if (opk != A2A_OP_HOP_EO && opk != A2A_OP_SCHUR) return c->fail(A2A_EINVAL, "op must be HOP_EO or SCHUR");
+// mean milliseconds of one stencil application (HOP_EO, or the two launches of the Schur
+// operator) on nrhs device-layout fields with RHS-block width R, timed with HIP events
+static int stencil_time(Ctx* c, int clover_h, double kappa, int opk, int prec, int nrhs, int reps, int R,
+                        double* ms) {
   GaugeField* gf;
   CloverField* cf;
   KappaOp* kop;
   A2A_TRY(resolve_op(c, clover_h, kappa, prec, &gf, &cf, &kop));
-  Solver sv(c, prec, effective_R(c, prec));
+  Solver sv(c, prec, R);
   const int op = sv.op_index(clover_h, kappa, kop, gf);
   std::vector<Slot> slots(nrhs);
   int rc = A2A_OK;
@@ -552,6 +561,94 @@ extern "C" int a2a_bench_stencil(a2a_ctx* h, int clover_h, double kappa, int opk
   if (e1) (void)hipEventDestroy(e1);
   for (auto& s : slots) slot_free(c, &s);
   return rc;
+}
+
+extern "C" int a2a_bench_stencil(a2a_ctx* h, int clover_h, double kappa, int opk, int prec, int nrhs, int reps,
+                                 double* ms) {
+  if (!h || !ms || nrhs <= 0 || reps <= 0) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  if (check_prec(prec)) return c->fail(A2A_EINVAL, "unknown precision mode");
+  if (opk != A2A_OP_HOP_EO && opk != A2A_OP_SCHUR) return c->fail(A2A_EINVAL, "op must be HOP_EO or SCHUR");
+  return stencil_time(c, clover_h, kappa, opk, prec, nrhs, reps, effective_R(c, prec), ms);
+}
+
+// ---- autotuner: RHS-block width of the stencil, per (arch, lattice, precision, RHS bucket)
+static std::string tune_key(const Geo& g, int prec, int nrhs) {
+  int b = 1;
+  while (b < nrhs && b < 64) b <<= 1;
+  return "gfx950:" + std::to_string(g.X) + "x" + std::to_string(g.Y) + "x" + std::to_string(g.Z) + "x" +
+         std::to_string(g.T) + ":p" + std::to_string(prec) + ":n" + std::to_string(b);
+}
+
+static void tune_save(Ctx* c) {
+  if (c->tune_path.empty()) return;
+  FILE* f = std::fopen(c->tune_path.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "{");
+  bool first = true;
+  for (auto& kv : c->tuned) {
+    std::fprintf(f, "%s\n  \"%s\": %d", first ? "" : ",", kv.first.c_str(), kv.second);
+    first = false;
+  }
+  std::fprintf(f, "\n}\n");
+  std::fclose(f);
+}
+
+static void tune_load(Ctx* c) {
+  if (c->tune_path.empty()) return;
+  FILE* f = std::fopen(c->tune_path.c_str(), "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    char key[400];
+    int r;
+    if (std::sscanf(line, " \"%399[^\"]\": %d", key, &r) == 2 && (r == 1 || r == 2 || r == 4)) c->tuned[key] = r;
+  }
+  std::fclose(f);
+}
+
+// Time the Schur operator for each candidate width on min(nrhs, 16) fields and keep the
+// fastest; results are cached in the context (and in A2A_TUNE_CACHE if set).
+static int autotune_R(Ctx* c, int clover_h, double kappa, int prec, int nrhs, int* R, double* ms_out) {
+  CloverField* cf = c->clover(clover_h);
+  if (!cf) return c->fail(A2A_EHANDLE, "unknown clover handle");
+  const Geo g = c->gauge(cf->gauge)->g;
+  const std::string key = tune_key(g, prec, nrhs);
+  for (int k = 0; k < 3; ++k)
+    if (ms_out) ms_out[k] = -1.0;
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end() && !ms_out) {
+    *R = it->second;
+    return A2A_OK;
+  }
+  const int n = std::min(nrhs, 16);
+  const int cand[3] = {1, 2, 4};
+  double best = 1e300;
+  int bestR = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (prec == 0 && cand[k] > 2) continue;
+    double ms = 0;
+    A2A_TRY(stencil_time(c, clover_h, kappa, A2A_OP_SCHUR, prec, n, 3, cand[k], &ms));
+    if (ms_out) ms_out[k] = ms;
+    if (ms < best) {
+      best = ms;
+      bestR = cand[k];
+    }
+  }
+  c->tuned[key] = bestR;
+  tune_save(c);
+  *R = bestR;
+  return A2A_OK;
+}
+
+extern "C" int a2a_autotune(a2a_ctx* h, int clover_h, double kappa, int prec, int nrhs, int* best_R,
+                            double* ms_per_width) {
+  if (!h || !best_R || nrhs <= 0) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  if (check_prec(prec)) return c->fail(A2A_EINVAL, "unknown precision mode");
+  return autotune_R(c, clover_h, kappa, prec, nrhs, best_R, ms_per_width);
 }
 
 // =========================================================================================
@@ -884,6 +981,10 @@ extern "C" int a2a_engine_step(a2a_engine* e, int iters, int* active) {
     }
     if (e->active + r->nsrc > e->max_slots) break;
     int rc = engine_admit(e, r);
+    if (rc == A2A_ENOMEM && c->evict_unused_kops() > 0) {  // drop clover fields of finished kappas
+      c->err.clear();
+      rc = engine_admit(e, r);
+    }
     if (rc == A2A_ENOMEM && e->active > 0) {  // wait for memory to free up
       c->err.clear();
       break;

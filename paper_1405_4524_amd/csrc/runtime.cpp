@@ -243,6 +243,20 @@ static void free_kop(Ctx* c, KappaOp* k) {
   }
 }
 
+// Free the per-kappa clover fields that no solver references (least recently used first is
+// not needed: everything unreferenced goes).  Returns the number of bytes released.
+size_t Ctx::evict_unused_kops() {
+  const size_t before = used;
+  for (auto& kv : clovers) {
+    auto& v = kv.second->kops;
+    for (auto& k : v)
+      if (k->refs <= 0) free_kop(this, k.get());
+    v.erase(std::remove_if(v.begin(), v.end(), [](const std::unique_ptr<KappaOp>& k) { return k->refs <= 0; }),
+            v.end());
+  }
+  return before - used;
+}
+
 // A(kappa), A^{-1}(kappa) for a clover field, FP64 always and `prec` on demand; cached.
 int Ctx::kappa_op(CloverField* cf, double kappa, int prec, KappaOp** out) {
   KappaOp* k = nullptr;
@@ -358,8 +372,31 @@ static int upload(Ctx* c, void* dst, const void* src, size_t n) {
   return c->sync();
 }
 
+// Drop operators no live slot uses (their per-kappa clover may then be evicted).
+void Solver::gc_ops() {
+  std::vector<int> used(ops.size(), 0);
+  for (Slot* s : live) used[s->op] = 1;
+  bool all = true;
+  for (int u : used) all = all && u;
+  if (all) return;
+  std::vector<int> remap(ops.size(), -1);
+  std::vector<OpEntry> keep;
+  for (size_t i = 0; i < ops.size(); ++i) {
+    if (used[i]) {
+      remap[i] = (int)keep.size();
+      keep.push_back(ops[i]);
+    } else if (ops[i].kop) {
+      ops[i].kop->refs--;
+    }
+  }
+  for (Slot* s : live) s->op = remap[s->op];
+  ops.swap(keep);
+  dirty = true;
+}
+
 int Solver::rebuild() {
   if (!dirty) return A2A_OK;
+  gc_ops();
   // ops and slots
   A2A_TRY(grow(ctx, (void**)&d_ops, &cap_ops, sizeof(OpDev) * std::max<size_t>(1, ops.size())));
   std::vector<OpDev> hops(ops.size());

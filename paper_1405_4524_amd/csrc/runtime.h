@@ -119,6 +119,7 @@ struct Solver {
   ~Solver();
   int op_index(int clover_h, double kappa, KappaOp* kop, const GaugeField* gf);
   int add_slot(Slot* s);
+  void gc_ops();
   int rebuild();
   // subset helpers (indices into live)
   int upload_subset(const std::vector<int>& idx, int R_sub);
@@ -159,10 +160,13 @@ struct Ctx {
   // options
   int rhs_block = 4;
   int check_every = 4;
-  double delta_lo = 0.01, delta_64 = 1e-3;
+  double delta_lo = 0.1, delta_64 = 1e-3;
   int xcd_order = 1;
   int timing = 0;
   int debug = 0;  // A2A_DEBUG=1 in the environment: residual trace on stderr
+  int autotune = 0;                  // pick the stencil RHS-block width per workload
+  std::map<std::string, int> tuned;  // tune key -> RHS-block width
+  std::string tune_path;             // A2A_TUNE_CACHE: JSON file of tuned widths
   // reduction scratch
   double* scal_pool = nullptr;
   double* scal_host = nullptr;
@@ -216,6 +220,7 @@ struct Ctx {
   }
   int gauge_links(GaugeField* gf, int prec, void** out0, void** out1);
   int kappa_op(CloverField* cf, double kappa, int prec, KappaOp** out);
+  size_t evict_unused_kops();
   int timing_begin(int cls, hipEvent_t* a);
   int timing_end(int cls, hipEvent_t a, double alg_bytes);
   int timing_collect();

@@ -52,6 +52,25 @@ def test_batch_equals_alone(ctx, orc, fields):
         assert np.linalg.norm(r) / np.linalg.norm(eta[i]) <= 1e-10
 
 
+def test_autotune_picks_a_width_and_solves(ctx, orc, fields):
+    f = fields[1]
+    print("[gpu] autotune", flush=True)
+    best, ms = ctx.autotune(f["c"], 0.125, 2, 6)
+    assert best in (1, 2, 4) and set(ms) == {1, 2, 4} and all(v > 0 for v in ms.values())
+    assert ms[best] == min(ms.values())
+    ctx.set_option("autotune", 1)
+    try:
+        eta = inputs.z2_noise(f["dims"], 6, seed=31)
+        X, info, rc = ctx.solve_propagators(f["c"], eta, 0.125, 1.5, tol=1e-10, prec=2)
+    finally:
+        ctx.set_option("autotune", 0)
+    assert rc == 0
+    A = orc.clover(f["U"], 0.125, 1.5)
+    for i in range(6):
+        r = eta[i] - orc.apply_D(f["U"], A, 0.125, X[i], -1)
+        assert np.linalg.norm(r) / np.linalg.norm(eta[i]) <= 1e-10
+
+
 def test_engine_mixed_stream_matches_alone(ctx, orc, fields):
     import torch
 
