@@ -100,8 +100,10 @@ int a2a_init(a2a_ctx **ctx, int device, size_t hbm_budget_bytes, void *hip_strea
 int a2a_finalize(a2a_ctx *ctx);
 /* Message for the last failed call on ctx (never NULL; empty after success). */
 const char *a2a_last_error(const a2a_ctx *ctx);
-/* Tuning knobs: "rhs_block" (1, 2, 4: RHS per thread in the stencil), "check_every"
- * (iterations between residual checks), "delta" (reliable-update reduction factor),
+/* Tuning knobs: "rhs_block" (1, 2, 4: RHS per thread in the stencil), "rhs_block64" (1, 2:
+ * RHS per thread in the FP64 stencils of set-up, reliable updates and reconstruction; default
+ * 2), "check_every" (iterations between residual checks), "delta" (reliable-update reduction
+ * factor), "delta64" (the same for the FP64-only mode),
  * "xcd_order" (0/1), "kernel_timing" (0/1), "autotune" (0/1), "hbm_budget" (bytes; resets
  * the budget given at a2a_init).  Returns A2A_EINVAL for an unknown key. */
 int a2a_set_option(a2a_ctx *ctx, const char *key, double value);

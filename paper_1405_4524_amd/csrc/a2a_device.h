@@ -144,6 +144,37 @@ struct Field {
   }
 };
 
+// a spinor of 16-byte chunks at p0 + site*ss + k*cs (any inner layout)
+template <typename S>
+struct StridedSpinor {
+  static constexpr int NCH = 24 * (int)sizeof(S) / 16;
+  template <typename A>
+  HD static void load(const char* p0, long long ss, long long cs, long site, A* r) {
+    S tmp[24];
+    const char* p = p0 + site * ss;
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+      uint4 c = *(const uint4*)(p + k * cs);
+      __builtin_memcpy((char*)tmp + k * 16, &c, 16);
+    }
+#pragma unroll
+    for (int i = 0; i < 24; ++i) r[i] = Conv<S>::template to<A>(tmp[i]);
+  }
+  template <typename A>
+  HD static void store(char* p0, long long ss, long long cs, long site, const A* r) {
+    S tmp[24];
+#pragma unroll
+    for (int i = 0; i < 24; ++i) tmp[i] = Conv<S>::from(r[i]);
+    char* p = p0 + site * ss;
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+      uint4 c;
+      __builtin_memcpy(&c, (const char*)tmp + k * 16, 16);
+      *(uint4*)(p + k * cs) = c;
+    }
+  }
+};
+
 template <typename S> using SpinorF = Field<S, 24>;
 template <typename S> using LinkF = Field<S, 18>;
 // a clover pair is two consecutive 36-real block fields (block 0 then block 1)
@@ -375,6 +406,13 @@ struct OpDev {
 };
 
 // One right-hand side of a batch.
+// Inner vectors are arrays of 16-byte chunks addressed by strides, so that one set of kernels
+// serves both inner layouts:
+//   per slot     chunk k of site i at arena + i*16 + k*hv*16   (plane-major, one slot)
+//   interleaved  [site][tile][chunk][16 lanes] of 16-byte chunks shared by up to 64 slots of a
+//                group; arena points at the slot's lane (tile*768 + lane*16 for 2-byte reals),
+//                site stride = tiles*768, chunk stride = 256.  The inner x of FP16 mode (FP32,
+//                six chunks) uses twice the site stride and an extra offset of tile*768.
 struct SlotDev {
   int op;
   int nblk;              // site blocks of this slot's operator
@@ -382,11 +420,42 @@ struct SlotDev {
   int pad;
   char* arena[2];        // [prec] base of this slot's vectors
   long long vstride[2];  // [prec] bytes between consecutive vectors
+  long long lss, lcs;    // inner vectors: bytes between sites, between chunks of a site
+  long long lss_x, lxoff;  // inner x: site stride and extra offset
   double* scal;          // per-slot scalar block (NSCAL doubles)
   const double* src;     // canonical source (device)
   double* sol;           // canonical solution (device)
   const double* x0;      // canonical initial guess (device) or null
 };
+
+// a vector of one slot in one arena: base of vector 0, site and chunk strides
+struct VView {
+  char* base;
+  long long vs, ss, cs;
+};
+HD VView lo_view(const SlotDev& sd) { return VView{sd.arena[0], sd.vstride[0], sd.lss, sd.lcs}; }
+HD VView hi_view(const SlotDev& sd, long hv) { return VView{sd.arena[1], sd.vstride[1], 16, (long long)hv * 16}; }
+HD VView view_of(const SlotDev& sd, int psel, long hv) { return psel ? hi_view(sd, hv) : lo_view(sd); }
+
+template <typename S, typename A>
+HD void vload(const VView& w, int v, long site, Spinor<A>& s) {
+  StridedSpinor<S>::template load<A>(w.base + (long long)v * w.vs, w.ss, w.cs, site, (A*)s.v);
+}
+template <typename S, typename A>
+HD void vstore(const VView& w, int v, long site, const Spinor<A>& s) {
+  StridedSpinor<S>::template store<A>(w.base + (long long)v * w.vs, w.ss, w.cs, site, (const A*)s.v);
+}
+// the inner iterate x (storage SX) of a slot
+template <typename SX, typename A>
+HD void xload(const SlotDev& sd, int v, long site, Spinor<A>& s) {
+  StridedSpinor<SX>::template load<A>(sd.arena[0] + (long long)v * sd.vstride[0] + sd.lxoff, sd.lss_x, sd.lcs, site,
+                                      (A*)s.v);
+}
+template <typename SX, typename A>
+HD void xstore(const SlotDev& sd, int v, long site, const Spinor<A>& s) {
+  StridedSpinor<SX>::template store<A>(sd.arena[0] + (long long)v * sd.vstride[0] + sd.lxoff, sd.lss_x, sd.lcs, site,
+                                       (const A*)s.v);
+}
 
 // slot scalar block layout (doubles)
 enum {

@@ -48,7 +48,8 @@ enum VecKind {
 struct VecArgs {
   const OpDev* ops;
   const SlotDev* slots;
-  const int2* tiles;
+  const int2* tiles;     // per-slot mapping: {slot, site block}; interleaved: {lane tile, site block}
+  const int* ilslots;    // interleaved mapping: 16 slot indices per lane tile (-1 = idle lane)
   int kind;
   int par;        // parity for VK_CLOVER
   int use_inv;    // VK_CLOVER: 1 -> A^{-1}
@@ -77,6 +78,10 @@ void launch_finalize(int kind, const OpDev* ops, const SlotDev* slots, const int
 
 void launch_hop(int prec, int R, const HopArgs& a, int ntiles, hipStream_t s);
 void launch_vec(int prec, const VecArgs& a, int ntiles, hipStream_t s);
+// the lane-interleaved variant (FP16 / BF16 inner vectors in interleaved groups); kinds that
+// touch inner vectors only
+void launch_vec_il(int prec, const VecArgs& a, int ntiles, hipStream_t s);
+bool vec_kind_il(int kind);
 void launch_layout_in(int prec, const LayoutArgs& a, int ntiles, hipStream_t s);
 void launch_layout_out(int prec, const LayoutArgs& a, int ntiles, hipStream_t s);
 

@@ -46,12 +46,17 @@ int slot_alloc(Ctx* c, Slot* s, int prec, long hv, int nblk, int nlo, int nhi) {
       return rc;
     }
     s->lo = (char*)p;
+    s->lo_alloc = s->lo;
   }
+  s->lss = 16;
+  s->lcs = 16LL * hv;
+  s->lss_x = 16;
+  s->lxoff = 0;
   if (nhi) {
     int rc = c->dalloc(&p, bh * nhi);
     if (rc) {
-      c->dfree(s->lo);
-      s->lo = nullptr;
+      c->dfree(s->lo_alloc);
+      s->lo = s->lo_alloc = nullptr;
       c->free_sid(s->sid);
       s->sid = -1;
       return rc;
@@ -62,11 +67,56 @@ int slot_alloc(Ctx* c, Slot* s, int prec, long hv, int nblk, int nlo, int nhi) {
 }
 
 void slot_free(Ctx* c, Slot* s) {
-  c->dfree(s->lo);
+  c->dfree(s->lo_alloc);
   c->dfree(s->hi);
-  s->lo = s->hi = nullptr;
+  s->lo = s->hi = s->lo_alloc = s->il_base = nullptr;
   if (s->sid >= 0) c->free_sid(s->sid);
   s->sid = -1;
+}
+
+// Interleaved inner layout (FP16 / BF16 storage): consecutive slots form groups of up to 64
+// lanes (tiles of 16) sharing one arena [vector][site][tile][3 chunks][16 lanes] of 16-byte
+// chunks.  Lane 0 of each group owns the arena.  Groups never span calls or requests, so a
+// group's arena is freed together with all of its slots.
+constexpr int IL_MAX = 64;
+
+bool use_interleave(const Ctx* c, int prec) { return c->interleave && (prec == 2 || prec == 3); }
+
+int il_alloc(Ctx* c, Slot* slots, int n, long hv, int nlo) {
+  for (int g0 = 0; g0 < n; g0 += IL_MAX) {
+    const int m = std::min(IL_MAX, n - g0);
+    const int nt = (m + 15) / 16;
+    const size_t vs = ((size_t)hv * nt * 768 + 255) & ~(size_t)255;
+    void* p = nullptr;
+    A2A_TRY(c->dalloc(&p, vs * nlo));
+    for (int j = 0; j < m; ++j) {
+      Slot& s = slots[g0 + j];
+      const int tile = j / 16, lane = j % 16;
+      s.lo = (char*)p + tile * 768 + lane * 16;
+      s.lo_alloc = j == 0 ? (char*)p : nullptr;
+      s.lo_stride = vs;
+      s.lss = 768LL * nt;
+      s.lcs = 256;
+      s.lss_x = 2 * 768LL * nt;
+      s.lxoff = 768LL * tile;
+      s.il_base = (char*)p;
+      s.il_nt = nt;
+      s.il_lane = j;
+    }
+  }
+  return A2A_OK;
+}
+
+// arenas of n slots of one operator: per slot, or interleaved groups for FP16 / BF16
+int slots_alloc(Ctx* c, Slot* slots, int n, int prec, long hv, int nblk, int nlo, int nhi) {
+  const bool il = use_interleave(c, prec);
+  int rc = A2A_OK;
+  int k = 0;
+  for (; k < n && !rc; ++k) rc = slot_alloc(c, &slots[k], prec, hv, nblk, il ? 0 : nlo, nhi);
+  if (!rc && il && nlo) rc = il_alloc(c, slots, n, hv, nlo);
+  if (rc)
+    for (int j = 0; j < k; ++j) slot_free(c, &slots[j]);
+  return rc;
 }
 
 int effective_R(Ctx* c, int prec) {
@@ -121,8 +171,8 @@ int solve_core(Ctx* c, int clover_h, const double* src, int nrhs, double kappa, 
     s.tol = tol;
     s.max_iter = max_iter;
     s.t_submit = t0;
-    rc = slot_alloc(c, &s, prec, hv, sv.ops[op].nblk, NVEC_LO, NVEC_HI);
   }
+  rc = slots_alloc(c, slots.data(), nrhs, prec, hv, sv.ops[op].nblk, NVEC_LO, NVEC_HI);
   if (!rc) {
     std::vector<int> idx;
     for (int i = 0; i < nrhs; ++i) {
@@ -178,9 +228,10 @@ int dslash_core(Ctx* c, int clover_h, double kappa, int opk, int dagger, int pre
     s.op = op;
     s.src = in + (size_t)i * 24 * V;
     s.sol = out + (size_t)i * 24 * V;
-    rc = slot_alloc(c, &s, prec, hv, sv.ops[op].nblk, 5, 0);
-    if (!rc) sv.add_slot(&s);
   }
+  rc = slots_alloc(c, slots.data(), nrhs, prec, hv, sv.ops[op].nblk, 5, 0);
+  if (!rc)
+    for (auto& s : slots) sv.add_slot(&s);
   if (!rc) rc = sv.rebuild();
   if (!rc) {
     const int H = sv.n_hop_tiles, Vn = sv.n_vec_tiles, R = sv.R;
@@ -342,6 +393,10 @@ extern "C" int a2a_set_option(a2a_ctx* h, const char* key, double v) {
     int r = (int)v;
     if (r != 1 && r != 2 && r != 4) return c->fail(A2A_EINVAL, "rhs_block must be 1, 2 or 4");
     c->rhs_block = r;
+  } else if (k == "rhs_block64") {
+    int r = (int)v;
+    if (r != 1 && r != 2) return c->fail(A2A_EINVAL, "rhs_block64 must be 1 or 2");
+    c->rhs_block64 = r;
   } else if (k == "check_every") {
     if (v < 1) return c->fail(A2A_EINVAL, "check_every must be >= 1");
     c->check_every = (int)v;
@@ -357,6 +412,8 @@ extern "C" int a2a_set_option(a2a_ctx* h, const char* key, double v) {
     c->timing = v != 0;
   } else if (k == "autotune") {
     c->autotune = v != 0;
+  } else if (k == "interleave") {
+    c->interleave = v != 0;
   } else if (k == "hbm_budget") {
     if (!(v > 0)) return c->fail(A2A_EINVAL, "hbm_budget must be positive");
     c->budget = (size_t)v;
@@ -527,11 +584,10 @@ static int stencil_time(Ctx* c, int clover_h, double kappa, int opk, int prec, i
   const int op = sv.op_index(clover_h, kappa, kop, gf);
   std::vector<Slot> slots(nrhs);
   int rc = A2A_OK;
-  for (int i = 0; i < nrhs && !rc; ++i) {
-    slots[i].op = op;
-    rc = slot_alloc(c, &slots[i], prec, gf->g.hv, sv.ops[op].nblk, 5, 0);
-    if (!rc) sv.add_slot(&slots[i]);
-  }
+  for (int i = 0; i < nrhs; ++i) slots[i].op = op;
+  rc = slots_alloc(c, slots.data(), nrhs, prec, gf->g.hv, sv.ops[op].nblk, 5, 0);
+  if (!rc)
+    for (auto& s : slots) sv.add_slot(&s);
   if (!rc) rc = sv.rebuild();
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (!rc) {
@@ -942,12 +998,11 @@ static int engine_admit(a2a_engine* e, Request* r) {
     s.t_submit = r->t_submit;
     s.req = r->ticket;
     s.req_idx = i;
-    rc = slot_alloc(c, &s, r->prec, gf->g.hv, sv->ops[op].nblk, NVEC_LO, NVEC_HI);
-    if (rc) {
-      for (int j = 0; j <= i; ++j) slot_free(c, &r->slots[j]);
-      r->slots.clear();
-      return rc;
-    }
+  }
+  rc = slots_alloc(c, r->slots.data(), r->nsrc, r->prec, gf->g.hv, sv->ops[op].nblk, NVEC_LO, NVEC_HI);
+  if (rc) {
+    r->slots.clear();
+    return rc;
   }
   e->active += r->nsrc;
   std::vector<int> idx;

@@ -28,72 +28,63 @@ __device__ __forceinline__ void dot3(const Spinor<A>& a, const Spinor<A>& b, dou
   }
 }
 
+// kinds whose result feeds a reduction
+template <int KIND>
+struct VecRed {
+  static constexpr bool on = KIND == VK_BICG_XR || KIND == VK_RU_RESCALE || KIND == VK_INIT;
+};
+
+// One site of one slot.  Reducing kinds add their (rhat, r), |r|^2 contributions to v3.
 template <class P, int KIND>
-__global__ __launch_bounds__(BS) void k_vec(VecArgs a) {
+__device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, int hv, int site, double (&v3)[3]) {
   using S = typename P::S;
   using SX = typename P::SX;
   using A = typename P::A;
-  const int2 tile = a.tiles[blockIdx.x];
-  const SlotDev& sd = a.slots[tile.x];
-  const int hv = a.ops[sd.op].g.hv;
-  const int site = tile.y * BS + (int)threadIdx.x;
-  const bool valid = site < hv;
-  char* lo = sd.arena[0];
+  const VView lw = lo_view(sd);
   char* hi = sd.arena[1];
-  const long long vl = sd.vstride[0], vh = sd.vstride[1];
+  const long long vh = sd.vstride[1];
   const double* sc = sd.scal;
-#define LO(v) (lo + (size_t)(v) * vl)
 #define HI(v) (hi + (size_t)(v) * vh)
-
   if (KIND == VK_BICG_S) {  // s = r - alpha v
-    if (!valid) return;
     const cx<A> al = scal_c<A>(sc, SC_ALPHA);
     Spinor<A> r, v;
-    load_spinor<S, A>(LO(VL_R), hv, site, r);
-    load_spinor<S, A>(LO(VL_V), hv, site, v);
+    vload<S, A>(lw, VL_R, site, r);
+    vload<S, A>(lw, VL_V, site, v);
 #pragma unroll
     for (int k = 0; k < 12; ++k) r.v[k] = r.v[k] - al * v.v[k];
-    store_spinor<S, A>(LO(VL_S), hv, site, r);
+    vstore<S, A>(lw, VL_S, site, r);
   } else if (KIND == VK_BICG_P) {  // p = r + beta (p - omega v)
-    if (!valid) return;
     const cx<A> be = scal_c<A>(sc, SC_BETA), om = scal_c<A>(sc, SC_OMEGA);
     Spinor<A> r, p, v;
-    load_spinor<S, A>(LO(VL_R), hv, site, r);
-    load_spinor<S, A>(LO(VL_P), hv, site, p);
-    load_spinor<S, A>(LO(VL_V), hv, site, v);
+    vload<S, A>(lw, VL_R, site, r);
+    vload<S, A>(lw, VL_P, site, p);
+    vload<S, A>(lw, VL_V, site, v);
 #pragma unroll
     for (int k = 0; k < 12; ++k) p.v[k] = r.v[k] + be * (p.v[k] - om * v.v[k]);
-    store_spinor<S, A>(LO(VL_P), hv, site, p);
+    vstore<S, A>(lw, VL_P, site, p);
   } else if (KIND == VK_BICG_XR) {  // x += alpha p + omega s; r = s - omega t; (rhat, r), |r|^2
-    double v3[3] = {0.0, 0.0, 0.0};
-    if (valid) {
-      const cx<A> al = scal_c<A>(sc, SC_ALPHA), om = scal_c<A>(sc, SC_OMEGA);
-      Spinor<A> x, p, s, t;
-      load_spinor<SX, A>(LO(VL_X), hv, site, x);
-      load_spinor<S, A>(LO(VL_P), hv, site, p);
-      load_spinor<S, A>(LO(VL_S), hv, site, s);
-      load_spinor<S, A>(LO(VL_T), hv, site, t);
+    const cx<A> al = scal_c<A>(sc, SC_ALPHA), om = scal_c<A>(sc, SC_OMEGA);
+    Spinor<A> x, p, s, t;
+    xload<SX, A>(sd, VL_X, site, x);
+    vload<S, A>(lw, VL_P, site, p);
+    vload<S, A>(lw, VL_S, site, s);
+    vload<S, A>(lw, VL_T, site, t);
 #pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        x.v[k] = x.v[k] + al * p.v[k] + om * s.v[k];
-        s.v[k] = s.v[k] - om * t.v[k];
-      }
-      store_spinor<SX, A>(LO(VL_X), hv, site, x);
-      store_spinor<S, A>(LO(VL_R), hv, site, s);
-      load_spinor<S, A>(LO(VL_R), hv, site, s);  // reduce the stored values
-      Spinor<A> rh;
-      load_spinor<S, A>(LO(VL_RHAT), hv, site, rh);
-      dot3(rh, s, v3);
+    for (int k = 0; k < 12; ++k) {
+      x.v[k] = x.v[k] + al * p.v[k] + om * s.v[k];
+      s.v[k] = s.v[k] - om * t.v[k];
     }
-    block_sum_n<3, BS>(v3);
-    if (threadIdx.x < 3)
-      store_partial(a.rb, sd.sid, tile.y, threadIdx.x, threadIdx.x == 0 ? v3[0] : threadIdx.x == 1 ? v3[1] : v3[2]);
+    xstore<SX, A>(sd, VL_X, site, x);
+    vstore<S, A>(lw, VL_R, site, s);
+    vload<S, A>(lw, VL_R, site, s);  // reduce the stored values
+    Spinor<A> rh;
+    vload<S, A>(lw, VL_RHAT, site, rh);
+    dot3(rh, s, v3);
   } else if (KIND == VK_RU_ACCUM) {  // x64 += sigma x_lo; x_lo = 0
-    if (!valid) return;
     const double sg = sc[SC_SIGMA];
     Spinor<A> xl;
     Spinor<double> xh;
-    load_spinor<SX, A>(LO(VL_X), hv, site, xl);
+    xload<SX, A>(sd, VL_X, site, xl);
     load_spinor<double, double>(HI(VH_X), hv, site, xh);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -102,51 +93,44 @@ __global__ __launch_bounds__(BS) void k_vec(VecArgs a) {
       xl.v[k] = mk((A)0, (A)0);
     }
     store_spinor<double, double>(HI(VH_X), hv, site, xh);
-    store_spinor<SX, A>(LO(VL_X), hv, site, xl);
+    xstore<SX, A>(sd, VL_X, site, xl);
   } else if (KIND == VK_RU_RESCALE || KIND == VK_INIT) {
-    double v3[3] = {0.0, 0.0, 0.0};
     const double snew =
         KIND == VK_INIT ? sqrt(sc[SC_R64N2] / (12.0 * hv)) : ru_scale(sc[SC_R64N2], sc[SC_SIGMA], hv);
     const double inv = (snew > 0.0) ? 1.0 / snew : 0.0;
-    if (valid) {
-      Spinor<double> rh64;
-      load_spinor<double, double>(HI(VH_R), hv, site, rh64);
-      Spinor<A> r;
+    Spinor<double> rh64;
+    load_spinor<double, double>(HI(VH_R), hv, site, rh64);
+    Spinor<A> r;
 #pragma unroll
-      for (int k = 0; k < 12; ++k) r.v[k] = mk((A)(rh64.v[k].re * inv), (A)(rh64.v[k].im * inv));
-      store_spinor<S, A>(LO(VL_R), hv, site, r);
-      load_spinor<S, A>(LO(VL_R), hv, site, r);
-      Spinor<A> rh;
-      if (KIND == VK_INIT) {
-        Spinor<A> z;
+    for (int k = 0; k < 12; ++k) r.v[k] = mk((A)(rh64.v[k].re * inv), (A)(rh64.v[k].im * inv));
+    vstore<S, A>(lw, VL_R, site, r);
+    vload<S, A>(lw, VL_R, site, r);
+    Spinor<A> rh;
+    if (KIND == VK_INIT) {
+      Spinor<A> z;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) z.v[k] = mk((A)0, (A)0);
-        store_spinor<S, A>(LO(VL_RHAT), hv, site, r);
-        store_spinor<S, A>(LO(VL_P), hv, site, r);
-        store_spinor<S, A>(LO(VL_V), hv, site, z);
-        store_spinor<SX, A>(LO(VL_X), hv, site, z);
-        rh = r;
-      } else {
-        const A ratio = (A)(sc[SC_SIGMA] * inv);
-        Spinor<A> p, v;
-        load_spinor<S, A>(LO(VL_P), hv, site, p);
-        load_spinor<S, A>(LO(VL_V), hv, site, v);
+      for (int k = 0; k < 12; ++k) z.v[k] = mk((A)0, (A)0);
+      vstore<S, A>(lw, VL_RHAT, site, r);
+      vstore<S, A>(lw, VL_P, site, r);
+      vstore<S, A>(lw, VL_V, site, z);
+      xstore<SX, A>(sd, VL_X, site, z);
+      rh = r;
+    } else {
+      const A ratio = (A)(sc[SC_SIGMA] * inv);
+      Spinor<A> p, v;
+      vload<S, A>(lw, VL_P, site, p);
+      vload<S, A>(lw, VL_V, site, v);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          p.v[k] = ratio * p.v[k];
-          v.v[k] = ratio * v.v[k];
-        }
-        store_spinor<S, A>(LO(VL_P), hv, site, p);
-        store_spinor<S, A>(LO(VL_V), hv, site, v);
-        load_spinor<S, A>(LO(VL_RHAT), hv, site, rh);
+      for (int k = 0; k < 12; ++k) {
+        p.v[k] = ratio * p.v[k];
+        v.v[k] = ratio * v.v[k];
       }
-      dot3(rh, r, v3);
+      vstore<S, A>(lw, VL_P, site, p);
+      vstore<S, A>(lw, VL_V, site, v);
+      vload<S, A>(lw, VL_RHAT, site, rh);
     }
-    block_sum_n<3, BS>(v3);
-    if (threadIdx.x < 3)
-      store_partial(a.rb, sd.sid, tile.y, threadIdx.x, threadIdx.x == 0 ? v3[0] : threadIdx.x == 1 ? v3[1] : v3[2]);
+    dot3(rh, r, v3);
   } else if (KIND == VK_CLOVER) {  // FP64: hi[vout] = C hi[vin], C = A or A^{-1} of parity par
-    if (!valid) return;
     const OpDev& op = a.ops[sd.op];
     const void* C = a.use_inv ? op.Ai[1][a.par] : op.A[1][a.par];
     Spinor<double> in, out;
@@ -154,19 +138,16 @@ __global__ __launch_bounds__(BS) void k_vec(VecArgs a) {
     clover_apply_mem<double, double>(C, hv, site, in, out);
     store_spinor<double, double>(HI(a.vout), hv, site, out);
   } else if (KIND == VK_ZERO_X) {
-    if (!valid) return;
     Spinor<A> z;
 #pragma unroll
     for (int k = 0; k < 12; ++k) z.v[k] = mk((A)0, (A)0);
-    store_spinor<SX, A>(LO(VL_X), hv, site, z);
+    xstore<SX, A>(sd, VL_X, site, z);
   } else if (KIND == VK_ZERO_HI) {
-    if (!valid) return;
     Spinor<double> z;
 #pragma unroll
     for (int k = 0; k < 12; ++k) z.v[k] = mk(0.0, 0.0);
     store_spinor<double, double>(HI(a.vout), hv, site, z);
   } else if (KIND == VK_ZERO_LO || KIND == VK_FILL_LO) {
-    if (!valid) return;
     Spinor<A> z;
     uint32_t h = (uint32_t)site * 2654435761u + (uint32_t)sd.sid * 40503u + 12345u;
 #pragma unroll
@@ -181,10 +162,99 @@ __global__ __launch_bounds__(BS) void k_vec(VecArgs a) {
         z.v[k] = mk(re, im);
       }
     }
-    store_spinor<S, A>(LO(a.vout), hv, site, z);
+    vstore<S, A>(lw, a.vout, site, z);
   }
-#undef LO
 #undef HI
+}
+
+// per-slot mapping: tiles {slot, block of BS sites}, one site per thread
+template <class P, int KIND>
+__global__ __launch_bounds__(BS) void k_vec(VecArgs a) {
+  const int2 tile = a.tiles[blockIdx.x];
+  const SlotDev& sd = a.slots[tile.x];
+  const int hv = a.ops[sd.op].g.hv;
+  const int site = tile.y * BS + (int)threadIdx.x;
+  double v3[3] = {0.0, 0.0, 0.0};
+  if (site < hv) vec_site<P, KIND>(a, sd, hv, site, v3);
+  if (VecRed<KIND>::on) {
+    block_sum_n<3, BS>(v3);
+    if (threadIdx.x < 3)
+      store_partial(a.rb, sd.sid, tile.y, threadIdx.x, threadIdx.x == 0 ? v3[0] : threadIdx.x == 1 ? v3[1] : v3[2]);
+  }
+}
+
+// interleaved mapping: tiles {16-lane group tile, block of BS sites}; thread (lane n, row q)
+// visits sites block*BS + 16 i + q, so a wave touches 4 sites x 16 lanes = 4 contiguous
+// 256-byte runs per chunk.  Reductions are per lane (slot) and land in the same partial
+// slots as the per-slot mapping (block index = site block of BS sites).
+template <class P, int KIND>
+__global__ __launch_bounds__(BS) void k_vec_il(VecArgs a) {
+  const int2 tile = a.tiles[blockIdx.x];
+  const int n = threadIdx.x & 15, q = threadIdx.x >> 4;
+  const int slot = a.ilslots[tile.x * 16 + n];
+  double v3[3] = {0.0, 0.0, 0.0};
+  if (slot >= 0) {
+    const SlotDev& sd = a.slots[slot];
+    const int hv = a.ops[sd.op].g.hv;
+    for (int i = 0; i < BS / 16; ++i) {
+      const int site = tile.y * BS + 16 * i + q;
+      if (site < hv) vec_site<P, KIND>(a, sd, hv, site, v3);
+    }
+  }
+  if (VecRed<KIND>::on) {
+    __shared__ double red[BS / 64][16][3];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      v3[k] += __shfl_xor(v3[k], 16, 64);
+      v3[k] += __shfl_xor(v3[k], 32, 64);
+    }
+    if (lane < 16)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) red[w][lane][k] = v3[k];
+    __syncthreads();
+    if (threadIdx.x < 48) {
+      const int m = threadIdx.x & 15, k = threadIdx.x >> 4;
+      const int sl = a.ilslots[tile.x * 16 + m];
+      if (sl >= 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < BS / 64; ++j) t += red[j][m][k];
+        store_partial(a.rb, a.slots[sl].sid, tile.y, k, t);
+      }
+    }
+  }
+}
+
+template <class P>
+static void launch_vec_il_p(const VecArgs& a, int n, hipStream_t s) {
+  const dim3 g(n), b(BS);
+  switch (a.kind) {
+    case VK_BICG_S: hipLaunchKernelGGL((k_vec_il<P, VK_BICG_S>), g, b, 0, s, a); break;
+    case VK_BICG_XR: hipLaunchKernelGGL((k_vec_il<P, VK_BICG_XR>), g, b, 0, s, a); break;
+    case VK_BICG_P: hipLaunchKernelGGL((k_vec_il<P, VK_BICG_P>), g, b, 0, s, a); break;
+    case VK_RU_ACCUM: hipLaunchKernelGGL((k_vec_il<P, VK_RU_ACCUM>), g, b, 0, s, a); break;
+    case VK_RU_RESCALE: hipLaunchKernelGGL((k_vec_il<P, VK_RU_RESCALE>), g, b, 0, s, a); break;
+    case VK_INIT: hipLaunchKernelGGL((k_vec_il<P, VK_INIT>), g, b, 0, s, a); break;
+    case VK_ZERO_X: hipLaunchKernelGGL((k_vec_il<P, VK_ZERO_X>), g, b, 0, s, a); break;
+    case VK_ZERO_LO: hipLaunchKernelGGL((k_vec_il<P, VK_ZERO_LO>), g, b, 0, s, a); break;
+    case VK_FILL_LO: hipLaunchKernelGGL((k_vec_il<P, VK_FILL_LO>), g, b, 0, s, a); break;
+    default: break;
+  }
+}
+
+bool vec_kind_il(int kind) {
+  return kind == VK_BICG_S || kind == VK_BICG_XR || kind == VK_BICG_P || kind == VK_RU_ACCUM ||
+         kind == VK_RU_RESCALE || kind == VK_INIT || kind == VK_ZERO_X || kind == VK_ZERO_LO || kind == VK_FILL_LO;
+}
+
+void launch_vec_il(int prec, const VecArgs& a, int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return;
+  switch (prec) {
+    case 2: launch_vec_il_p<PrecF16>(a, ntiles, s); break;
+    case 3: launch_vec_il_p<PrecB16>(a, ntiles, s); break;
+    default: break;
+  }
 }
 
 template <class P>
@@ -255,8 +325,7 @@ __global__ __launch_bounds__(BS) void k_layout_in(LayoutArgs a) {
   double nn[1] = {0.0};
   if (site < hv) {
     const double* src = a.which_in ? sd.x0 : sd.src;
-    char* base = sd.arena[a.psel];
-    const long long vs = sd.vstride[a.psel];
+    const VView w = view_of(sd, a.psel, hv);
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
       int c[4];
@@ -270,7 +339,7 @@ __global__ __launch_bounds__(BS) void k_layout_in(LayoutArgs a) {
         double sgn = (a.gamma5 && k >= 6) ? -1.0 : 1.0;
         s.v[k] = mk((A)(sgn * re), (A)(sgn * im));
       }
-      store_spinor<S, A>(base + (size_t)(par ? a.v_odd : a.v_even) * vs, hv, site, s);
+      vstore<S, A>(w, par ? a.v_odd : a.v_even, site, s);
     }
   }
   if (a.red != RED_NONE) {
@@ -290,15 +359,14 @@ __global__ __launch_bounds__(BS) void k_layout_out(LayoutArgs a) {
   const int site = tile.y * BS + (int)threadIdx.x;
   if (site >= hv) return;
   double* dst = sd.sol;
-  const char* base = sd.arena[a.psel];
-  const long long vs = sd.vstride[a.psel];
+  const VView w = view_of(sd, a.psel, hv);
 #pragma unroll
   for (int par = 0; par < 2; ++par) {
     int c[4];
     cb_coords(g, site, par, c);
     double* p = dst + lex_index(g, c) * 24;
     Spinor<A> s;
-    load_spinor<S, A>(base + (size_t)(par ? a.v_odd : a.v_even) * vs, hv, site, s);
+    vload<S, A>(w, par ? a.v_odd : a.v_even, site, s);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       double sgn = (a.gamma5 && k >= 6) ? -1.0 : 1.0;

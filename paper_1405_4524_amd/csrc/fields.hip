@@ -45,6 +45,91 @@ void launch_gauge_to_eo(int prec, const Geo& g, const double* canon, void* const
 }
 
 // ------------------------------------------------------------------------------------
+// per-site hop links for the matrix-core stencil
+// ------------------------------------------------------------------------------------
+// For every site x of parity par, the eight 3x3 colour matrices that multiply the
+// neighbour spinors of the hopping term, d = 2 mu + f:
+//   f = 0:  U_mu(x)            times the boundary sign if x + mu wraps in t
+//   f = 1:  U_mu(x - mu)^dag   times the boundary sign if x - mu wraps in t
+// stored as [site][d][a][b] complex pairs of the storage format (288 B per site in 16 bits).
+template <class P>
+__global__ __launch_bounds__(BS) void k_hop_links(Geo g, const double* canon, int par, void* dst) {
+  using S = typename P::S;
+  const int site = blockIdx.x * BS + threadIdx.x;
+  if (site >= g.hv) return;
+  int c[4];
+  cb_coords(g, site, par, c);
+  S* out = (S*)dst + (size_t)site * 144;
+  const long lx = lex_index(g, c);
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    const double* f = canon + (lx * 4 + mu) * 18;
+    const double sf = (mu == 3 && c[3] == g.T - 1) ? (double)g.tbc : 1.0;
+    int cb[4] = {c[0], c[1], c[2], c[3]};
+    const int L = mu == 0 ? g.X : mu == 1 ? g.Y : mu == 2 ? g.Z : g.T;
+    cb[mu] = c[mu] == 0 ? L - 1 : c[mu] - 1;
+    const double* bk = canon + (lex_index(g, cb) * 4 + mu) * 18;
+    const double sb = (mu == 3 && c[3] == 0) ? (double)g.tbc : 1.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        S* o0 = out + ((2 * mu) * 9 + a * 3 + b) * 2;
+        o0[0] = Conv<S>::from(sf * f[(a * 3 + b) * 2]);
+        o0[1] = Conv<S>::from(sf * f[(a * 3 + b) * 2 + 1]);
+        S* o1 = out + ((2 * mu + 1) * 9 + a * 3 + b) * 2;  // (U^dag)_ab = conj(U_ba)
+        o1[0] = Conv<S>::from(sb * bk[(b * 3 + a) * 2]);
+        o1[1] = Conv<S>::from(-sb * bk[(b * 3 + a) * 2 + 1]);
+      }
+  }
+}
+
+void launch_hop_links(int prec, const Geo& g, const double* canon, int par, void* dst, hipStream_t s) {
+  dim3 grid((g.hv + BS - 1) / BS);
+  if (prec == 2) hipLaunchKernelGGL(k_hop_links<PrecF16>, grid, dim3(BS), 0, s, g, canon, par, dst);
+  if (prec == 3) hipLaunchKernelGGL(k_hop_links<PrecB16>, grid, dim3(BS), 0, s, g, canon, par, dst);
+}
+
+// packed FP64 clover blocks -> full 6x6 complex blocks [site][block][i][j] in the storage format
+template <class P>
+__global__ __launch_bounds__(BS) void k_clover_full(long hv, const double* packed, void* dst) {
+  using S = typename P::S;
+  const long site = (long)blockIdx.x * BS + threadIdx.x;
+  if (site >= hv) return;
+  S* out = (S*)dst + site * 144;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    double blk[36];
+    CloverBlkF<double>::template load<double>((const char*)packed + b * CloverBlkF<double>::bytes(hv), hv, site, blk);
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        double re, im;
+        if (i == j) {
+          re = blk[i];
+          im = 0.0;
+        } else if (i > j) {
+          re = blk[tri_off(i, j)];
+          im = blk[tri_off(i, j) + 1];
+        } else {
+          re = blk[tri_off(j, i)];
+          im = -blk[tri_off(j, i) + 1];
+        }
+        S* o = out + ((b * 6 + i) * 6 + j) * 2;
+        o[0] = Conv<S>::from(re);
+        o[1] = Conv<S>::from(im);
+      }
+  }
+}
+
+void launch_clover_full(int prec, long hv, const double* packed, void* dst, hipStream_t s) {
+  dim3 grid((unsigned)((hv + BS - 1) / BS));
+  if (prec == 2) hipLaunchKernelGGL(k_clover_full<PrecF16>, grid, dim3(BS), 0, s, hv, packed, dst);
+  if (prec == 3) hipLaunchKernelGGL(k_clover_full<PrecB16>, grid, dim3(BS), 0, s, hv, packed, dst);
+}
+
+// ------------------------------------------------------------------------------------
 // clover field
 // ------------------------------------------------------------------------------------
 struct M3 {

@@ -27,16 +27,13 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
   const int sel = a.psel;
   const int po = a.out_par, pi = 1 - po;
 
-  const char* base[R];
-  long long vs[R];
+  VView w[R];
   bool on[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     int sl = grp[r];
     on[r] = sl >= 0;
-    const SlotDev& sd = a.slots[on[r] ? sl : slot0];
-    base[r] = sd.arena[sel];
-    vs[r] = sd.vstride[sel];
+    w[r] = view_of(a.slots[on[r] ? sl : slot0], sel, hv);
   }
 
   Spinor<A> acc[R];
@@ -62,7 +59,7 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
         for (int r = 0; r < R; ++r) {
           if (!on[r]) continue;
           Spinor<A> p;
-          load_spinor<S, A>(base[r] + (size_t)a.vin * vs[r], hv, nf, p);
+          vload<S, A>(w[r], a.vin, nf, p);
           cx<A> h[6], uh[6];
           project(mu, 1, p, h);
           su3_mul_half(U, h, uh);
@@ -78,7 +75,7 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
         for (int r = 0; r < R; ++r) {
           if (!on[r]) continue;
           Spinor<A> p;
-          load_spinor<S, A>(base[r] + (size_t)a.vin * vs[r], hv, nb, p);
+          vload<S, A>(w[r], a.vin, nb, p);
           cx<A> h[6], uh[6];
           project(mu, 0, p, h);
           su3_dag_mul_half(U, h, uh);
@@ -101,7 +98,7 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
       for (int k = 0; k < 12; ++k) acc[r].v[k] = gam * acc[r].v[k];
       if (a.vaux1 >= 0) {
         Spinor<A> x1;
-        load_spinor<S, A>(base[r] + (size_t)a.vaux1 * vs[r], hv, site, x1);
+        vload<S, A>(w[r], a.vaux1, site, x1);
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[r].v[k] = acc[r].v[k] + ca * x1.v[k];
       }
@@ -118,7 +115,7 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
           cx<A> i6[6], o6[6];
           if (EPI == EPI_CLOV) {
             Spinor<A> x2;
-            load_spinor<S, A>(base[r] + (size_t)a.vaux2 * vs[r], hv, site, x2);
+            vload<S, A>(w[r], a.vaux2, site, x2);
 #pragma unroll
             for (int k = 0; k < 6; ++k) i6[k] = x2.v[b * 6 + k];
             clover_apply_block(blk, i6, o6);
@@ -136,7 +133,7 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
     }
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (on[r]) store_spinor<S, A>((char*)base[r] + (size_t)a.vout * vs[r], hv, site, acc[r]);
+      if (on[r]) vstore<S, A>(w[r], a.vout, site, acc[r]);
   }
 
   // ---- reductions over the values as stored: one block partial per slot of the group
@@ -148,10 +145,10 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
   for (int r = 0; r < R; ++r) {
     if (!valid || !on[r]) continue;
     Spinor<A> o;
-    load_spinor<S, A>(base[r] + (size_t)a.vout * vs[r], hv, site, o);
+    vload<S, A>(w[r], a.vout, site, o);
     if (a.red == RED_ALPHA) {  // (rhat, o)
       Spinor<A> rh;
-      load_spinor<S, A>(base[r] + (size_t)a.vrhat * vs[r], hv, site, rh);
+      vload<S, A>(w[r], a.vrhat, site, rh);
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
         v[r * 3 + 0] += (double)rh.v[k].re * o.v[k].re + (double)rh.v[k].im * o.v[k].im;
@@ -159,7 +156,7 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
       }
     } else if (a.red == RED_OMEGA) {  // (o, aux2), |o|^2
       Spinor<A> x2;
-      load_spinor<S, A>(base[r] + (size_t)a.vaux2 * vs[r], hv, site, x2);
+      vload<S, A>(w[r], a.vaux2, site, x2);
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
         v[r * 3 + 0] += (double)o.v[k].re * x2.v[k].re + (double)o.v[k].im * x2.v[k].im;

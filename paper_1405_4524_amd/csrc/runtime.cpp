@@ -311,6 +311,8 @@ int Ctx::kappa_op(CloverField* cf, double kappa, int prec, KappaOp** out) {
 // ------------------------------------------------------------------------------------------
 // Solver
 // ------------------------------------------------------------------------------------------
+Solver::Solver(Ctx* c, int p, int r) : ctx(c), prec(p), R(r), R64(c->rhs_block64 == 1 ? 1 : 2) {}
+
 Solver::~Solver() {
   ctx->dfree(d_ops);
   ctx->dfree(d_slots);
@@ -320,6 +322,10 @@ Solver::~Solver() {
   ctx->dfree(d_sub_groups);
   ctx->dfree(d_sub_tiles);
   ctx->dfree(d_sub_list);
+  ctx->dfree(d_vec_nonil);
+  ctx->dfree(d_il_slots);
+  ctx->dfree(d_il_tiles);
+  ctx->dfree(d_sub_il_slots);
   for (auto& o : ops)
     if (o.kop) o.kop->refs--;
 }
@@ -394,6 +400,48 @@ void Solver::gc_ops() {
   dirty = true;
 }
 
+// Vector-kernel tile lists for the slots idx (indices into live): per-slot tiles of every
+// slot, per-slot tiles of the slots outside interleaved groups, and the interleaved lane
+// tiles (16 lanes of one group tile) with their site blocks.
+static void vec_lists(const std::vector<Slot*>& live, const std::vector<OpEntry>& ops, const std::vector<int>& idx,
+                      bool xcd, std::vector<int2>& all, std::vector<int2>& nonil, std::vector<int>& ils,
+                      std::vector<int2>& ilt) {
+  for (int o = 0; o < (int)ops.size(); ++o) {
+    std::vector<int> mine;
+    for (int i : idx)
+      if (live[i]->op == o) mine.push_back(i);
+    if (mine.empty()) continue;
+    std::map<std::pair<char*, int>, int> ent;  // (group, tile) -> lane-tile index
+    const int e0 = (int)(ils.size() / 16);
+    for (int i : mine) {
+      const Slot* s = live[i];
+      if (!s->il_base) continue;
+      auto key = std::make_pair(s->il_base, s->il_lane / 16);
+      auto it = ent.find(key);
+      int e;
+      if (it == ent.end()) {
+        e = (int)(ils.size() / 16);
+        ent[key] = e;
+        ils.insert(ils.end(), 16, -1);
+      } else {
+        e = it->second;
+      }
+      ils[(size_t)e * 16 + s->il_lane % 16] = i;
+    }
+    const int e1 = (int)(ils.size() / 16);
+    for (int b = 0; b < ops[o].nblk; ++b) {
+      for (int i : mine) {
+        all.push_back(make_int2(i, b));
+        if (!live[i]->il_base) nonil.push_back(make_int2(i, b));
+      }
+      for (int e = e0; e < e1; ++e) ilt.push_back(make_int2(e, b));
+    }
+  }
+  xcd_order(all, xcd);
+  xcd_order(nonil, xcd);
+  xcd_order(ilt, xcd);
+}
+
 int Solver::rebuild() {
   if (!dirty) return A2A_OK;
   gc_ops();
@@ -416,6 +464,10 @@ int Solver::rebuild() {
     d.arena[1] = s->hi;
     d.vstride[0] = (long long)s->lo_stride;
     d.vstride[1] = (long long)s->hi_stride;
+    d.lss = s->lss;
+    d.lcs = s->lcs;
+    d.lss_x = s->lss_x;
+    d.lxoff = s->lxoff;
     d.scal = ctx->scal_pool + (size_t)s->sid * NSCAL;
     d.src = s->src;
     d.sol = s->sol;
@@ -424,7 +476,10 @@ int Solver::rebuild() {
   A2A_TRY(upload(ctx, d_slots, hs.data(), sizeof(SlotDev) * n));
   // groups of R slots sharing an operator, and tile lists
   std::vector<int> groups;
-  std::vector<int2> htiles, vtiles;
+  std::vector<int2> htiles, vtiles, nonil, ilt;
+  std::vector<int> ils;
+  std::vector<int> every;
+  for (size_t i = 0; i < n; ++i) every.push_back((int)i);
   for (int o = 0; o < (int)ops.size(); ++o) {
     std::vector<int> mine;
     for (size_t i = 0; i < n; ++i)
@@ -439,11 +494,17 @@ int Solver::rebuild() {
       }
     for (int b = 0; b < ops[o].nblk; ++b)
       for (int gi = 0; gi < ng; ++gi) htiles.push_back(make_int2(g0 + gi, b));
-    for (int b = 0; b < ops[o].nblk; ++b)
-      for (int i : mine) vtiles.push_back(make_int2(i, b));
   }
   xcd_order(htiles, ctx->xcd_order);
-  xcd_order(vtiles, ctx->xcd_order);
+  vec_lists(live, ops, every, ctx->xcd_order, vtiles, nonil, ils, ilt);
+  A2A_TRY(grow(ctx, (void**)&d_vec_nonil, &cap_nonil, sizeof(int2) * std::max<size_t>(1, nonil.size())));
+  A2A_TRY(grow(ctx, (void**)&d_il_slots, &cap_ils, sizeof(int) * std::max<size_t>(1, ils.size())));
+  A2A_TRY(grow(ctx, (void**)&d_il_tiles, &cap_ilt, sizeof(int2) * std::max<size_t>(1, ilt.size())));
+  A2A_TRY(upload(ctx, d_vec_nonil, nonil.data(), sizeof(int2) * nonil.size()));
+  A2A_TRY(upload(ctx, d_il_slots, ils.data(), sizeof(int) * ils.size()));
+  A2A_TRY(upload(ctx, d_il_tiles, ilt.data(), sizeof(int2) * ilt.size()));
+  n_vec_nonil = (int)nonil.size();
+  n_il_tiles = (int)ilt.size();
   A2A_TRY(grow(ctx, (void**)&d_groups, &cap_groups, sizeof(int) * std::max<size_t>(1, groups.size())));
   A2A_TRY(grow(ctx, (void**)&d_hop_tiles, &cap_hop, sizeof(int2) * std::max<size_t>(1, htiles.size())));
   A2A_TRY(grow(ctx, (void**)&d_vec_tiles, &cap_vec, sizeof(int2) * std::max<size_t>(1, vtiles.size())));
@@ -459,7 +520,8 @@ int Solver::rebuild() {
 // groups of one slot each (R_sub = 1) or R for a subset of live slots
 int Solver::upload_subset(const std::vector<int>& idx, int R_sub) {
   std::vector<int> groups;
-  std::vector<int2> htiles, vtiles;
+  std::vector<int2> htiles, vtiles, nonil, ilt;
+  std::vector<int> ils;
   for (int o = 0; o < (int)ops.size(); ++o) {
     std::vector<int> mine;
     for (int i : idx)
@@ -472,24 +534,28 @@ int Solver::upload_subset(const std::vector<int>& idx, int R_sub) {
         size_t k = (size_t)gi * R_sub + r;
         groups.push_back(k < mine.size() ? mine[k] : -1);
       }
-    for (int b = 0; b < ops[o].nblk; ++b) {
+    for (int b = 0; b < ops[o].nblk; ++b)
       for (int gi = 0; gi < ng; ++gi) htiles.push_back(make_int2(g0 + gi, b));
-      for (int i : mine) vtiles.push_back(make_int2(i, b));
-    }
   }
   xcd_order(htiles, ctx->xcd_order);
-  xcd_order(vtiles, ctx->xcd_order);
-  // one buffer holds [hop tiles | vec tiles]
+  vec_lists(live, ops, idx, ctx->xcd_order, vtiles, nonil, ils, ilt);
+  // one buffer holds [hop tiles | vec tiles | non-interleaved vec tiles | interleaved tiles]
   A2A_TRY(grow(ctx, (void**)&d_sub_groups, &cap_subg, sizeof(int) * std::max<size_t>(1, groups.size())));
-  A2A_TRY(grow(ctx, (void**)&d_sub_tiles, &cap_subt, sizeof(int2) * std::max<size_t>(1, htiles.size() + vtiles.size())));
   std::vector<int2> all(htiles);
   all.insert(all.end(), vtiles.begin(), vtiles.end());
+  all.insert(all.end(), nonil.begin(), nonil.end());
+  all.insert(all.end(), ilt.begin(), ilt.end());
+  A2A_TRY(grow(ctx, (void**)&d_sub_tiles, &cap_subt, sizeof(int2) * std::max<size_t>(1, all.size())));
   A2A_TRY(grow(ctx, (void**)&d_sub_list, &cap_subl, sizeof(int) * std::max<size_t>(1, idx.size())));
+  A2A_TRY(grow(ctx, (void**)&d_sub_il_slots, &cap_subils, sizeof(int) * std::max<size_t>(1, ils.size())));
   A2A_TRY(upload(ctx, d_sub_groups, groups.data(), sizeof(int) * groups.size()));
   A2A_TRY(upload(ctx, d_sub_tiles, all.data(), sizeof(int2) * all.size()));
   A2A_TRY(upload(ctx, d_sub_list, idx.data(), sizeof(int) * idx.size()));
+  A2A_TRY(upload(ctx, d_sub_il_slots, ils.data(), sizeof(int) * ils.size()));
   sub_nh = (int)htiles.size();
   sub_nv = (int)vtiles.size();
+  sub_nn = (int)nonil.size();
+  sub_ni = (int)ilt.size();
   sub_n = (int)idx.size();
   return A2A_OK;
 }
@@ -562,7 +628,17 @@ int Solver::vec(bool sub, int n_tiles, int kind, int par, int use_inv, int vin, 
   const bool timed = !sub && (kind == VK_BICG_S || kind == VK_BICG_XR || kind == VK_BICG_P);
   hipEvent_t ev = nullptr;
   if (timed) A2A_TRY(ctx->timing_begin(2, &ev));
-  launch_vec(prec, a, n_tiles, ctx->stream);
+  const int n_il = sub ? sub_ni : n_il_tiles;
+  if (vec_kind_il(kind) && n_il > 0) {  // interleaved slots with the lane mapping, the rest per slot
+    VecArgs b = a;
+    b.tiles = sub ? d_sub_tiles + sub_nh + sub_nv + sub_nn : d_il_tiles;
+    b.ilslots = sub ? d_sub_il_slots : d_il_slots;
+    launch_vec_il(prec, b, n_il, ctx->stream);
+    a.tiles = sub ? d_sub_tiles + sub_nh + sub_nv : d_vec_nonil;
+    launch_vec(prec, a, sub ? sub_nn : n_vec_nonil, ctx->stream);
+  } else {
+    launch_vec(prec, a, n_tiles, ctx->stream);
+  }
   A2A_HIP(ctx, hipGetLastError());
   if (timed) {
     const double sz = prec == 0 ? 8.0 : prec == 1 ? 4.0 : 2.0;
@@ -628,8 +704,8 @@ int Solver::iteration() {
 // FP64: x64 is current; r64 = b - M x64 and |r64|^2 for a subset (uploaded by the caller).
 int Solver::true_residual(const std::vector<int>& idx) {
   (void)idx;
-  A2A_TRY(hop(true, sub_nh, 1, 1, 0, 0, VH_X, VH_TE, -1, -1, -1, 0, 0, 1.0, 0, 1, RED_NONE, nullptr));
-  A2A_TRY(hop(true, sub_nh, 1, 1, 0, 1, VH_TE, VH_R, VH_BHAT, VH_X, -1, 1.0, -1.0, 1.0, 2, 0, RED_R64, nullptr));
+  A2A_TRY(hop(true, sub_nh, R64, 1, 0, 0, VH_X, VH_TE, -1, -1, -1, 0, 0, 1.0, 0, 1, RED_NONE, nullptr));
+  A2A_TRY(hop(true, sub_nh, R64, 1, 0, 1, VH_TE, VH_R, VH_BHAT, VH_X, -1, 1.0, -1.0, 1.0, 2, 0, RED_R64, nullptr));
   return A2A_OK;
 }
 
@@ -641,16 +717,16 @@ int Solver::setup(const std::vector<int>& idx) {
   std::vector<int> with_x0;
   for (int i : idx)
     if (live[i]->x0) with_x0.push_back(i);
-  A2A_TRY(upload_subset(idx, 1));
+  A2A_TRY(upload_subset(idx, R64));
   int nh = sub_nh, nv = sub_nv;
   A2A_TRY(layout_in(true, nv, 0, 1, 0, VH_ETA_E, VH_ETA_O, 0, RED_ETA));
   A2A_TRY(vec(true, nv, VK_CLOVER, 0, 1, VH_ETA_E, VH_TE));
-  A2A_TRY(hop(true, nh, 1, 1, 0, 1, VH_TE, VH_BHAT, VH_ETA_O, -1, -1, 1.0, 0, 1.0, 1, 0, RED_NONE, nullptr));
+  A2A_TRY(hop(true, nh, R64, 1, 0, 1, VH_TE, VH_BHAT, VH_ETA_O, -1, -1, 1.0, 0, 1.0, 1, 0, RED_NONE, nullptr));
   A2A_TRY(vec(true, nv, VK_ZERO_HI, 0, 0, -1, VH_X));
   if (!with_x0.empty()) {
     A2A_TRY(upload_subset(with_x0, 1));
     A2A_TRY(layout_in(true, sub_nv, 1, 1, 0, VH_TE, VH_X, 0, RED_NONE));
-    A2A_TRY(upload_subset(idx, 1));
+    A2A_TRY(upload_subset(idx, R64));
   }
   A2A_TRY(true_residual(idx));
   A2A_TRY(vec(true, nv, VK_INIT));
@@ -676,14 +752,14 @@ int Solver::setup(const std::vector<int>& idx) {
 // solution.  Fills info; returns through slot state.
 int Solver::finalize(const std::vector<int>& idx) {
   if (idx.empty()) return A2A_OK;
-  A2A_TRY(upload_subset(idx, 1));
+  A2A_TRY(upload_subset(idx, R64));
   const int nh = sub_nh, nv = sub_nv;
   // x_e = A_ee^{-1} (eta_e + kappa H_eo x_o)  -> VH_TE
-  A2A_TRY(hop(true, nh, 1, 1, 0, 0, VH_X, VH_TE, VH_ETA_E, -1, -1, 1.0, 0, 1.0, 1, 1, RED_NONE, nullptr));
+  A2A_TRY(hop(true, nh, R64, 1, 0, 0, VH_X, VH_TE, VH_ETA_E, -1, -1, 1.0, 0, 1.0, 1, 1, RED_NONE, nullptr));
   // r_e = eta_e - A_ee x_e + kappa H_eo x_o
-  A2A_TRY(hop(true, nh, 1, 1, 0, 0, VH_X, VH_R, VH_ETA_E, VH_TE, -1, 1.0, -1.0, 1.0, 1, 0, RED_RES_E, nullptr));
+  A2A_TRY(hop(true, nh, R64, 1, 0, 0, VH_X, VH_R, VH_ETA_E, VH_TE, -1, 1.0, -1.0, 1.0, 1, 0, RED_RES_E, nullptr));
   // r_o = eta_o - A_oo x_o + kappa H_oe x_e
-  A2A_TRY(hop(true, nh, 1, 1, 0, 1, VH_TE, VH_R, VH_ETA_O, VH_X, -1, 1.0, -1.0, 1.0, 1, 0, RED_RES_O, nullptr));
+  A2A_TRY(hop(true, nh, R64, 1, 0, 1, VH_TE, VH_R, VH_ETA_O, VH_X, -1, 1.0, -1.0, 1.0, 1, 0, RED_RES_O, nullptr));
   A2A_TRY(layout_out(true, nv, 1, 0, VH_TE, VH_X, 0));
   A2A_TRY(ctx->read_scal());
   const double t = now_seconds();
@@ -728,7 +804,7 @@ int Solver::check() {
     A2A_TRY(upload_subset(ru, 1));
     A2A_TRY(vec(true, sub_nv, VK_RU_ACCUM));
   }
-  A2A_TRY(upload_subset(all, 1));
+  A2A_TRY(upload_subset(all, R64));
   A2A_TRY(true_residual(all));
   A2A_TRY(ctx->read_scal());
   std::vector<int> done, rescale, reinit;

@@ -79,9 +79,13 @@ struct Slot {
   const double* src = nullptr;
   double* sol = nullptr;
   const double* x0 = nullptr;
-  char* lo = nullptr;
+  char* lo = nullptr;  // inner vectors (this slot's lane within an interleaved group, or its own arena)
   char* hi = nullptr;
   size_t lo_stride = 0, hi_stride = 0;
+  long long lss = 16, lcs = 0, lss_x = 16, lxoff = 0;  // inner layout strides (SlotDev)
+  char* lo_alloc = nullptr;  // allocation this slot owns (its arena, or its group's for lane 0)
+  char* il_base = nullptr;   // interleaved group: arena base (group identity), tiles, lane
+  int il_nt = 0, il_lane = -1;
   double tol = 1e-10, target = 0, eta_norm = 0, last_r64 = INFINITY;
   int max_iter = 10000;
   int iters = 0, rus = 0, restarts = 0, stagn = 0;
@@ -96,7 +100,8 @@ struct Slot {
 struct Solver {
   Ctx* ctx;
   int prec;
-  int R;  // RHS per thread in the stencil
+  int R;    // RHS per thread in the stencil
+  int R64;  // RHS per thread in the FP64 stencils of setup, reliable updates and reconstruction
   std::vector<OpEntry> ops;
   std::vector<Slot*> live;  // slots in the device tables (running)
   // device tables
@@ -108,14 +113,20 @@ struct Solver {
   int* d_sub_groups = nullptr;
   int2* d_sub_tiles = nullptr;
   int* d_sub_list = nullptr;
+  int2* d_vec_nonil = nullptr;  // per-slot tiles of the slots not in interleaved groups
+  int* d_il_slots = nullptr;    // interleaved lane tiles: 16 slot indices each
+  int2* d_il_tiles = nullptr;   // {lane tile, site block}
+  int* d_sub_il_slots = nullptr;
   size_t cap_ops = 0, cap_slots = 0, cap_groups = 0, cap_hop = 0, cap_vec = 0, cap_subg = 0, cap_subt = 0,
-         cap_subl = 0;
-  int n_hop_tiles = 0, n_vec_tiles = 0;
-  int sub_nh = 0, sub_nv = 0, sub_n = 0;  // tile and slot counts of the last uploaded subset
+         cap_subl = 0, cap_nonil = 0, cap_ils = 0, cap_ilt = 0, cap_subils = 0;
+  int n_hop_tiles = 0, n_vec_tiles = 0, n_vec_nonil = 0, n_il_tiles = 0;
+  // tile and slot counts of the last uploaded subset; its tile buffer holds
+  // [hop tiles | per-slot tiles | per-slot tiles of non-interleaved slots | interleaved tiles]
+  int sub_nh = 0, sub_nv = 0, sub_n = 0, sub_nn = 0, sub_ni = 0;
   bool dirty = true;
   bool with_hi = true;
 
-  Solver(Ctx* c, int p, int r) : ctx(c), prec(p), R(r) {}
+  Solver(Ctx* c, int p, int r);
   ~Solver();
   int op_index(int clover_h, double kappa, KappaOp* kop, const GaugeField* gf);
   int add_slot(Slot* s);
@@ -159,12 +170,14 @@ struct Ctx {
   unsigned long long use_clock = 0;
   // options
   int rhs_block = 4;
+  int rhs_block64 = 2;  // RHS per thread of the FP64 stencils (1 or 2)
   int check_every = 4;
   double delta_lo = 0.1, delta_64 = 1e-3;
   int xcd_order = 1;
   int timing = 0;
   int debug = 0;  // A2A_DEBUG=1 in the environment: residual trace on stderr
   int autotune = 0;                  // pick the stencil RHS-block width per workload
+  int interleave = 0;                // FP16/BF16 inner vectors in the interleaved group layout
   std::map<std::string, int> tuned;  // tune key -> RHS-block width
   std::string tune_path;             // A2A_TUNE_CACHE: JSON file of tuned widths
   // reduction scratch

@@ -71,7 +71,16 @@ def test_autotune_picks_a_width_and_solves(ctx, orc, fields):
         assert np.linalg.norm(r) / np.linalg.norm(eta[i]) <= 1e-10
 
 
-def test_engine_mixed_stream_matches_alone(ctx, orc, fields):
+@pytest.mark.parametrize("il", [0, 1])
+def test_engine_mixed_stream_matches_alone(ctx, orc, fields, il):
+    ctx.set_option("interleave", il)
+    try:
+        _engine_mixed_stream(ctx, orc, fields)
+    finally:
+        ctx.set_option("interleave", 0)
+
+
+def _engine_mixed_stream(ctx, orc, fields):
     import torch
 
     print("[gpu] engine mixed stream", flush=True)
