@@ -34,17 +34,18 @@ STORAGE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
 # copy (fetch x2.0, write x1.0). Valid only for the kernel sources they were taken on (hash of the
 # stencil's sources) and for the same workload, precision, RHS block and kernel class.
 TRAFFIC = {
-    ("schur2", "l32t64", "f16", 2): {"src": "5416965449cd31f9", "bytes": 1.7666e10,
-                                     "profile": "profiles/bench_l32t64_f16_rb2_hbm_counters.txt"},
+    ("schur2", "l32t64", "f16", "rb2"): {"src": "5416965449cd31f9", "bytes": 1.7666e10,
+                                         "profile": "profiles/bench_l32t64_f16_rb2_hbm_counters.txt"},
 }
-STENCIL_SOURCES = ("hop.hip", "a2a_device.h", "a2a_reduce.h", "a2a_kernels.h")
+STENCIL_SOURCES = {"per-thread": ("hop.hip", "a2a_device.h", "a2a_reduce.h", "a2a_kernels.h"),
+                   "mfma": ("hop_mfma.hip", "a2a_device.h", "a2a_reduce.h", "a2a_kernels.h")}
 
 
-def stencil_src_hash():
+def stencil_src_hash(kind):
     import hashlib
 
     h = hashlib.sha256()
-    for f in STENCIL_SOURCES:
+    for f in STENCIL_SOURCES[kind]:
         with open(os.path.join(ROOT, "paper_1405_4524_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -63,6 +64,9 @@ def main():
     ap.add_argument("--prec", default="f16", choices=list(PREC))
     ap.add_argument("--rhs-block", type=int, default=2)
     ap.add_argument("--check-every", type=int, default=4)
+    ap.add_argument("--interleave", type=int, default=1,
+                    help="1: FP16/BF16 inner vectors in lane-interleaved groups (matrix-core stencil)")
+    ap.add_argument("--mfma", type=int, default=1, help="0: interleaved groups use the per-thread stencil")
     ap.add_argument("--fp64-sources", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and stencil side measurements")
@@ -112,6 +116,8 @@ def main():
     ctx.z2_noise_dev(dims, w["noise_seed"], 0, nsrc, src)
     ctx.set_option("rhs_block", args.rhs_block)
     ctx.set_option("check_every", args.check_every)
+    ctx.set_option("interleave", args.interleave)
+    ctx.set_option("mfma", args.mfma)
 
     if args.stencil_only:
         stencil_only(args, ctx, links, dims, tbc, kappa, csw, V)
@@ -161,11 +167,17 @@ def main():
     dom = max(kstats, key=lambda k: kstats[k][1])
     n_l, ms_l, by_l = kstats[dom]
     achieved = by_l / (ms_l * 1e-3) / 1e9 if ms_l > 0 else 0.0
-    tr = TRAFFIC.get((dom, args.workload, args.prec, args.rhs_block))
-    traffic = tr["bytes"] if tr and tr["src"] == stencil_src_hash() else None
-    roofline = {"bound": "hbm", "kernel": {"schur1": "k_hop<.., EPI_INV> (H_eo + A_ee^-1)",
-                                            "schur2": "k_hop<.., EPI_CLOV> (H_oe + A_oo + axpy + dot)",
-                                            "blas": "k_vec (BiCGStab updates)"}[dom],
+    mfma = bool(args.interleave and args.mfma and prec in (2, 3))
+    layout = "il" if mfma else f"rb{args.rhs_block}"
+    tr = TRAFFIC.get((dom, args.workload, args.prec, layout))
+    kind = "mfma" if mfma else "per-thread"
+    traffic = tr["bytes"] if tr and tr["src"] == stencil_src_hash(kind) else None
+    names = ({"schur1": "k_hop_mfma<.., EPI_INV> (H_eo + A_ee^-1, matrix cores)",
+              "schur2": "k_hop_mfma<.., EPI_CLOV> (H_oe + A_oo + axpy + dot, matrix cores)"} if mfma else
+             {"schur1": "k_hop<.., EPI_INV> (H_eo + A_ee^-1)",
+              "schur2": "k_hop<.., EPI_CLOV> (H_oe + A_oo + axpy + dot)"})
+    names["blas"] = "k_vec (BiCGStab updates)"
+    roofline = {"bound": "hbm", "kernel": names[dom],
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_unit": "bytes/launch",
@@ -183,7 +195,10 @@ def main():
                       "tol": tol, "links": f"exp(i {w['eps']} H), seed {w['gauge_seed']}",
                       "noise": f"complex Z2 splitmix64 seed {w['noise_seed']}",
                       "precision": f"inner {args.prec} storage / f32 arithmetic, f64 reliable updates"
-                      if prec else "f64", "rhs_block": args.rhs_block},
+                      if prec else "f64", "rhs_block": args.rhs_block,
+                      "layout": "lane-interleaved groups, matrix-core stencil" if mfma else
+                      ("lane-interleaved groups, per-thread stencil" if args.interleave and prec in (2, 3)
+                       else "per-slot")},
            "solve": {"iters_min": min(iters), "iters_max": max(iters), "reliable_updates_max": max(rus),
                      "max_true_rel_residual": max(resid), "all_converged": all(x["converged"] for x in last)},
            "roofline": roofline, "kernels": kernels}

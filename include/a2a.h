@@ -105,7 +105,11 @@ const char *a2a_last_error(const a2a_ctx *ctx);
  * 2), "check_every" (iterations between residual checks), "delta" (reliable-update reduction
  * factor), "delta64" (the same for the FP64-only mode),
  * "xcd_order" (0/1), "kernel_timing" (0/1), "autotune" (0/1), "hbm_budget" (bytes; resets
- * the budget given at a2a_init).  Returns A2A_EINVAL for an unknown key. */
+ * the budget given at a2a_init), "interleave" (0/1, default 1: FP16 / BF16 inner vectors of
+ * the sources of one call or request in lane-interleaved groups of up to 48, which the stencil
+ * applies on the matrix cores), "mfma" (0/1: 0 makes interleaved groups use the per-thread
+ * stencil).
+ * Returns A2A_EINVAL for an unknown key. */
 int a2a_set_option(a2a_ctx *ctx, const char *key, double value);
 /* Bytes of device memory currently held by the context. */
 size_t a2a_mem_in_use(const a2a_ctx *ctx);

@@ -403,6 +403,11 @@ struct OpDev {
   const void* U[2][2];   // [prec][parity] -> 4 link fields (mu-major) of that parity's sites
   const void* A[2][2];   // [prec][parity] clover
   const void* Ai[2][2];  // [prec][parity] clover inverse
+  // matrix-core stencil (16-bit inner precision, per output parity): hop links [site][8][3][3],
+  // full clover and inverse-clover blocks [site][2][6][6], complex pairs of 16-bit reals
+  const void* HL[2];
+  const void* AF[2];
+  const void* AIF[2];
 };
 
 // One right-hand side of a batch.

@@ -30,6 +30,31 @@ struct HopArgs {
   RedBuf rb;
 };
 
+// Matrix-core stencil for lane-interleaved groups (FP16 / BF16 inner vectors).
+constexpr int IL_LANES = 48;  // RHS per interleaved group (three tiles of 16 lanes)
+
+struct ILGroupDev {
+  int op;
+  int nt;  // lane tiles in use
+  int pad0, pad1;
+  char* base;             // arena: [vector][site][tile][3 chunks][16 lanes] of 16-byte chunks
+  long long vs;           // bytes per vector
+  int slot[IL_LANES];     // slot-table index of each lane, -1 = idle
+};
+
+struct HopMArgs {
+  const OpDev* ops;
+  const SlotDev* slots;
+  const ILGroupDev* groups;
+  const int2* tiles;  // {group, site block of BS sites}
+  int out_par;
+  int vin, vout, vaux1, vaux2, vrhat;
+  double ca, cb, gsign;
+  int gpow;
+  int red;
+  RedBuf rb;
+};
+
 // Site-local / vector kernels over per-slot tiles {slot, site block}.
 enum VecKind {
   VK_BICG_S = 0,    // s = r - alpha v
@@ -77,6 +102,10 @@ void launch_finalize(int kind, const OpDev* ops, const SlotDev* slots, const int
                      hipStream_t s);
 
 void launch_hop(int prec, int R, const HopArgs& a, int ntiles, hipStream_t s);
+// o = gam H in (+ cb A aux2) (then A^{-1} .) for every lane of the groups, on the matrix
+// cores; reduction kinds NONE, ALPHA and OMEGA (with the clover term); no axpy term
+bool hop_mfma_supports(int prec, int inv, bool clov, int red, bool aux1);
+void launch_hop_mfma(int prec, const HopMArgs& a, int ntiles, int inv, bool clov, hipStream_t s);
 void launch_vec(int prec, const VecArgs& a, int ntiles, hipStream_t s);
 // the lane-interleaved variant (FP16 / BF16 inner vectors in interleaved groups); kinds that
 // touch inner vectors only
@@ -91,6 +120,10 @@ void launch_gauge_to_eo(int prec, const Geo& g, const double* canon, void* const
 void launch_clover_field(const Geo& g, const double* canon_links, double* G[2], hipStream_t s);
 // A = 1 + kappa c_sw G per parity in FP64, plus its per-block inverse (FP64)
 void launch_clover_make(const Geo& g, const double* G, double kcsw, double* A, double* Ainv, hipStream_t s);
+// per-site hop links (both directions, boundary sign folded in) of one parity, 16-bit formats
+void launch_hop_links(int prec, const Geo& g, const double* canon, int par, void* dst, hipStream_t s);
+// packed FP64 clover blocks -> full 6x6 blocks in a 16-bit format
+void launch_clover_full(int prec, long hv, const double* packed, void* dst, hipStream_t s);
 // precision conversion of a packed clover field
 void launch_clover_convert(int prec, long hv, const double* src, void* dst, hipStream_t s);
 

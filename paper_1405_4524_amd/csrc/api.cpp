@@ -74,11 +74,11 @@ void slot_free(Ctx* c, Slot* s) {
   s->sid = -1;
 }
 
-// Interleaved inner layout (FP16 / BF16 storage): consecutive slots form groups of up to 64
-// lanes (tiles of 16) sharing one arena [vector][site][tile][3 chunks][16 lanes] of 16-byte
-// chunks.  Lane 0 of each group owns the arena.  Groups never span calls or requests, so a
-// group's arena is freed together with all of its slots.
-constexpr int IL_MAX = 64;
+// Interleaved inner layout (FP16 / BF16 storage): consecutive slots form groups of up to
+// IL_LANES lanes (tiles of 16) sharing one arena [vector][site][tile][3 chunks][16 lanes] of
+// 16-byte chunks.  Lane 0 of each group owns the arena.  Groups never span calls or requests,
+// so a group's arena is freed together with all of its slots.
+constexpr int IL_MAX = IL_LANES;
 
 bool use_interleave(const Ctx* c, int prec) { return c->interleave && (prec == 2 || prec == 3); }
 
@@ -137,6 +137,10 @@ int resolve_op(Ctx* c, int clover_h, double kappa, int prec, GaugeField** gf, Cl
   A2A_TRY(c->gauge_links(*gf, 0, &u0, &u1));
   A2A_TRY(c->gauge_links(*gf, prec, &u0, &u1));
   A2A_TRY(c->kappa_op(*cf, kappa, prec, kop));
+  if (use_interleave(c, prec) && c->mfma) {  // fields of the matrix-core stencil
+    A2A_TRY(c->hop_links(*gf, prec));
+    A2A_TRY(c->clover_full(*kop, prec, (*gf)->g.hv));
+  }
   return A2A_OK;
 }
 
@@ -414,6 +418,8 @@ extern "C" int a2a_set_option(a2a_ctx* h, const char* key, double v) {
     c->autotune = v != 0;
   } else if (k == "interleave") {
     c->interleave = v != 0;
+  } else if (k == "mfma") {
+    c->mfma = v != 0;
   } else if (k == "hbm_budget") {
     if (!(v > 0)) return c->fail(A2A_EINVAL, "hbm_budget must be positive");
     c->budget = (size_t)v;
@@ -531,7 +537,10 @@ extern "C" int a2a_unload(a2a_ctx* h, int handle) {
     }
     c->dfree(gf->canon);
     for (int q = 0; q < 4; ++q)
-      for (int p = 0; p < 2; ++p) c->dfree(gf->U[q][p]);
+      for (int p = 0; p < 2; ++p) {
+        c->dfree(gf->U[q][p]);
+        c->dfree(gf->HL[q][p]);
+      }
     c->gauges.erase(handle);
     return A2A_OK;
   }

@@ -183,12 +183,15 @@ __global__ __launch_bounds__(BS) void k_vec(VecArgs a) {
   }
 }
 
-// interleaved mapping: tiles {16-lane group tile, block of BS sites}; thread (lane n, row q)
-// visits sites block*BS + 16 i + q, so a wave touches 4 sites x 16 lanes = 4 contiguous
-// 256-byte runs per chunk.  Reductions are per lane (slot) and land in the same partial
-// slots as the per-slot mapping (block index = site block of BS sites).
+// interleaved mapping: tiles {16-lane group tile, block of BS sites}; BSI threads as (lane n,
+// row q) visit sites block*BS + 64 i + q, so a wave touches 4 sites x 16 lanes = 4 contiguous
+// 256-byte runs per chunk and a block keeps 16 waves of loads in flight.  Reductions are per
+// lane (slot) and land in the same partial slots as the per-slot mapping (block index = site
+// block of BS sites).
+constexpr int BSI = 1024;
+
 template <class P, int KIND>
-__global__ __launch_bounds__(BS) void k_vec_il(VecArgs a) {
+__global__ __launch_bounds__(BSI) void k_vec_il(VecArgs a) {
   const int2 tile = a.tiles[blockIdx.x];
   const int n = threadIdx.x & 15, q = threadIdx.x >> 4;
   const int slot = a.ilslots[tile.x * 16 + n];
@@ -196,13 +199,14 @@ __global__ __launch_bounds__(BS) void k_vec_il(VecArgs a) {
   if (slot >= 0) {
     const SlotDev& sd = a.slots[slot];
     const int hv = a.ops[sd.op].g.hv;
-    for (int i = 0; i < BS / 16; ++i) {
-      const int site = tile.y * BS + 16 * i + q;
+#pragma unroll
+    for (int i = 0; i < BS / (BSI / 16); ++i) {
+      const int site = tile.y * BS + (BSI / 16) * i + q;
       if (site < hv) vec_site<P, KIND>(a, sd, hv, site, v3);
     }
   }
   if (VecRed<KIND>::on) {
-    __shared__ double red[BS / 64][16][3];
+    __shared__ double red[BSI / 64][16][3];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -219,7 +223,7 @@ __global__ __launch_bounds__(BS) void k_vec_il(VecArgs a) {
       if (sl >= 0) {
         double t = 0.0;
 #pragma unroll
-        for (int j = 0; j < BS / 64; ++j) t += red[j][m][k];
+        for (int j = 0; j < BSI / 64; ++j) t += red[j][m][k];
         store_partial(a.rb, a.slots[sl].sid, tile.y, k, t);
       }
     }
@@ -228,7 +232,7 @@ __global__ __launch_bounds__(BS) void k_vec_il(VecArgs a) {
 
 template <class P>
 static void launch_vec_il_p(const VecArgs& a, int n, hipStream_t s) {
-  const dim3 g(n), b(BS);
+  const dim3 g(n), b(BSI);
   switch (a.kind) {
     case VK_BICG_S: hipLaunchKernelGGL((k_vec_il<P, VK_BICG_S>), g, b, 0, s, a); break;
     case VK_BICG_XR: hipLaunchKernelGGL((k_vec_il<P, VK_BICG_XR>), g, b, 0, s, a); break;

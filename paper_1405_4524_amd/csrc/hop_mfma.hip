@@ -1,0 +1,479 @@
+// hop_mfma.hip -- the Wilson-clover hopping stencil on the matrix cores for lane-interleaved
+// groups of right-hand sides (FP16 or BF16 storage, FP32 accumulation).
+//
+// At one output site x the hopping term H (the sum over the eight neighbours in the
+// hopping-parameter form of the Wilson-clover operator, Sec. 7) is a real 24 x 192 matrix
+// acting on the eight neighbour spinors stacked as 8 x 24 reals: block d = 2 mu + f of the
+// matrix is the real form of (1 -+ gamma_mu) (x) V_d with V_d the site's hop link of
+// direction d (the link, or the daggered backward link, with the fermion boundary sign).
+// Every RHS of a group sees the same matrix, so one wavefront takes one site at a time and
+// multiplies the matrix with the 192 x 16 block of neighbour data of each 16-lane tile on the
+// matrix cores: v_mfma_f32_16x16x32 over 2 row tiles (24 rows + 8 unused) x 6 K steps.  The
+// clover term A_x psi(x) is one more K step (24 columns + 8 zero columns).  The inverse-clover
+// epilogue is a second product after a register -> LDS -> register transpose of the hop result
+// (which rounds that intermediate to the storage format).  Calls with an axpy term (aux1) use
+// the per-thread stencil.
+//
+// The matrix is rebuilt per site in LDS by the 64 lanes of the wave: lane (d, s, c') writes
+// the three row blocks (colour a = 0..2) of its direction d for output spin s and real /
+// imaginary part c'.  Each entry is the real or imaginary part of a link element, possibly
+// swapped and negated; which one is fixed per lane and selected once before the site loop.
+//
+// Layout of one wavefront's LDS matrix: 24 rows of 464 bytes = 232 halves: columns 0..191
+// the hopping blocks (d, spin s', colour b, re/im), 192..215 the clover block, 216..231 zero.
+// Rows are 464 B apart so that the 16-byte fragment reads of 16 consecutive rows fall on
+// distinct banks.
+#include "a2a_kernels.h"
+
+namespace a2a {
+
+namespace {
+
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename S>
+struct MM;
+
+template <>
+struct MM<_Float16> {
+  static __device__ __forceinline__ f4v mma(const uint4& a, const uint4& b, const f4v& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8v, a), __builtin_bit_cast(h8v, b), c, 0, 0,
+                                                  0);
+  }
+  static __device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+    const _Float16 a = (_Float16)lo, b = (_Float16)hi;
+    return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+  }
+  static __device__ __forceinline__ float lo(uint32_t u) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(u & 0xffffu));
+  }
+  static __device__ __forceinline__ float hi(uint32_t u) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(u >> 16)); }
+};
+
+template <>
+struct MM<bf16_t> {
+  static __device__ __forceinline__ f4v mma(const uint4& a, const uint4& b, const f4v& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8v, a), __builtin_bit_cast(b8v, b), c, 0, 0,
+                                                   0);
+  }
+  static __device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+    return (uint32_t)float_to_bf16(lo).v | ((uint32_t)float_to_bf16(hi).v << 16);
+  }
+  static __device__ __forceinline__ float lo(uint32_t u) { return bf16_to_float(bf16_t{(uint16_t)(u & 0xffffu)}); }
+  static __device__ __forceinline__ float hi(uint32_t u) { return bf16_to_float(bf16_t{(uint16_t)(u >> 16)}); }
+};
+
+constexpr int WAVES = BS / 64;
+constexpr int SITES_PER_WAVE = BS / WAVES;  // a block covers BS sites, like every reducing kernel
+constexpr int TROW = 29;                    // uint4 per matrix row (464 B)
+constexpr int TCLO = 24;                    // uint4 column of the clover K step (half 192)
+constexpr int TRW = 5;                      // uint4 per transpose row (80 B)
+constexpr int NTMAX = IL_LANES / 16;        // lane tiles per group
+
+__device__ __forceinline__ uint32_t rot16(uint32_t v) { return (v >> 16) | (v << 16); }
+
+// Pointers read from the group and operator tables are generic; accesses through them would be
+// FLAT instructions, which count against the LDS counter too and so make every LDS wait also
+// wait for outstanding HBM traffic.  All of these fields point to device global memory.
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) uint32_t* gptr1;
+typedef const __attribute__((address_space(1))) v2u* gptr2;
+typedef const __attribute__((address_space(1))) v4u* gptr4;
+__device__ __forceinline__ uint32_t gld1(const void* p) { return *(gptr1)p; }
+__device__ __forceinline__ uint2 gld2(const void* p) {
+  const v2u v = *(gptr2)p;
+  return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ uint4 gld4(const void* p) {
+  const v4u v = *(gptr4)p;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gst2(void* p, const uint2& v) {
+  v2u w;
+  w.x = v.x;
+  w.y = v.y;
+  *(__attribute__((address_space(1))) v2u*)p = w;
+}
+
+// (1 + sg gamma_mu)[s][t] in the chiral basis as a unit complex (re, im), entries in {-1, 0, 1}.
+// gamma_mu = [[0, a_mu], [a_mu^dag, 0]] with a_k = -i sigma_k (mu = 0, 1, 2) and a_4 = 1.
+__device__ __forceinline__ void proj_entry(int mu, int sg, int s, int t, int& re, int& im) {
+  re = 0;
+  im = 0;
+  if (s == t) {
+    re = 1;
+    return;
+  }
+  if ((s < 2) == (t < 2)) return;
+  const int u = s < 2 ? s : t, v = s < 2 ? t - 2 : s - 2;  // entry a[u][v] (conjugated below the diagonal)
+  int ar = 0, ai = 0;
+  if (mu == 0) {
+    if (u != v) ai = -1;  // -i sigma_1
+  } else if (mu == 1) {
+    if (u == 0 && v == 1) ar = -1;  // -i sigma_2
+    if (u == 1 && v == 0) ar = 1;
+  } else if (mu == 2) {
+    if (u == v) ai = u == 0 ? -1 : 1;  // -i sigma_3
+  } else {
+    if (u == v) ar = 1;
+  }
+  if (s >= 2) ai = -ai;
+  re = sg * ar;
+  im = sg * ai;
+}
+
+// Real-form row c' of (P v) for a unit complex P and a link element v = (vr, vi) packed as two
+// 16-bit halves: c' = 0 gives (Re Pv, -Im Pv), c' = 1 gives (Im Pv, Re Pv).  All eight cases
+// are one of (vr,-vi), (vi,vr), (-vr,vi), (-vi,-vr): a byte permutation (identity, half swap,
+// or all-zero for a vanishing projector entry) and a sign mask.
+struct Variant {
+  uint32_t sel, xm;
+};
+__device__ __forceinline__ Variant variant(int re, int im, int cp) {
+  int T = -1;
+  if (re == 1) T = cp ? 1 : 0;
+  if (re == -1) T = cp ? 3 : 2;
+  if (im == 1) T = cp ? 0 : 3;
+  if (im == -1) T = cp ? 2 : 1;
+  Variant r;
+  r.sel = T < 0 ? 0x0c0c0c0cu : (T == 1 || T == 3) ? 0x01000302u : 0x03020100u;
+  r.xm = T == 0 ? 0x80000000u : T == 2 ? 0x00008000u : T == 3 ? 0x80008000u : 0u;
+  return r;
+}
+__device__ __forceinline__ uint32_t apply(const Variant& V, uint32_t v) {
+  return __builtin_amdgcn_perm(v, v, V.sel) ^ V.xm;
+}
+
+// LDS traffic of one wavefront is executed in issue order, so lanes of the same wave see each
+// other's LDS writes without waiting on any counter; only the compiler must keep the order.
+__device__ __forceinline__ void wave_lds_sync() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+}  // namespace
+
+// Data one 16-lane tile of one site needs: the six K steps of neighbour data, the clover
+// input (EPI_CLOV), the other operand of the reduction and the axpy term, in output layout.
+struct TileIn {
+  uint4 B[6];
+  uint4 Bc;
+  uint2 x0, x1;  // reduction partner (rows of row tile 0 and 1)
+};
+
+template <int EPI, int RED>
+__device__ __forceinline__ void load_tile(TileIn& d, const char* vin, const char* vaux2,
+                                          const char* vred, const int (&nbs)[6], const int (&hoff)[6], int site,
+                                          int NT, int nt, int n, int gq) {
+#pragma unroll
+  for (int kt = 0; kt < 6; ++kt) d.B[kt] = gld4(vin + ((long long)nbs[kt] * NT + nt) * 768 + hoff[kt]);
+  const long long sbase = ((long long)site * NT + nt) * 768;
+  const long long off0 = sbase + (gq >> 1) * 256 + n * 16 + (gq & 1) * 8;
+  const long long off1 = sbase + 512 + n * 16 + (gq & 1) * 8;  // rows 16.. (lanes gq < 2)
+  if (EPI == 1) d.Bc = gq < 3 ? gld4(vaux2 + sbase + gq * 256 + n * 16) : make_uint4(0, 0, 0, 0);
+  if (RED == RED_ALPHA || RED == RED_OMEGA) {
+    d.x0 = gld2(vred + off0);
+    d.x1 = gq < 2 ? gld2(vred + off1) : make_uint2(0, 0);
+  }
+}
+
+// cb indices of the neighbour site each lane's chunk of K step kt comes from: chunk 4 kt + gq
+// belongs to direction d = (4 kt + gq) / 3, d = 2 mu + f (f = 0 forward, 1 backward)
+__device__ __forceinline__ void site_neighbours(const Geo& g, int site, int po, int gq, int (&nbs)[6]) {
+  int c[4];
+  cb_coords(g, site, po, c);
+  const int xh = c[0] >> 1, x = c[0], y = c[1], z = c[2], t = c[3];
+  const int sy = g.Xh, sz = g.Xh * g.Y, st = g.Xh * g.Y * g.Z;
+  const int row = site - xh;
+  int nb[8];
+  nb[0] = row + ((x + 1 == g.X ? 0 : x + 1) >> 1);
+  nb[1] = row + ((x == 0 ? g.X - 1 : x - 1) >> 1);
+  nb[2] = site + (y == g.Y - 1 ? -(g.Y - 1) * sy : sy);
+  nb[3] = site + (y == 0 ? (g.Y - 1) * sy : -sy);
+  nb[4] = site + (z == g.Z - 1 ? -(g.Z - 1) * sz : sz);
+  nb[5] = site + (z == 0 ? (g.Z - 1) * sz : -sz);
+  nb[6] = site + (t == g.T - 1 ? -(g.T - 1) * st : st);
+  nb[7] = site + (t == 0 ? (g.T - 1) * st : -st);
+  nbs[0] = gq >= 3 ? nb[1] : nb[0];
+  nbs[1] = gq >= 2 ? nb[2] : nb[1];
+  nbs[2] = gq >= 1 ? nb[3] : nb[2];
+  nbs[3] = gq >= 3 ? nb[5] : nb[4];
+  nbs[4] = gq >= 2 ? nb[6] : nb[5];
+  nbs[5] = gq >= 1 ? nb[7] : nb[6];
+}
+
+// A block takes one 16-lane tile of a group over BS consecutive sites (64 per wave).  Blocks
+// run tile-major (all site blocks of tile 0, then tile 1, ...) and are not grouped by XCD, so
+// the chip sweeps one window of the lattice at a time with a per-site footprint of 768 bytes,
+// and the z and t neighbours are still in the last-level cache when they are read.  The
+// neighbour data of site i + 2 is requested while site i is computed (a ring of three register
+// buffers), the next site's links and clover while the current site's matrix is built, and the
+// matrix fragments are read from LDS right before their products.
+template <class P, int EPI, int RED>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RED == RED_NONE ? 3 : 2, RED == RED_NONE ? 3 : 2))) void k_hop_mfma(HopMArgs a) {
+  using S = typename P::S;
+  using M = MM<S>;
+  __shared__ uint4 tbl[WAVES][24][TROW];
+  __shared__ uint4 trb[EPI == 2 ? WAVES : 1][16][TRW];
+
+  const int2 tile = a.tiles[blockIdx.x];  // {group * NTMAX + lane tile, site block}
+  const ILGroupDev& grp = a.groups[tile.x / NTMAX];
+  const int nt = tile.x % NTMAX;
+  const OpDev& op = a.ops[grp.op];
+  const Geo g = op.g;
+  const int hv = g.hv;
+  const int NT = grp.nt;
+  const int po = a.out_par;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n = lane & 15, gq = lane >> 4;
+  uint4(*T)[TROW] = tbl[w];
+
+  // ---- lane constants: matrix-building role (d, s, c') and the four spin-column variants
+  const int bd = lane & 7, bs = (lane >> 3) & 3, bc = lane >> 5;
+  Variant var[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    int re, im;
+    proj_entry(bd >> 1, (bd & 1) ? 1 : -1, bs, t, re, im);
+    var[t] = variant(re, im, bc);
+  }
+  // clover-building role: row o, column half h (lanes 48..63 repeat lanes 0..15: same values)
+  const int co = (lane >> 1) % 24, ch = lane & 1;
+  const int cs = co / 6, ca_ = (co % 6) >> 1, ccp = co & 1;
+  const int cblk = cs >> 1, ci = 3 * cs + ca_ - 6 * cblk;
+  const int clo_off = ((cblk * 6 + ci) * 6) * 4;  // bytes of the row's six block entries
+  // fragment rows (rows 24..31 of the second row tile read valid rows; their outputs are unused)
+  const int frow0 = n, frow1 = n + 16 < 24 ? n + 16 : n + 8;
+  int hoff[6];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) hoff[t] = ((4 * t + gq) % 3) * 256 + n * 16;
+
+  double kp = 1.0;
+  for (int i = 0; i < a.gpow; ++i) kp *= op.kappa;
+  const float gam = (float)(a.gsign * kp);
+  const float cbv = (float)a.cb;
+
+  const char* hl = (const char*)op.HL[po];
+  const char* cf = (const char*)(EPI == 2 ? op.AIF[po] : op.AF[po]);
+  const long long vs = grp.vs;
+  const char* vin = grp.base + (long long)a.vin * vs;
+  char* vout = grp.base + (long long)a.vout * vs;
+  const char* vaux2 = a.vaux2 >= 0 ? grp.base + (long long)a.vaux2 * vs : nullptr;
+  const char* vred = RED == RED_ALPHA ? (a.vrhat >= 0 ? grp.base + (long long)a.vrhat * vs : nullptr) : vaux2;
+
+  const int myslot = (int)gld1(&grp.slot[nt * 16 + n]);
+
+  // per-lane reduction partials over the wave's sites in FP32 (products of two 16-bit values are
+  // exact; at most 64 sites x 8 terms per lane); lanes, waves and blocks are summed in FP64
+  float red[3] = {0.f, 0.f, 0.f};
+
+  // zero the matrix once: the padding columns stay zero
+  for (int e = lane; e < 24 * TROW; e += 64) (&T[0][0])[e] = make_uint4(0, 0, 0, 0);
+  wave_lds_sync();
+
+  const int s0 = tile.y * BS + w * SITES_PER_WAVE;
+  const int cnt = s0 < hv ? (hv - s0 < SITES_PER_WAVE ? hv - s0 : SITES_PER_WAVE) : 0;
+  const int items = cnt;  // one item per site: this block's lane tile
+
+  uint32_t L[9], C[6] = {0, 0, 0, 0, 0, 0};  // links and clover row entries of the next site to build
+  auto load_site = [&](int site) {
+    const uint32_t* lk = (const uint32_t*)(hl + (size_t)site * 288) + bd * 9;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) L[j] = gld1(lk + j);
+    if (EPI != 0) {
+      const char* src = cf + (size_t)site * 288 + clo_off;
+      const uint2 q0 = gld2(src), q1 = gld2(src + 8), q2 = gld2(src + 16);
+      C[0] = q0.x;
+      C[1] = q0.y;
+      C[2] = q1.x;
+      C[3] = q1.y;
+      C[4] = q2.x;
+      C[5] = q2.y;
+    }
+  };
+  auto build = [&]() {
+#pragma unroll
+    for (int ca = 0; ca < 3; ++ca) {
+      uint32_t o[12];
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) o[sp * 3 + b] = apply(var[sp], L[ca * 3 + b]);
+      uint4* dst = &T[6 * bs + 2 * ca + bc][bd * 3];
+      dst[0] = make_uint4(o[0], o[1], o[2], o[3]);
+      dst[1] = make_uint4(o[4], o[5], o[6], o[7]);
+      dst[2] = make_uint4(o[8], o[9], o[10], o[11]);
+    }
+    if (EPI != 0) {
+      uint32_t o[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) o[j] = ch != cblk ? 0u : ccp ? rot16(C[j]) : (C[j] ^ 0x80000000u);
+      uint2* dst = (uint2*)((char*)&T[co][TCLO] + 24 * ch);
+      dst[0] = make_uint2(o[0], o[1]);
+      dst[1] = make_uint2(o[2], o[3]);
+      dst[2] = make_uint2(o[4], o[5]);
+    }
+  };
+
+  // prefetch cursor: site pk
+  int pk = 0;
+  auto prefetch = [&](TileIn& dst) {
+    if (pk >= cnt) return;
+    int nbs_p[6];
+    site_neighbours(g, s0 + pk, po, gq, nbs_p);
+    load_tile<EPI, RED>(dst, vin, vaux2, vred, nbs_p, hoff, s0 + pk, NT, nt, n, gq);
+    ++pk;
+  };
+  // compute cursor: site ck
+  int ck = 0;
+  auto step = [&](TileIn& cur, TileIn& pf) {
+    const int site = s0 + ck;
+    build();  // this site's matrix; then request the next site's links
+    if (ck + 1 < cnt) load_site(site + 1);
+    prefetch(pf);
+    __builtin_amdgcn_sched_barrier(0);  // keep the requests ahead of this item's work
+    wave_lds_sync();
+    f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < 6; ++kt) {
+      acc0 = M::mma(T[frow0][4 * kt + gq], cur.B[kt], acc0);
+      acc1 = M::mma(T[frow1][4 * kt + gq], cur.B[kt], acc1);
+    }
+    float v0[4], v1[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      v0[r] = gam * acc0[r];
+      v1[r] = gam * acc1[r];
+    }
+    if (EPI == 1) {
+      const f4v zero = {0.f, 0.f, 0.f, 0.f};
+      const f4v c0 = M::mma(T[frow0][TCLO + gq], cur.Bc, zero), c1 = M::mma(T[frow1][TCLO + gq], cur.Bc, zero);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v0[r] += cbv * c0[r];
+        v1[r] += cbv * c1[r];
+      }
+    }
+    if (EPI == 2) {  // o = A^{-1} (.): transpose the rounded result through LDS, second product
+      const uint2 p0 = make_uint2(M::pack2(v0[0], v0[1]), M::pack2(v0[2], v0[3]));
+      const uint2 p1 = gq < 2 ? make_uint2(M::pack2(v1[0], v1[1]), M::pack2(v1[2], v1[3])) : make_uint2(0, 0);
+      uint2* tr = (uint2*)&trb[w][n][0];
+      tr[gq] = p0;
+      tr[4 + gq] = p1;
+      wave_lds_sync();
+      const uint4 B2 = trb[w][n][gq];
+      wave_lds_sync();
+      const f4v zero = {0.f, 0.f, 0.f, 0.f};
+      const f4v c0 = M::mma(T[frow0][TCLO + gq], B2, zero), c1 = M::mma(T[frow1][TCLO + gq], B2, zero);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v0[r] = c0[r];
+        v1[r] = c1[r];
+      }
+    }
+    if (myslot >= 0) {
+      const long long sbase = ((long long)site * NT + nt) * 768;
+      const long long off0 = sbase + (gq >> 1) * 256 + n * 16 + (gq & 1) * 8;
+      const uint2 q0 = make_uint2(M::pack2(v0[0], v0[1]), M::pack2(v0[2], v0[3]));
+      const uint2 q1 = make_uint2(M::pack2(v1[0], v1[1]), M::pack2(v1[2], v1[3]));
+      gst2(vout + off0, q0);
+      if (gq < 2) gst2(vout + off0 + 512, q1);
+      if (RED == RED_ALPHA || RED == RED_OMEGA) {  // over the values as stored
+        float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          if (m == 1 && gq >= 2) continue;
+          const uint2 q = m ? q1 : q0;
+          const uint2 x = m ? cur.x1 : cur.x0;
+          const float o0 = M::lo(q.x), o1 = M::hi(q.x), o2 = M::lo(q.y), o3 = M::hi(q.y);
+          const float x0 = M::lo(x.x), x1 = M::hi(x.x), x2 = M::lo(x.y), x3 = M::hi(x.y);
+          if (RED == RED_ALPHA) {  // (rhat, o)
+            r0 += x0 * o0 + x1 * o1 + x2 * o2 + x3 * o3;
+            r1 += x0 * o1 - x1 * o0 + x2 * o3 - x3 * o2;
+          } else {  // (o, aux2), |o|^2
+            r0 += o0 * x0 + o1 * x1 + o2 * x2 + o3 * x3;
+            r1 += o0 * x1 - o1 * x0 + o2 * x3 - o3 * x2;
+            r2 += o0 * o0 + o1 * o1 + o2 * o2 + o3 * o3;
+          }
+        }
+        red[0] += r0;
+        red[1] += r1;
+        red[2] += r2;
+      }
+    }
+    ++ck;
+  };
+
+  if (items > 0) {
+    TileIn R0, R1, R2;
+    load_site(s0);
+    prefetch(R0);
+    prefetch(R1);
+    for (int i = 0; i < items; i += 3) {
+      step(R0, R2);
+      if (i + 1 < items) step(R1, R0);
+      if (i + 2 < items) step(R2, R1);
+    }
+  }
+
+  if (RED == RED_ALPHA || RED == RED_OMEGA) {
+    __syncthreads();  // every wave is done with its matrix: reuse the LDS as scratch
+    double* scr = (double*)&tbl[0][0][0];  // [wave][lane][3]
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double x = (double)red[q];
+      x += __shfl_xor(x, 16, 64);
+      x += __shfl_xor(x, 32, 64);
+      if (lane < 16) scr[(w * 16 + lane) * 3 + q] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 48) {
+      const int m = threadIdx.x / 3, q = threadIdx.x % 3;
+      const int sl = grp.slot[nt * 16 + m];
+      if (sl >= 0) {
+        double sum = 0.0;
+#pragma unroll
+        for (int j = 0; j < WAVES; ++j) sum += scr[(j * 16 + m) * 3 + q];
+        store_partial(a.rb, a.slots[sl].sid, tile.y, q, sum);
+      }
+    }
+  }
+}
+
+template <class P>
+static void launch_mfma_p(const HopMArgs& a, int ntiles, int epi, hipStream_t s) {
+  const dim3 g(ntiles), b(BS);
+  if (epi == 2) {
+    hipLaunchKernelGGL((k_hop_mfma<P, 2, RED_NONE>), g, b, 0, s, a);
+  } else if (epi == 1) {
+    if (a.red == RED_ALPHA)
+      hipLaunchKernelGGL((k_hop_mfma<P, 1, RED_ALPHA>), g, b, 0, s, a);
+    else if (a.red == RED_OMEGA)
+      hipLaunchKernelGGL((k_hop_mfma<P, 1, RED_OMEGA>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_hop_mfma<P, 1, RED_NONE>), g, b, 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_hop_mfma<P, 0, RED_NONE>), g, b, 0, s, a);
+  }
+}
+
+bool hop_mfma_supports(int prec, int inv, bool clov, int red, bool aux1) {
+  if ((prec != 2 && prec != 3) || aux1) return false;
+  if (inv) return red == RED_NONE;
+  if (clov) return red == RED_NONE || red == RED_ALPHA || red == RED_OMEGA;
+  return red == RED_NONE;
+}
+
+void launch_hop_mfma(int prec, const HopMArgs& a, int ntiles, int inv, bool clov, hipStream_t s) {
+  if (ntiles <= 0) return;
+  const int epi = inv ? 2 : clov ? 1 : 0;
+  if (prec == 2) launch_mfma_p<PrecF16>(a, ntiles, epi, s);
+  if (prec == 3) launch_mfma_p<PrecB16>(a, ntiles, epi, s);
+}
+
+}  // namespace a2a

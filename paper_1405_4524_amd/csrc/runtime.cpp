@@ -231,6 +231,45 @@ int Ctx::gauge_links(GaugeField* gf, int prec, void** out0, void** out1) {
   return A2A_OK;
 }
 
+int Ctx::hop_links(GaugeField* gf, int prec) {
+  if (prec != 2 && prec != 3) return A2A_OK;
+  if (gf->HL[prec][0]) return A2A_OK;
+  void* d[2] = {nullptr, nullptr};
+  for (int p = 0; p < 2; ++p) {
+    int rc = dalloc(&d[p], (size_t)gf->g.hv * 288);
+    if (rc) {
+      dfree(d[0]);
+      return rc;
+    }
+  }
+  for (int p = 0; p < 2; ++p) launch_hop_links(prec, gf->g, gf->canon, p, d[p], stream);
+  A2A_HIP(this, hipGetLastError());
+  gf->HL[prec][0] = d[0];
+  gf->HL[prec][1] = d[1];
+  return A2A_OK;
+}
+
+int Ctx::clover_full(KappaOp* k, int prec, long hv) {
+  if (prec != 2 && prec != 3) return A2A_OK;
+  if (k->AF[prec][0]) return A2A_OK;
+  void* d[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int i = 0; i < 4; ++i) {
+    int rc = dalloc(&d[i], (size_t)hv * 288);
+    if (rc) {
+      for (int j = 0; j < i; ++j) dfree(d[j]);
+      return rc;
+    }
+  }
+  for (int p = 0; p < 2; ++p) {
+    launch_clover_full(prec, hv, k->A64[p], d[p], stream);
+    launch_clover_full(prec, hv, k->Ai64[p], d[2 + p], stream);
+    k->AF[prec][p] = d[p];
+    k->AIF[prec][p] = d[2 + p];
+  }
+  A2A_HIP(this, hipGetLastError());
+  return A2A_OK;
+}
+
 static void free_kop(Ctx* c, KappaOp* k) {
   for (int p = 0; p < 2; ++p) {
     c->dfree(k->A64[p]);
@@ -238,6 +277,9 @@ static void free_kop(Ctx* c, KappaOp* k) {
     for (int q = 1; q < 4; ++q) {
       c->dfree(k->Alo[q][p]);
       c->dfree(k->Ailo[q][p]);
+      c->dfree(k->AF[q][p]);
+      c->dfree(k->AIF[q][p]);
+      k->AF[q][p] = k->AIF[q][p] = nullptr;
     }
     k->A64[p] = k->Ai64[p] = nullptr;
   }
@@ -326,6 +368,10 @@ Solver::~Solver() {
   ctx->dfree(d_il_slots);
   ctx->dfree(d_il_tiles);
   ctx->dfree(d_sub_il_slots);
+  ctx->dfree(d_ilgroups);
+  ctx->dfree(d_il_hop_tiles);
+  ctx->dfree(d_groups_nonil);
+  ctx->dfree(d_hop_nonil);
   for (auto& o : ops)
     if (o.kop) o.kop->refs--;
 }
@@ -342,9 +388,25 @@ static int grow(Ctx* c, void** p, size_t* cap, size_t need) {
   return A2A_OK;
 }
 
+static void set_mfma_fields(OpDev& d, int prec, const KappaOp* kop, const GaugeField* gf) {
+  for (int p = 0; p < 2; ++p) {
+    d.HL[p] = (prec == 2 || prec == 3) ? gf->HL[prec][p] : nullptr;
+    d.AF[p] = (prec == 2 || prec == 3) ? kop->AF[prec][p] : nullptr;
+    d.AIF[p] = (prec == 2 || prec == 3) ? kop->AIF[prec][p] : nullptr;
+  }
+}
+
 int Solver::op_index(int clover_h, double kappa, KappaOp* kop, const GaugeField* gf) {
   for (int i = 0; i < (int)ops.size(); ++i)
-    if (ops[i].clover_h == clover_h && ops[i].kappa == kappa) return i;
+    if (ops[i].clover_h == clover_h && ops[i].kappa == kappa) {
+      OpDev d = ops[i].dev;
+      set_mfma_fields(d, prec, kop, gf);
+      if (std::memcmp(&d, &ops[i].dev, sizeof(OpDev)) != 0) {  // fields built since
+        ops[i].dev = d;
+        dirty = true;
+      }
+      return i;
+    }
   OpEntry e{};
   e.clover_h = clover_h;
   e.kappa = kappa;
@@ -360,6 +422,7 @@ int Solver::op_index(int clover_h, double kappa, KappaOp* kop, const GaugeField*
     e.dev.A[0][p] = prec == 0 ? kop->A64[p] : kop->Alo[prec][p];
     e.dev.Ai[0][p] = prec == 0 ? kop->Ai64[p] : kop->Ailo[prec][p];
   }
+  set_mfma_fields(e.dev, prec, kop, gf);
   e.nblk = (gf->g.hv + BS - 1) / BS;
   ops.push_back(e);
   dirty = true;
@@ -497,6 +560,62 @@ int Solver::rebuild() {
   }
   xcd_order(htiles, ctx->xcd_order);
   vec_lists(live, ops, every, ctx->xcd_order, vtiles, nonil, ils, ilt);
+  // interleaved groups for the matrix-core stencil, and R-groups of the remaining slots
+  std::vector<ILGroupDev> ilg;
+  std::vector<int2> ilh, hnon;
+  std::vector<int> gnon;
+  il_mfma = true;
+  for (int o = 0; o < (int)ops.size(); ++o) {
+    std::map<char*, int> gidx;
+    std::vector<int> rest;
+    const int e0 = (int)ilg.size();
+    for (size_t i = 0; i < n; ++i) {
+      const Slot* s = live[i];
+      if (s->op != o) continue;
+      if (!s->il_base) {
+        rest.push_back((int)i);
+        continue;
+      }
+      auto it = gidx.find(s->il_base);
+      if (it == gidx.end()) {
+        ILGroupDev d{};
+        d.op = o;
+        d.nt = s->il_nt;
+        d.base = s->il_base;
+        d.vs = (long long)s->lo_stride;
+        for (int l = 0; l < IL_LANES; ++l) d.slot[l] = -1;
+        it = gidx.emplace(s->il_base, (int)ilg.size()).first;
+        ilg.push_back(d);
+      }
+      ilg[it->second].slot[s->il_lane] = (int)i;
+    }
+    const int e1 = (int)ilg.size();
+    if (e1 > e0 && !(ops[o].dev.HL[0] && ops[o].dev.AF[0] && ops[o].dev.AIF[0])) il_mfma = false;
+    const int g0 = (int)(gnon.size() / R);
+    const int ng = (int)((rest.size() + R - 1) / R);
+    for (int gi = 0; gi < ng; ++gi)
+      for (int r = 0; r < R; ++r) {
+        size_t k = (size_t)gi * R + r;
+        gnon.push_back(k < rest.size() ? rest[k] : -1);
+      }
+    // matrix-core stencil: tile-major, one lane tile per block
+    for (int e = e0; e < e1; ++e)
+      for (int t = 0; t < ilg[e].nt; ++t)
+        for (int b = 0; b < ops[o].nblk; ++b) ilh.push_back(make_int2(e * (IL_LANES / 16) + t, b));
+    for (int b = 0; b < ops[o].nblk; ++b)
+      for (int gi = 0; gi < ng; ++gi) hnon.push_back(make_int2(g0 + gi, b));
+  }
+  xcd_order(hnon, ctx->xcd_order);  // the matrix-core tiles stay in tile-major order, unslabbed
+  A2A_TRY(grow(ctx, (void**)&d_ilgroups, &cap_ilg, sizeof(ILGroupDev) * std::max<size_t>(1, ilg.size())));
+  A2A_TRY(grow(ctx, (void**)&d_il_hop_tiles, &cap_ilh, sizeof(int2) * std::max<size_t>(1, ilh.size())));
+  A2A_TRY(grow(ctx, (void**)&d_groups_nonil, &cap_gnonil, sizeof(int) * std::max<size_t>(1, gnon.size())));
+  A2A_TRY(grow(ctx, (void**)&d_hop_nonil, &cap_hnonil, sizeof(int2) * std::max<size_t>(1, hnon.size())));
+  A2A_TRY(upload(ctx, d_ilgroups, ilg.data(), sizeof(ILGroupDev) * ilg.size()));
+  A2A_TRY(upload(ctx, d_il_hop_tiles, ilh.data(), sizeof(int2) * ilh.size()));
+  A2A_TRY(upload(ctx, d_groups_nonil, gnon.data(), sizeof(int) * gnon.size()));
+  A2A_TRY(upload(ctx, d_hop_nonil, hnon.data(), sizeof(int2) * hnon.size()));
+  n_il_hop_tiles = (int)ilh.size();
+  n_hop_nonil = (int)hnon.size();
   A2A_TRY(grow(ctx, (void**)&d_vec_nonil, &cap_nonil, sizeof(int2) * std::max<size_t>(1, nonil.size())));
   A2A_TRY(grow(ctx, (void**)&d_il_slots, &cap_ils, sizeof(int) * std::max<size_t>(1, ils.size())));
   A2A_TRY(grow(ctx, (void**)&d_il_tiles, &cap_ilt, sizeof(int2) * std::max<size_t>(1, ilt.size())));
@@ -592,7 +711,34 @@ int Solver::hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par,
   const int c = (cls && cls[0] == '1') ? 0 : 1;
   hipEvent_t ev = nullptr;
   if (cls) A2A_TRY(ctx->timing_begin(c, &ev));
-  launch_hop(kprec, Rk, a, n_tiles, ctx->stream);
+  const bool clov = (vaux2 >= 0 && cb != 0.0);
+  if (!sub && psel == 0 && kprec == prec && ctx->mfma && il_mfma && n_il_hop_tiles > 0 &&
+      hop_mfma_supports(kprec, inv, clov, red, vaux1 >= 0)) {
+    // interleaved groups on the matrix cores, the other slots with the per-thread stencil
+    HopMArgs m{};
+    m.ops = d_ops;
+    m.slots = d_slots;
+    m.groups = d_ilgroups;
+    m.tiles = d_il_hop_tiles;
+    m.out_par = out_par;
+    m.vin = vin;
+    m.vout = vout;
+    m.vaux1 = vaux1;
+    m.vaux2 = vaux2;
+    m.vrhat = vrhat;
+    m.ca = ca;
+    m.cb = cb;
+    m.gsign = gsign;
+    m.gpow = gpow;
+    m.red = red;
+    m.rb = ctx->redbuf();
+    launch_hop_mfma(kprec, m, n_il_hop_tiles, inv, clov, ctx->stream);
+    a.groups = d_groups_nonil;
+    a.tiles = d_hop_nonil;
+    launch_hop(kprec, Rk, a, n_hop_nonil, ctx->stream);
+  } else {
+    launch_hop(kprec, Rk, a, n_tiles, ctx->stream);
+  }
   A2A_HIP(ctx, hipGetLastError());
   if (cls && ctx->timing) {
     // compulsory bytes: links and clover once per site, every spinor stream once per RHS

@@ -42,6 +42,7 @@ struct GaugeField {
   Geo g{};
   double* canon = nullptr;        // canonical FP64 links on the device
   void* U[4][2] = {};              // [precision][parity], built on first use
+  void* HL[4][2] = {};             // [precision][parity] per-site hop links (16-bit precisions)
 };
 
 struct KappaOp {
@@ -50,6 +51,8 @@ struct KappaOp {
   double* Ai64[2] = {};
   void* Alo[4][2] = {};
   void* Ailo[4][2] = {};
+  void* AF[4][2] = {};   // full 6x6 clover blocks (16-bit precisions, matrix-core stencil)
+  void* AIF[4][2] = {};
   int refs = 0;
   unsigned long long last_use = 0;
 };
@@ -117,9 +120,16 @@ struct Solver {
   int* d_il_slots = nullptr;    // interleaved lane tiles: 16 slot indices each
   int2* d_il_tiles = nullptr;   // {lane tile, site block}
   int* d_sub_il_slots = nullptr;
+  ILGroupDev* d_ilgroups = nullptr;  // interleaved groups of live slots (matrix-core stencil)
+  int2* d_il_hop_tiles = nullptr;    // {group, site block}
+  int* d_groups_nonil = nullptr;     // R-groups of the slots outside interleaved groups
+  int2* d_hop_nonil = nullptr;
   size_t cap_ops = 0, cap_slots = 0, cap_groups = 0, cap_hop = 0, cap_vec = 0, cap_subg = 0, cap_subt = 0,
-         cap_subl = 0, cap_nonil = 0, cap_ils = 0, cap_ilt = 0, cap_subils = 0;
+         cap_subl = 0, cap_nonil = 0, cap_ils = 0, cap_ilt = 0, cap_subils = 0, cap_ilg = 0, cap_ilh = 0,
+         cap_gnonil = 0, cap_hnonil = 0;
   int n_hop_tiles = 0, n_vec_tiles = 0, n_vec_nonil = 0, n_il_tiles = 0;
+  int n_il_hop_tiles = 0, n_hop_nonil = 0;
+  bool il_mfma = false;  // every interleaved group's operator has its matrix-core fields
   // tile and slot counts of the last uploaded subset; its tile buffer holds
   // [hop tiles | per-slot tiles | per-slot tiles of non-interleaved slots | interleaved tiles]
   int sub_nh = 0, sub_nv = 0, sub_n = 0, sub_nn = 0, sub_ni = 0;
@@ -177,7 +187,8 @@ struct Ctx {
   int timing = 0;
   int debug = 0;  // A2A_DEBUG=1 in the environment: residual trace on stderr
   int autotune = 0;                  // pick the stencil RHS-block width per workload
-  int interleave = 0;                // FP16/BF16 inner vectors in the interleaved group layout
+  int interleave = 1;                // FP16/BF16 inner vectors in the interleaved group layout
+  int mfma = 1;                      // interleaved groups use the matrix-core stencil
   std::map<std::string, int> tuned;  // tune key -> RHS-block width
   std::string tune_path;             // A2A_TUNE_CACHE: JSON file of tuned widths
   // reduction scratch
@@ -232,6 +243,8 @@ struct Ctx {
     return it == clovers.end() ? nullptr : it->second.get();
   }
   int gauge_links(GaugeField* gf, int prec, void** out0, void** out1);
+  int hop_links(GaugeField* gf, int prec);               // gf->HL[prec][*]
+  int clover_full(KappaOp* k, int prec, long hv);        // k->AF / k->AIF [prec][*]
   int kappa_op(CloverField* cf, double kappa, int prec, KappaOp** out);
   size_t evict_unused_kops();
   int timing_begin(int cls, hipEvent_t* a);

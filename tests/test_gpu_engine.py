@@ -77,7 +77,7 @@ def test_engine_mixed_stream_matches_alone(ctx, orc, fields, il):
     try:
         _engine_mixed_stream(ctx, orc, fields)
     finally:
-        ctx.set_option("interleave", 0)
+        ctx.set_option("interleave", 1)
 
 
 def _engine_mixed_stream(ctx, orc, fields):

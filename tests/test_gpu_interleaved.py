@@ -1,9 +1,10 @@
 """GPU tests of the lane-interleaved inner layout (FP16 / BF16 storage): slots of one call form
-groups of up to 64 lanes (tiles of 16) sharing one arena.  The operators it feeds must match the
-oracle to the low-precision operator tolerances, a RHS must give the same operator output
-whatever group it sits in, and solves must meet the binding criterion with the oracle's D and
-agree with the per-slot layout's solutions (both solved to 1e-10; cond(D) ~ 10-100 bounds the
-difference by ~1e-8)."""
+groups of up to 48 lanes (tiles of 16) sharing one arena, and the stencil runs on the matrix
+cores.  The operators must match the oracle to the low-precision operator tolerances (with the
+matrix-core stencil and with the per-thread stencil on the same layout), a RHS must give the
+same operator output whatever group it sits in, and solves must meet the binding criterion with
+the oracle's D and agree with the per-slot layout's solutions (both solved to 1e-10;
+cond(D) ~ 10-100 bounds the difference by ~1e-8)."""
 import numpy as np
 import pytest
 
@@ -35,15 +36,17 @@ class interleaved:
         self.ctx.set_option("interleave", self.on)
 
     def __exit__(self, *exc):
-        self.ctx.set_option("interleave", 0)
+        self.ctx.set_option("interleave", 1)
 
 
+@pytest.mark.parametrize("mfma", [1, 0])
 @pytest.mark.parametrize("prec", [2, 3])
-def test_interleaved_operators(ctx, orc, prec):
+def test_interleaved_operators(ctx, orc, prec, mfma):
     from paper_1405_4524_amd import a2a
 
     dims, tbc, kappa, csw = (6, 4, 4, 10), -1, 0.125, 1.2
-    print(f"[gpu] interleaved operators prec={prec}", flush=True)
+    print(f"[gpu] interleaved operators prec={prec} mfma={mfma}", flush=True)
+    ctx.set_option("mfma", mfma)
     U = inputs.gauge_field(dims, 0.35, 7)
     A = orc.clover(U, kappa, csw)
     Ai = orc.invert_sites(A)
@@ -73,12 +76,13 @@ def test_interleaved_operators(ctx, orc, prec):
             # a RHS gives the same output alone and in any lane of a group
             one = ctx.dslash_clover(c, kappa, psi[16:17], op=op, prec=prec)
             assert np.array_equal(one[0], ctx.dslash_clover(c, kappa, psi, op=op, prec=prec)[16])
+    ctx.set_option("mfma", 1)
     ctx.unload(g)
 
 
 @pytest.mark.parametrize("prec", [2, 3])
 def test_interleaved_solve(ctx, orc, prec):
-    """70 sources: one full 64-lane group and one group of 6 lanes."""
+    """70 sources: one full 48-lane group and one group of 22 lanes (two tiles, one partial)."""
     dims, tbc, kappa, csw = (4, 4, 4, 8), -1, 0.125, 1.5
     print(f"[gpu] interleaved solve prec={prec}", flush=True)
     U = inputs.gauge_field(dims, 0.35, 3)
@@ -89,7 +93,8 @@ def test_interleaved_solve(ctx, orc, prec):
     with interleaved(ctx):
         X, info, rc = ctx.solve_propagators(c, eta, kappa, csw, tol=1e-10, prec=prec, max_iter=5000)
     assert rc == 0, [x for x in info if not x["converged"]][:3]
-    Xp, _, rc = ctx.solve_propagators(c, eta, kappa, csw, tol=1e-10, prec=prec, max_iter=5000)
+    with interleaved(ctx, 0):
+        Xp, _, rc = ctx.solve_propagators(c, eta, kappa, csw, tol=1e-10, prec=prec, max_iter=5000)
     assert rc == 0
     for i in range(70):
         r = eta[i] - orc.apply_D(U, A, kappa, X[i], tbc)
