@@ -224,14 +224,17 @@ def main():
         out["speedup_vs_fp64_plain"] = round(value / f64_rate, 2)
         # ---- the hopping stencil alone (one parity, H_eo), compulsory bytes (V/2)(8l + 2 n s)/launch
         ds = {}
-        for p_name, p, n in (("f64", 0, 1), ("f32", 1, 1), ("f16", 2, 1), ("f16", 2, 16)):
+        for key, p, n, il in (("f64_n1", 0, 1, 0), ("f32_n1", 1, 1, 0), ("f16_n1", 2, 1, 0),
+                              ("f16_n16_per_slot", 2, 16, 0), ("f16_n48_matrix_cores", 2, 48, 1)):
             ctx.set_option("rhs_block", 4 if n > 1 else 1)
+            ctx.set_option("interleave", il)
             ms = ctx.bench_stencil(c, kappa, a2a.OP_HOP_EO, p, n, 20)
             sb = STORAGE_BYTES[p]
             byts = (V // 2) * (8 * 18 * sb + 2 * n * 24 * sb)
-            ds[f"{p_name}_n{n}"] = {"ms": round(ms, 4), "GBps": round(byts / (ms * 1e-3) / 1e9, 1),
-                                    "frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
+            ds[key] = {"ms": round(ms, 4), "GBps": round(byts / (ms * 1e-3) / 1e9, 1),
+                       "frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
         ctx.set_option("rhs_block", args.rhs_block)
+        ctx.set_option("interleave", args.interleave)
         log(f"stencil: {ds}")
         out["dslash_hop_eo"] = ds
         ctx.unload(g)

@@ -35,8 +35,8 @@ constexpr int IL_LANES = 48;  // RHS per interleaved group (three tiles of 16 la
 
 struct ILGroupDev {
   int op;
-  int nt;  // lane tiles in use
-  int pad0, pad1;
+  int nt;                  // lane tiles in use
+  int bxh, by, bz, bt;     // site bricks of the stencil sweep (divide Xh, Y, Z, T)
   char* base;             // arena: [vector][site][tile][3 chunks][16 lanes] of 16-byte chunks
   long long vs;           // bytes per vector
   int slot[IL_LANES];     // slot-table index of each lane, -1 = idle

@@ -91,6 +91,14 @@ __device__ __forceinline__ uint4 gld4(const void* p) {
   const v4u v = *(gptr4)p;
   return make_uint4(v.x, v.y, v.z, v.w);
 }
+__device__ __forceinline__ void gst4(void* p, const uint4& v) {
+  v4u w;
+  w.x = v.x;
+  w.y = v.y;
+  w.z = v.z;
+  w.w = v.w;
+  *(__attribute__((address_space(1))) v4u*)p = w;
+}
 __device__ __forceinline__ void gst2(void* p, const uint2& v) {
   v2u w;
   w.x = v.x;
@@ -157,28 +165,28 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 }  // namespace
 
-// Data one 16-lane tile of one site needs: the six K steps of neighbour data, the clover
-// input (EPI_CLOV), the other operand of the reduction and the axpy term, in output layout.
+// Data one 16-lane tile of one site needs, each as the lane's 16 bytes in the B-fragment layout
+// (chunk gq of its RHS; lanes gq = 3 repeat chunk 0): the six K steps of neighbour data, the
+// clover input (EPI_CLOV) and the other operand of the ALPHA reduction (OMEGA's is the clover
+// input).  One 16-byte load per lane and operand keeps the count of memory instructions, which
+// is what the address units spend their cycles on, low.
 struct TileIn {
+  uint4 SD;  // this lane's 16 bytes of the site's links (lanes 0..17) and clover (18..35)
   uint4 B[6];
   uint4 Bc;
-  uint2 x0, x1;  // reduction partner (rows of row tile 0 and 1)
+  uint4 Bx;
+  int site;
 };
 
 template <int EPI, int RED>
-__device__ __forceinline__ void load_tile(TileIn& d, const char* vin, const char* vaux2,
-                                          const char* vred, const int (&nbs)[6], const int (&hoff)[6], int site,
-                                          int NT, int nt, int n, int gq) {
+__device__ __forceinline__ void load_tile(TileIn& d, const char* vin, const char* vaux2, const char* vrh,
+                                          const int (&nbs)[6], const int (&hoff)[6], int site, int NT, int nt,
+                                          int n, int gq) {
 #pragma unroll
   for (int kt = 0; kt < 6; ++kt) d.B[kt] = gld4(vin + ((long long)nbs[kt] * NT + nt) * 768 + hoff[kt]);
-  const long long sbase = ((long long)site * NT + nt) * 768;
-  const long long off0 = sbase + (gq >> 1) * 256 + n * 16 + (gq & 1) * 8;
-  const long long off1 = sbase + 512 + n * 16 + (gq & 1) * 8;  // rows 16.. (lanes gq < 2)
-  if (EPI == 1) d.Bc = gq < 3 ? gld4(vaux2 + sbase + gq * 256 + n * 16) : make_uint4(0, 0, 0, 0);
-  if (RED == RED_ALPHA || RED == RED_OMEGA) {
-    d.x0 = gld2(vred + off0);
-    d.x1 = gq < 2 ? gld2(vred + off1) : make_uint2(0, 0);
-  }
+  const long long own = ((long long)site * NT + nt) * 768 + (gq < 3 ? gq : 0) * 256 + n * 16;
+  if (EPI == 1) d.Bc = gld4(vaux2 + own);
+  if (RED == RED_ALPHA) d.Bx = gld4(vrh + own);
 }
 
 // cb indices of the neighbour site each lane's chunk of K step kt comes from: chunk 4 kt + gq
@@ -206,19 +214,39 @@ __device__ __forceinline__ void site_neighbours(const Geo& g, int site, int po, 
   nbs[5] = gq >= 1 ? nb[7] : nb[6];
 }
 
-// A block takes one 16-lane tile of a group over BS consecutive sites (64 per wave).  Blocks
-// run tile-major (all site blocks of tile 0, then tile 1, ...) and are not grouped by XCD, so
-// the chip sweeps one window of the lattice at a time with a per-site footprint of 768 bytes,
-// and the z and t neighbours are still in the last-level cache when they are read.  The
-// neighbour data of site i + 2 is requested while site i is computed (a ring of three register
-// buffers), the next site's links and clover while the current site's matrix is built, and the
-// matrix fragments are read from LDS right before their products.
+// A block takes one 16-lane tile of a group over BS sites (64 per wave) of a 4D brick of the
+// lattice (the whole x row, then y, z, t extents), so that most neighbours of a block's sites
+// are sites of the same block; bricks follow in lexicographic order.  Blocks run tile-major
+// (all site blocks of tile 0, then tile 1, ...) and are not grouped by XCD, so the chip sweeps
+// one window of the lattice at a time with a per-site footprint of 768 bytes.  The links,
+// clover and neighbour data of site i + 2 are requested while site i is computed (a ring of
+// three register buffers), and the matrix fragments are read from LDS right before their
+// products.
+
+// cb index of position p of the brick sweep
+__device__ __forceinline__ int brick_site(const Geo& g, int bxh, int by, int bz, int bt, int p) {
+  const int B = bxh * by * bz * bt;
+  int br = p / B, r = p - br * B;
+  const int rx = r % bxh;
+  r /= bxh;
+  const int ry = r % by;
+  r /= by;
+  const int rz = r % bz, rt = r / bz;
+  const int nbx = g.Xh / bxh, nby = g.Y / by, nbz = g.Z / bz;
+  const int ix = br % nbx;
+  br /= nbx;
+  const int iy = br % nby;
+  br /= nby;
+  const int iz = br % nbz, it = br / nbz;
+  return (((it * bt + rt) * g.Z + iz * bz + rz) * g.Y + iy * by + ry) * g.Xh + ix * bxh + rx;
+}
 template <class P, int EPI, int RED>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RED == RED_NONE ? 3 : 2, RED == RED_NONE ? 3 : 2))) void k_hop_mfma(HopMArgs a) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_hop_mfma(HopMArgs a) {
   using S = typename P::S;
   using M = MM<S>;
-  __shared__ uint4 tbl[WAVES][24][TROW];
-  __shared__ uint4 trb[EPI == 2 ? WAVES : 1][16][TRW];
+  __shared__ uint4 tbl[WAVES][24][TROW];  // the site's matrix
+  __shared__ uint4 stg[WAVES][64];        // the site's links (chunks 0..17) and clover (18..35)
+  __shared__ uint4 trb[WAVES][16][TRW];   // register-layout transposes, one row per RHS lane
 
   const int2 tile = a.tiles[blockIdx.x];  // {group * NTMAX + lane tile, site block}
   const ILGroupDev& grp = a.groups[tile.x / NTMAX];
@@ -232,6 +260,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RED == RED_N
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n = lane & 15, gq = lane >> 4;
   uint4(*T)[TROW] = tbl[w];
+  uint2* tr2 = (uint2*)&trb[w][n][0];  // this lane's transpose row as 8-byte pieces
 
   // ---- lane constants: matrix-building role (d, s, c') and the four spin-column variants
   const int bd = lane & 7, bs = (lane >> 3) & 3, bc = lane >> 5;
@@ -246,12 +275,13 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RED == RED_N
   const int co = (lane >> 1) % 24, ch = lane & 1;
   const int cs = co / 6, ca_ = (co % 6) >> 1, ccp = co & 1;
   const int cblk = cs >> 1, ci = 3 * cs + ca_ - 6 * cblk;
-  const int clo_off = ((cblk * 6 + ci) * 6) * 4;  // bytes of the row's six block entries
+  const int cdw = 72 + (cblk * 6 + ci) * 6;  // staged dword of the row's six block entries
   // fragment rows (rows 24..31 of the second row tile read valid rows; their outputs are unused)
   const int frow0 = n, frow1 = n + 16 < 24 ? n + 16 : n + 8;
   int hoff[6];
 #pragma unroll
   for (int t = 0; t < 6; ++t) hoff[t] = ((4 * t + gq) % 3) * 256 + n * 16;
+  const int ochunk = gq < 3 ? gq : 0;  // the chunk this lane loads / stores (gq = 3 repeats 0)
 
   double kp = 1.0;
   for (int i = 0; i < a.gpow; ++i) kp *= op.kappa;
@@ -264,7 +294,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RED == RED_N
   const char* vin = grp.base + (long long)a.vin * vs;
   char* vout = grp.base + (long long)a.vout * vs;
   const char* vaux2 = a.vaux2 >= 0 ? grp.base + (long long)a.vaux2 * vs : nullptr;
-  const char* vred = RED == RED_ALPHA ? (a.vrhat >= 0 ? grp.base + (long long)a.vrhat * vs : nullptr) : vaux2;
+  const char* vrh = a.vrhat >= 0 ? grp.base + (long long)a.vrhat * vs : nullptr;
 
   const int myslot = (int)gld1(&grp.slot[nt * 16 + n]);
 
@@ -280,23 +310,17 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RED == RED_N
   const int cnt = s0 < hv ? (hv - s0 < SITES_PER_WAVE ? hv - s0 : SITES_PER_WAVE) : 0;
   const int items = cnt;  // one item per site: this block's lane tile
 
-  uint32_t L[9], C[6] = {0, 0, 0, 0, 0, 0};  // links and clover row entries of the next site to build
-  auto load_site = [&](int site) {
-    const uint32_t* lk = (const uint32_t*)(hl + (size_t)site * 288) + bd * 9;
+  // a site's links and clover: 36 chunks of 16 bytes, one per lane (lanes 36.. repeat)
+  const int sdl = lane < 36 ? lane : lane - 36;
+  const bool sd_clover = EPI != 0 && sdl >= 18;
+  const char* sd_base = sd_clover ? cf + (sdl - 18) * 16 : hl + (sdl % 18) * 16;
+  auto build = [&](const uint4& SD) {
+    stg[w][lane] = SD;
+    wave_lds_sync();
+    const uint32_t* st32 = (const uint32_t*)&stg[w][0];
+    uint32_t L[9];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) L[j] = gld1(lk + j);
-    if (EPI != 0) {
-      const char* src = cf + (size_t)site * 288 + clo_off;
-      const uint2 q0 = gld2(src), q1 = gld2(src + 8), q2 = gld2(src + 16);
-      C[0] = q0.x;
-      C[1] = q0.y;
-      C[2] = q1.x;
-      C[3] = q1.y;
-      C[4] = q2.x;
-      C[5] = q2.y;
-    }
-  };
-  auto build = [&]() {
+    for (int j = 0; j < 9; ++j) L[j] = st32[bd * 9 + j];
 #pragma unroll
     for (int ca = 0; ca < 3; ++ca) {
       uint32_t o[12];
@@ -312,7 +336,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RED == RED_N
     if (EPI != 0) {
       uint32_t o[6];
 #pragma unroll
-      for (int j = 0; j < 6; ++j) o[j] = ch != cblk ? 0u : ccp ? rot16(C[j]) : (C[j] ^ 0x80000000u);
+      for (int j = 0; j < 6; ++j) {
+        const uint32_t c = st32[cdw + j];
+        o[j] = ch != cblk ? 0u : ccp ? rot16(c) : (c ^ 0x80000000u);
+      }
       uint2* dst = (uint2*)((char*)&T[co][TCLO] + 24 * ch);
       dst[0] = make_uint2(o[0], o[1]);
       dst[1] = make_uint2(o[2], o[3]);
@@ -322,19 +349,26 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RED == RED_N
 
   // prefetch cursor: site pk
   int pk = 0;
+  const int bxh = grp.bxh, bby = grp.by, bbz = grp.bz, bbt = grp.bt;
+  auto site_at = [&](int p) { return __builtin_amdgcn_readfirstlane(brick_site(g, bxh, bby, bbz, bbt, p)); };
+  // Loads and stores in the sweep are unconditional (positions past the wave's range are clamped
+  // to its last site, whose values are then recomputed and rewritten unchanged), so the number
+  // of memory operations in flight is the same on every path and the waits on them stay exact.
   auto prefetch = [&](TileIn& dst) {
-    if (pk >= cnt) return;
+    const int site = site_at(s0 + (pk < cnt ? pk : cnt - 1));
+    dst.site = site;
+    dst.SD = gld4(sd_base + (size_t)site * 288);
     int nbs_p[6];
-    site_neighbours(g, s0 + pk, po, gq, nbs_p);
-    load_tile<EPI, RED>(dst, vin, vaux2, vred, nbs_p, hoff, s0 + pk, NT, nt, n, gq);
+    site_neighbours(g, site, po, gq, nbs_p);
+    load_tile<EPI, RED>(dst, vin, vaux2, vrh, nbs_p, hoff, site, NT, nt, n, gq);
     ++pk;
   };
   // compute cursor: site ck
   int ck = 0;
   auto step = [&](TileIn& cur, TileIn& pf) {
-    const int site = s0 + ck;
-    build();  // this site's matrix; then request the next site's links
-    if (ck + 1 < cnt) load_site(site + 1);
+    const int site = cur.site;
+    const bool live = ck < cnt;
+    build(cur.SD);  // this site's matrix
     prefetch(pf);
     __builtin_amdgcn_sched_barrier(0);  // keep the requests ahead of this item's work
     wave_lds_sync();
@@ -360,11 +394,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RED == RED_N
       }
     }
     if (EPI == 2) {  // o = A^{-1} (.): transpose the rounded result through LDS, second product
-      const uint2 p0 = make_uint2(M::pack2(v0[0], v0[1]), M::pack2(v0[2], v0[3]));
-      const uint2 p1 = gq < 2 ? make_uint2(M::pack2(v1[0], v1[1]), M::pack2(v1[2], v1[3])) : make_uint2(0, 0);
-      uint2* tr = (uint2*)&trb[w][n][0];
-      tr[gq] = p0;
-      tr[4 + gq] = p1;
+      tr2[gq] = make_uint2(M::pack2(v0[0], v0[1]), M::pack2(v0[2], v0[3]));
+      tr2[4 + gq] = gq < 2 ? make_uint2(M::pack2(v1[0], v1[1]), M::pack2(v1[2], v1[3])) : make_uint2(0, 0);
       wave_lds_sync();
       const uint4 B2 = trb[w][n][gq];
       wave_lds_sync();
@@ -376,48 +407,55 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(RED == RED_N
         v1[r] = c1[r];
       }
     }
-    if (myslot >= 0) {
-      const long long sbase = ((long long)site * NT + nt) * 768;
-      const long long off0 = sbase + (gq >> 1) * 256 + n * 16 + (gq & 1) * 8;
-      const uint2 q0 = make_uint2(M::pack2(v0[0], v0[1]), M::pack2(v0[2], v0[3]));
-      const uint2 q1 = make_uint2(M::pack2(v1[0], v1[1]), M::pack2(v1[2], v1[3]));
-      gst2(vout + off0, q0);
-      if (gq < 2) gst2(vout + off0 + 512, q1);
-      if (RED == RED_ALPHA || RED == RED_OMEGA) {  // over the values as stored
-        float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+    // rows 16 m + 4 gq .. +3 of row tile m, rounded to the storage format
+    const uint2 q0 = make_uint2(M::pack2(v0[0], v0[1]), M::pack2(v0[2], v0[3]));
+    const uint2 q1 = make_uint2(M::pack2(v1[0], v1[1]), M::pack2(v1[2], v1[3]));
+    if (RED == RED_ALPHA || RED == RED_OMEGA) {  // over the values as stored
+      trb[w][n][gq] = RED == RED_ALPHA ? cur.Bx : cur.Bc;  // the partner, to output rows
+      wave_lds_sync();
+      const uint2 xr0 = tr2[gq], xr1 = tr2[4 + gq];
+      wave_lds_sync();
+      float r0 = 0.f, r1 = 0.f, r2 = 0.f;
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          if (m == 1 && gq >= 2) continue;
-          const uint2 q = m ? q1 : q0;
-          const uint2 x = m ? cur.x1 : cur.x0;
-          const float o0 = M::lo(q.x), o1 = M::hi(q.x), o2 = M::lo(q.y), o3 = M::hi(q.y);
-          const float x0 = M::lo(x.x), x1 = M::hi(x.x), x2 = M::lo(x.y), x3 = M::hi(x.y);
-          if (RED == RED_ALPHA) {  // (rhat, o)
-            r0 += x0 * o0 + x1 * o1 + x2 * o2 + x3 * o3;
-            r1 += x0 * o1 - x1 * o0 + x2 * o3 - x3 * o2;
-          } else {  // (o, aux2), |o|^2
-            r0 += o0 * x0 + o1 * x1 + o2 * x2 + o3 * x3;
-            r1 += o0 * x1 - o1 * x0 + o2 * x3 - o3 * x2;
-            r2 += o0 * o0 + o1 * o1 + o2 * o2 + o3 * o3;
-          }
+      for (int m = 0; m < 2; ++m) {
+        if (m == 1 && gq >= 2) continue;
+        const uint2 q = m ? q1 : q0;
+        const uint2 x = m ? xr1 : xr0;
+        const float o0 = M::lo(q.x), o1 = M::hi(q.x), o2 = M::lo(q.y), o3 = M::hi(q.y);
+        const float x0 = M::lo(x.x), x1 = M::hi(x.x), x2 = M::lo(x.y), x3 = M::hi(x.y);
+        if (RED == RED_ALPHA) {  // (rhat, o)
+          r0 += x0 * o0 + x1 * o1 + x2 * o2 + x3 * o3;
+          r1 += x0 * o1 - x1 * o0 + x2 * o3 - x3 * o2;
+        } else {  // (o, aux2), |o|^2
+          r0 += o0 * x0 + o1 * x1 + o2 * x2 + o3 * x3;
+          r1 += o0 * x1 - o1 * x0 + o2 * x3 - o3 * x2;
+          r2 += o0 * o0 + o1 * o1 + o2 * o2 + o3 * o3;
         }
-        red[0] += r0;
-        red[1] += r1;
-        red[2] += r2;
       }
+      const float keep = (live && myslot >= 0) ? 1.f : 0.f;
+      red[0] += keep * r0;
+      red[1] += keep * r1;
+      red[2] += keep * r2;
     }
+    // to the storage layout through LDS: one 16-byte store per lane (idle lanes write their own
+    // unread lane slots; lanes gq = 3 repeat the chunk-0 store of lane gq = 0)
+    tr2[gq] = q0;
+    tr2[4 + gq] = q1;
+    wave_lds_sync();
+    const uint4 ob = trb[w][n][ochunk];
+    wave_lds_sync();
+    gst4(vout + ((long long)site * NT + nt) * 768 + ochunk * 256 + n * 16, ob);
     ++ck;
   };
 
   if (items > 0) {
     TileIn R0, R1, R2;
-    load_site(s0);
     prefetch(R0);
     prefetch(R1);
     for (int i = 0; i < items; i += 3) {
       step(R0, R2);
-      if (i + 1 < items) step(R1, R0);
-      if (i + 2 < items) step(R2, R1);
+      step(R1, R0);
+      step(R2, R1);
     }
   }
 

@@ -463,6 +463,27 @@ void Solver::gc_ops() {
   dirty = true;
 }
 
+// Site bricks of the matrix-core stencil's sweep: the whole x row (xh extent up to 16), then
+// extents in y, z, t that divide the lattice, aiming at BS sites per brick with the extra
+// extent spread over y, z and t.
+static void brick_dims(const Geo& g, int* bxh, int* by, int* bz, int* bt) {
+  int bx = g.Xh;
+  while (bx > 16 && bx % 2 == 0) bx /= 2;
+  *bxh = bx;
+  *by = *bz = *bt = 1;
+  const int target = std::max(1, BS / bx);
+  static const int cand[][3] = {{4, 2, 2}, {2, 2, 4}, {2, 4, 2}, {4, 4, 1}, {2, 2, 2}, {4, 2, 1},
+                                {2, 2, 1}, {4, 1, 1}, {2, 1, 1}, {1, 1, 1}};
+  for (const auto& c : cand) {
+    if (c[0] * c[1] * c[2] > target) continue;
+    if (g.Y % c[0] || g.Z % c[1] || g.T % c[2]) continue;
+    *by = c[0];
+    *bz = c[1];
+    *bt = c[2];
+    return;
+  }
+}
+
 // Vector-kernel tile lists for the slots idx (indices into live): per-slot tiles of every
 // slot, per-slot tiles of the slots outside interleaved groups, and the interleaved lane
 // tiles (16 lanes of one group tile) with their site blocks.
@@ -581,6 +602,7 @@ int Solver::rebuild() {
         ILGroupDev d{};
         d.op = o;
         d.nt = s->il_nt;
+        brick_dims(ops[o].dev.g, &d.bxh, &d.by, &d.bz, &d.bt);
         d.base = s->il_base;
         d.vs = (long long)s->lo_stride;
         for (int l = 0; l < IL_LANES; ++l) d.slot[l] = -1;
