@@ -67,6 +67,7 @@ def main():
     ap.add_argument("--interleave", type=int, default=1,
                     help="1: FP16/BF16 inner vectors in lane-interleaved groups (matrix-core stencil)")
     ap.add_argument("--mfma", type=int, default=1, help="0: interleaved groups use the per-thread stencil")
+    ap.add_argument("--delta", type=float, default=0.03, help="reliable-update reduction factor")
     ap.add_argument("--fp64-sources", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and stencil side measurements")
@@ -118,6 +119,7 @@ def main():
     ctx.set_option("check_every", args.check_every)
     ctx.set_option("interleave", args.interleave)
     ctx.set_option("mfma", args.mfma)
+    ctx.set_option("delta", args.delta)
 
     if args.stencil_only:
         stencil_only(args, ctx, links, dims, tbc, kappa, csw, V)
@@ -156,7 +158,7 @@ def main():
     if args.copy_calib:
         copy_1gib(1)
     value = nsrc * args.steps / elapsed
-    kstats = {k: ctx.kernel_stats(k) for k in ("schur1", "schur2", "blas")}
+    kstats = {k: ctx.kernel_stats(k) for k in ("schur1", "schur2", "xr", "p", "s")}
     last = infos[-1]
     iters = [x["iters"] for x in last]
     resid = [x["true_rel_residual"] for x in last]
@@ -176,7 +178,9 @@ def main():
               "schur2": "k_hop_mfma<.., EPI_CLOV> (H_oe + A_oo + axpy + dot, matrix cores)"} if mfma else
              {"schur1": "k_hop<.., EPI_INV> (H_eo + A_ee^-1)",
               "schur2": "k_hop<.., EPI_CLOV> (H_oe + A_oo + axpy + dot)"})
-    names["blas"] = "k_vec (BiCGStab updates)"
+    names["xr"] = "k_vec_il<.., VK_BICG_XR> (x += alpha p + omega s; r = s - omega t; dots)"
+    names["p"] = "k_vec_il<.., VK_BICG_P> (p = r + beta (p - omega v))"
+    names["s"] = "k_vec_il<.., VK_BICG_S> (s = r - alpha v)"
     roofline = {"bound": "hbm", "kernel": names[dom],
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

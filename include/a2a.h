@@ -103,7 +103,8 @@ const char *a2a_last_error(const a2a_ctx *ctx);
 /* Tuning knobs: "rhs_block" (1, 2, 4: RHS per thread in the stencil), "rhs_block64" (1, 2:
  * RHS per thread in the FP64 stencils of set-up, reliable updates and reconstruction; default
  * 2), "check_every" (iterations between residual checks), "delta" (reliable-update reduction
- * factor), "delta64" (the same for the FP64-only mode),
+ * factor for FP16 / FP32 storage, default 0.03), "delta_bf16" (the same for BF16, default 0.1),
+ * "delta64" (the same for the FP64-only mode, default 1e-3),
  * "xcd_order" (0/1), "kernel_timing" (0/1), "autotune" (0/1), "hbm_budget" (bytes; resets
  * the budget given at a2a_init), "interleave" (0/1, default 1: FP16 / BF16 inner vectors of
  * the sources of one call or request in lane-interleaved groups of up to 48, which the stencil
@@ -213,7 +214,8 @@ int a2a_engine_destroy(a2a_engine *eng);
 /* With option "kernel_timing" = 1 the solver brackets every inner-solver launch with HIP
  * events on the context stream.  For kernel class `name` ("schur1": hop to even sites with
  * the A_ee^{-1} epilogue; "schur2": hop to odd sites with the A_oo, axpy and dot-product
- * epilogue; "blas": the BiCGStab vector updates) returns the launches, their total
+ * epilogue; "xr", "p", "s": the BiCGStab updates of x and r, of p, of s; "blas": the three
+ * updates together) returns the launches, their total
  * milliseconds and their total algorithmic bytes (links and clover once per site, each
  * spinor stream once per right-hand side) since the last reset; resets if reset != 0. */
 int a2a_kernel_stats(a2a_ctx *ctx, const char *name, long long *launches, double *total_ms, double *alg_bytes,

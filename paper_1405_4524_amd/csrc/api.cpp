@@ -407,6 +407,9 @@ extern "C" int a2a_set_option(a2a_ctx* h, const char* key, double v) {
   } else if (k == "delta") {
     if (!(v > 0 && v < 1)) return c->fail(A2A_EINVAL, "delta must be in (0, 1)");
     c->delta_lo = v;
+  } else if (k == "delta_bf16") {
+    if (!(v > 0 && v < 1)) return c->fail(A2A_EINVAL, "delta_bf16 must be in (0, 1)");
+    c->delta_bf16 = v;
   } else if (k == "delta64") {
     if (!(v > 0 && v < 1)) return c->fail(A2A_EINVAL, "delta64 must be in (0, 1)");
     c->delta_64 = v;
@@ -892,13 +895,26 @@ extern "C" int a2a_kernel_stats(a2a_ctx* h, const char* name, long long* launche
   Ctx* c = &h->c;
   A2A_TRY(c->timing_collect());
   std::string n(name);
-  int k = n == "schur1" ? 0 : n == "schur2" ? 1 : n == "blas" ? 2 : -1;
-  if (k < 0) return c->fail(A2A_EINVAL, "kernel class must be schur1, schur2 or blas");
-  if (launches) *launches = c->t_launches[k];
-  if (total_ms) *total_ms = c->t_ms[k];
-  if (alg_bytes) *alg_bytes = c->t_bytes[k];
+  int k0 = -1, k1 = -1;  // class range [k0, k1]
+  if (n == "schur1") k0 = k1 = 0;
+  if (n == "schur2") k0 = k1 = 1;
+  if (n == "xr") k0 = k1 = 2;
+  if (n == "p") k0 = k1 = 3;
+  if (n == "s") k0 = k1 = 4;
+  if (n == "blas") k0 = 2, k1 = 4;
+  if (k0 < 0) return c->fail(A2A_EINVAL, "kernel class must be schur1, schur2, xr, p, s or blas");
+  long long nl = 0;
+  double ms = 0, by = 0;
+  for (int k = k0; k <= k1; ++k) {
+    nl += c->t_launches[k];
+    ms += c->t_ms[k];
+    by += c->t_bytes[k];
+  }
+  if (launches) *launches = nl;
+  if (total_ms) *total_ms = ms;
+  if (alg_bytes) *alg_bytes = by;
   if (reset)
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < Ctx::NCLS; ++i) {
       c->t_launches[i] = 0;
       c->t_ms[i] = 0;
       c->t_bytes[i] = 0;

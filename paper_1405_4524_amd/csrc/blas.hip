@@ -28,6 +28,14 @@ __device__ __forceinline__ void dot3(const Spinor<A>& a, const Spinor<A>& b, dou
   }
 }
 
+// a spinor rounded to the storage format, as a store followed by a load would give it
+template <typename S, typename A>
+__device__ __forceinline__ void round_to(Spinor<A>& s) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k)
+    s.v[k] = mk(Conv<S>::template to<A>(Conv<S>::from(s.v[k].re)), Conv<S>::template to<A>(Conv<S>::from(s.v[k].im)));
+}
+
 // kinds whose result feeds a reduction
 template <int KIND>
 struct VecRed {
@@ -76,7 +84,7 @@ __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, in
     }
     xstore<SX, A>(sd, VL_X, site, x);
     vstore<S, A>(lw, VL_R, site, s);
-    vload<S, A>(lw, VL_R, site, s);  // reduce the stored values
+    round_to<S>(s);  // reduce the values as stored
     Spinor<A> rh;
     vload<S, A>(lw, VL_RHAT, site, rh);
     dot3(rh, s, v3);
@@ -104,7 +112,7 @@ __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, in
 #pragma unroll
     for (int k = 0; k < 12; ++k) r.v[k] = mk((A)(rh64.v[k].re * inv), (A)(rh64.v[k].im * inv));
     vstore<S, A>(lw, VL_R, site, r);
-    vload<S, A>(lw, VL_R, site, r);
+    round_to<S>(r);  // the values as stored
     Spinor<A> rh;
     if (KIND == VK_INIT) {
       Spinor<A> z;

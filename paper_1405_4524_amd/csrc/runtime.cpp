@@ -795,7 +795,8 @@ int Solver::vec(bool sub, int n_tiles, int kind, int par, int use_inv, int vin, 
   a.rb = ctx->redbuf();
   const bool timed = !sub && (kind == VK_BICG_S || kind == VK_BICG_XR || kind == VK_BICG_P);
   hipEvent_t ev = nullptr;
-  if (timed) A2A_TRY(ctx->timing_begin(2, &ev));
+  const int tcls = kind == VK_BICG_XR ? 2 : kind == VK_BICG_P ? 3 : 4;
+  if (timed) A2A_TRY(ctx->timing_begin(tcls, &ev));
   const int n_il = sub ? sub_ni : n_il_tiles;
   if (vec_kind_il(kind) && n_il > 0) {  // interleaved slots with the lane mapping, the rest per slot
     VecArgs b = a;
@@ -809,11 +810,15 @@ int Solver::vec(bool sub, int n_tiles, int kind, int par, int use_inv, int vin, 
   }
   A2A_HIP(ctx, hipGetLastError());
   if (timed) {
+    // compulsory bytes per site and RHS: s = r - alpha v reads 2 and writes 1 inner vector;
+    // p = r + beta (p - omega v) reads 3, writes 1; the x / r update reads p, s, t, rhat and x
+    // and writes r and x (x is FP32 in FP16 mode)
     const double sz = prec == 0 ? 8.0 : prec == 1 ? 4.0 : 2.0;
-    const int nvec = kind == VK_BICG_S ? 3 : kind == VK_BICG_XR ? 7 : 4;
+    const double szx = prec == 0 ? 8.0 : prec == 3 ? 2.0 : 4.0;
+    const double per = kind == VK_BICG_S ? 3 * sz : kind == VK_BICG_P ? 4 * sz : 5 * sz + 2 * szx;
     double bytes = 0;
-    for (Slot* s : live) bytes += (double)ops[s->op].dev.g.hv * nvec * 24 * sz;
-    A2A_TRY(ctx->timing_end(2, ev, bytes));
+    for (Slot* s : live) bytes += (double)ops[s->op].dev.g.hv * 24 * per;
+    A2A_TRY(ctx->timing_end(tcls, ev, bytes));
   }
   const int red = kind == VK_BICG_XR ? RED_RHO : kind == VK_RU_RESCALE ? RED_RU : kind == VK_INIT ? RED_INIT : RED_NONE;
   if (red != RED_NONE) A2A_TRY(finalize_red(sub, red));
@@ -949,7 +954,7 @@ int Solver::finalize(const std::vector<int>& idx) {
 int Solver::check() {
   A2A_TRY(ctx->read_scal());
   std::vector<int> ru, restart;
-  const double delta = prec == 0 ? ctx->delta_64 : ctx->delta_lo;
+  const double delta = prec == 0 ? ctx->delta_64 : prec == 3 ? ctx->delta_bf16 : ctx->delta_lo;
   for (int i = 0; i < (int)live.size(); ++i) {
     Slot* s = live[i];
     if (s->state != SS_RUN) continue;

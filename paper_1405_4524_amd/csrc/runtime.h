@@ -182,7 +182,9 @@ struct Ctx {
   int rhs_block = 4;
   int rhs_block64 = 2;  // RHS per thread of the FP64 stencils (1 or 2)
   int check_every = 4;
-  double delta_lo = 0.1, delta_64 = 1e-3;
+  // reliable-update trigger: the iterated residual has dropped by this factor since the last
+  // FP64 residual (FP16 and FP32 storage; BF16's 8-bit mantissa holds about two digits)
+  double delta_lo = 0.03, delta_bf16 = 0.1, delta_64 = 1e-3;
   int xcd_order = 1;
   int timing = 0;
   int debug = 0;  // A2A_DEBUG=1 in the environment: residual trace on stderr
@@ -203,9 +205,11 @@ struct Ctx {
   // kernel timing
   std::vector<EventRec> pending;
   std::vector<hipEvent_t> ev_pool;
-  long long t_launches[3] = {0, 0, 0};
-  double t_ms[3] = {0, 0, 0};
-  double t_bytes[3] = {0, 0, 0};  // algorithmic bytes of the timed launches
+  // timed classes: 0 schur1, 1 schur2, 2 x/r update, 3 p update, 4 s update
+  static constexpr int NCLS = 5;
+  long long t_launches[NCLS] = {};
+  double t_ms[NCLS] = {};
+  double t_bytes[NCLS] = {};  // algorithmic bytes of the timed launches
 
   int fail(int code, const std::string& msg) {
     err = msg;
