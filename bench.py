@@ -36,6 +36,8 @@ STORAGE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
 TRAFFIC = {
     ("schur2", "l32t64", "f16", "rb2"): {"src": "5416965449cd31f9", "bytes": 1.7666e10,
                                          "profile": "profiles/bench_l32t64_f16_rb2_hbm_counters.txt"},
+    ("schur2", "l32t64", "f16", "il"): {"src": "5a77d088f4641a52", "bytes": 1.6940e10,
+                                        "profile": "profiles/bench_l32t64_f16_interleaved_hbm_counters.txt"},
 }
 STENCIL_SOURCES = {"per-thread": ("hop.hip", "a2a_device.h", "a2a_reduce.h", "a2a_kernels.h"),
                    "mfma": ("hop_mfma.hip", "a2a_device.h", "a2a_reduce.h", "a2a_kernels.h")}
@@ -379,13 +381,20 @@ def stencil_only(args, ctx, links, dims, tbc, kappa, csw, V):
     g = ctx.load_gauge_dev(links, dims, tbc)
     c = ctx.load_clover(g, csw)
     res = {}
-    for p_name, p, n, rb in (("f64", 0, 1, 1), ("f32", 1, 1, 1), ("f16", 2, 1, 1), ("f16", 2, 16, 2)):
+    for key, p, n, rb, il, op in (("f64_n1", 0, 1, 1, 0, a2a.OP_HOP_EO), ("f32_n1", 1, 1, 1, 0, a2a.OP_HOP_EO),
+                                  ("f16_n1", 2, 1, 1, 0, a2a.OP_HOP_EO),
+                                  ("f16_n16_per_slot", 2, 16, 2, 0, a2a.OP_HOP_EO),
+                                  ("f16_n48_matrix_cores", 2, 48, 2, 1, a2a.OP_HOP_EO),
+                                  ("f16_n48_matrix_cores_schur", 2, 48, 2, 1, a2a.OP_SCHUR)):
         ctx.set_option("rhs_block", rb)
-        ms = ctx.bench_stencil(c, kappa, a2a.OP_HOP_EO, p, n, args.stencil_reps)
+        ctx.set_option("interleave", il)
+        ms = ctx.bench_stencil(c, kappa, op, p, n, args.stencil_reps)
         sb = STORAGE_BYTES[p]
         byts = (V // 2) * (8 * 18 * sb + 2 * n * 24 * sb)
-        res[f"{p_name}_n{n}"] = {"ms": round(ms, 4), "alg_bytes": byts, "GBps": round(byts / (ms * 1e-3) / 1e9, 1)}
-        log(f"stencil {p_name} n={n}: {ms:.4f} ms, {res[f'{p_name}_n{n}']['GBps']} GB/s")
+        if op == a2a.OP_SCHUR:  # H_eo + A_ee^-1, then H_oe + A_oo: two hops, clover twice, aux input
+            byts = 2 * byts + (V // 2) * (2 * 72 * sb + n * 24 * sb)
+        res[key] = {"ms": round(ms, 4), "alg_bytes": byts, "GBps": round(byts / (ms * 1e-3) / 1e9, 1)}
+        log(f"stencil {key}: {ms:.4f} ms, {res[key]['GBps']} GB/s")
     ms = copy_1gib(args.stencil_reps)
     res["copy_1GiB"] = {"ms": round(ms, 4), "GBps": round(2 * (1 << 30) / (ms * 1e-3) / 1e9, 1)}
     log(f"copy 1 GiB: {ms:.4f} ms")
