@@ -107,13 +107,23 @@ int il_alloc(Ctx* c, Slot* slots, int n, long hv, int nlo) {
   return A2A_OK;
 }
 
-// arenas of n slots of one operator: per slot, or interleaved groups for FP16 / BF16
+// arenas of n slots of one operator: per slot, or interleaved groups for FP16 / BF16.  Whole
+// 16-lane tiles go to interleaved groups; a remainder of at least IL_REM_MIN sources gets a
+// tile of its own, a smaller one stays per slot (a tile costs the same whatever its fill: the
+// per-thread stencil is cheaper per RHS below about 12 of 16 lanes).
+constexpr int IL_REM_MIN = 12;
+
 int slots_alloc(Ctx* c, Slot* slots, int n, int prec, long hv, int nblk, int nlo, int nhi) {
-  const bool il = use_interleave(c, prec);
+  const bool il = use_interleave(c, prec) && nlo > 0;
+  int n_il = 0;
+  if (il) {
+    n_il = n / 16 * 16;
+    if (n - n_il >= IL_REM_MIN) n_il = n;
+  }
   int rc = A2A_OK;
   int k = 0;
-  for (; k < n && !rc; ++k) rc = slot_alloc(c, &slots[k], prec, hv, nblk, il ? 0 : nlo, nhi);
-  if (!rc && il && nlo) rc = il_alloc(c, slots, n, hv, nlo);
+  for (; k < n && !rc; ++k) rc = slot_alloc(c, &slots[k], prec, hv, nblk, k < n_il ? 0 : nlo, nhi);
+  if (!rc && n_il > 0) rc = il_alloc(c, slots, n_il, hv, nlo);
   if (rc)
     for (int j = 0; j < k; ++j) slot_free(c, &slots[j]);
   return rc;

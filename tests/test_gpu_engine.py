@@ -90,7 +90,7 @@ def _engine_mixed_stream(ctx, orc, fields):
     for k in range(7):
         f = fields[k % 2]
         kappa = float(rng.uniform(0.120, 0.130))
-        nsrc = int(rng.integers(1, 6))
+        nsrc = 20 if k in (1, 4) else int(rng.integers(1, 6))  # 20: a 16-lane group + 4 per slot
         prec = [2, 1, 3, 0][k % 4]
         eta = inputs.z2_noise(f["dims"], nsrc, seed=100 + k)
         src = torch.from_numpy(eta).cuda()

@@ -1,6 +1,6 @@
 """GPU tests of the lane-interleaved inner layout (FP16 / BF16 storage): slots of one call form
-groups of up to 48 lanes (tiles of 16) sharing one arena, and the stencil runs on the matrix
-cores.  The operators must match the oracle to the low-precision operator tolerances (with the
+groups of up to 48 lanes (tiles of 16; a remainder below 12 sources stays per slot) sharing one
+arena, and the stencil runs on the matrix cores.  The operators must match the oracle to the low-precision operator tolerances (with the
 matrix-core stencil and with the per-thread stencil on the same layout), a RHS must give the
 same operator output whatever group it sits in, and solves must meet the binding criterion with
 the oracle's D and agree with the per-slot layout's solutions (both solved to 1e-10;
@@ -52,7 +52,7 @@ def test_interleaved_operators(ctx, orc, prec, mfma):
     Ai = orc.invert_sites(A)
     g = ctx.load_gauge(U, tbc)
     c = ctx.load_clover(g, csw)
-    n = 17  # two lane tiles, the second with one lane
+    n = 28  # two lane tiles, the second with 12 lanes
     psi = inputs.z2_noise(dims, n, seed=13)
     odd = (orc.parity_mask(dims) == 1)[..., None, None]
     g5 = np.array([1, 1, -1, -1])[:, None]
@@ -60,7 +60,7 @@ def test_interleaved_operators(ctx, orc, prec, mfma):
         for op in (a2a.OP_FULL_D, a2a.OP_SCHUR, a2a.OP_HOP_EO, a2a.OP_HOP_OE):
             for dag in (False, True):
                 got = ctx.dslash_clover(c, kappa, psi, op=op, dagger=dag, prec=prec)
-                for i in (0, 5, 15, 16):
+                for i in (0, 5, 15, 16, 27):
                     x = g5 * psi[i] if dag else psi[i]
                     if op == a2a.OP_FULL_D:
                         want = orc.apply_D(U, A, kappa, x, tbc)
@@ -73,16 +73,19 @@ def test_interleaved_operators(ctx, orc, prec, mfma):
                     if dag:
                         want = g5 * want
                     assert rel(got[i], want) < OP_TOL[prec], (op, dag, i, rel(got[i], want))
-            # a RHS gives the same output alone and in any lane of a group
-            one = ctx.dslash_clover(c, kappa, psi[16:17], op=op, prec=prec)
-            assert np.array_equal(one[0], ctx.dslash_clover(c, kappa, psi, op=op, prec=prec)[16])
+            # a RHS gives the same output in any lane of any group: lane 27 (tile 1 of a
+            # 28-lane group) against lane 0 of a 16-lane group
+            other = np.concatenate([psi[27:28], psi[:15]])
+            assert np.array_equal(ctx.dslash_clover(c, kappa, other, op=op, prec=prec)[0],
+                                  ctx.dslash_clover(c, kappa, psi, op=op, prec=prec)[27])
     ctx.set_option("mfma", 1)
     ctx.unload(g)
 
 
 @pytest.mark.parametrize("prec", [2, 3])
 def test_interleaved_solve(ctx, orc, prec):
-    """70 sources: one full 48-lane group and one group of 22 lanes (two tiles, one partial)."""
+    """70 sources: one full 48-lane group, one 16-lane group, and 6 sources in per-slot arenas
+    (a remainder below 12 lanes stays per slot) in the same solve."""
     dims, tbc, kappa, csw = (4, 4, 4, 8), -1, 0.125, 1.5
     print(f"[gpu] interleaved solve prec={prec}", flush=True)
     U = inputs.gauge_field(dims, 0.35, 3)
@@ -104,7 +107,8 @@ def test_interleaved_solve(ctx, orc, prec):
 
 
 def test_interleaved_solve_larger_lattice(ctx, orc):
-    """Several site blocks per parity (8^3x16: 16 blocks of 256) and a 40-lane group."""
+    """Several site blocks per parity (8^3x16: 16 blocks of 256), a 32-lane group and 8
+    sources per slot."""
     dims, tbc, kappa, csw = (8, 8, 8, 16), -1, 0.13, 1.5
     print("[gpu] interleaved solve 8^3x16", flush=True)
     U = inputs.gauge_field(dims, 0.35, 1)
