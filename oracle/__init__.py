@@ -61,6 +61,8 @@ def lib():
             "orc_schur": [P, I, P, P, P, D, P, P],
             "orc_solve": [P, I, P, P, D, I, P, P, D, I, P],
             "orc_bicgstab_fixed": [P, I, P, P, D, P, P, I, P],
+            "orc_solve_cgnr": [P, I, P, P, D, I, P, P, D, I, P],
+            "orc_cgnr_fixed": [P, I, P, P, D, P, P, I, P],
             "orc_stochastic_operators": [P, I, P, P, P],
             "orc_pion_from_O": [I, I, P, I, P],
             "orc_contract_pion": [P, I, P, P, I, P, P],
@@ -192,6 +194,32 @@ def bicgstab_fixed(U, A, kappa, eta, tbc, iters):
     hist = np.zeros(int(iters))
     _check(lib().orc_bicgstab_fixed(_p(_dims(U)), int(tbc), _p(U), _p(A), float(kappa), _p(eta), _p(X), int(iters),
                                     _p(hist)), "bicgstab_fixed")
+    return X, hist
+
+
+def solve_cgnr(U, A, kappa, eta, tbc, tol=1e-13, maxit=100000):
+    """X_i = D^{-1} eta_i by CG on the normal equations D^dag D x = D^dag eta (CGNR, carrying
+    the residual of the original system), restarted on the true residual.  Same returns as
+    :func:`solve`."""
+    U, A, eta = _c(U), _c(A), _c(eta)
+    single = eta.ndim == 6
+    if single:
+        eta = eta[None]
+    X = np.empty_like(eta)
+    info = np.zeros((eta.shape[0], 4))
+    rc = lib().orc_solve_cgnr(_p(_dims(U)), int(tbc), _p(U), _p(A), float(kappa), eta.shape[0], _p(eta), _p(X),
+                              float(tol), int(maxit), _p(info))
+    _check(rc, "solve_cgnr")
+    return (X[0] if single else X), info
+
+
+def cgnr_fixed(U, A, kappa, eta, tbc, iters):
+    """Exactly `iters` CGNR steps from zero on one source; returns (x, residual history)."""
+    U, A, eta = _c(U), _c(A), _c(eta)
+    X = np.empty_like(eta)
+    hist = np.zeros(int(iters))
+    _check(lib().orc_cgnr_fixed(_p(_dims(U)), int(tbc), _p(U), _p(A), float(kappa), _p(eta), _p(X), int(iters),
+                                _p(hist)), "cgnr_fixed")
     return X, hist
 
 

@@ -29,7 +29,8 @@
  * Sec. 7 (eq. of the stochastic estimator) needs X_i = D^{-1} eta_i; the oracle solves
  * the full (un-preconditioned) system with textbook BiCGStab (van der Vorst 1992) and
  * restarts from the current iterate until the true residual ||eta - D X|| / ||eta||
- * meets the tolerance.  The even-odd Schur operator is provided as its plain definition
+ * meets the tolerance; CG on the normal equations (CGNR) is the alternative solver.  The
+ * even-odd Schur operator is provided as its plain definition
  * (full-lattice operators restricted to a parity) so the GPU's Schur kernels can be
  * checked against it.
  *
@@ -611,6 +612,136 @@ int orc_bicgstab_fixed(const int *dims, int tbc, const double *U, const double *
     }
     free(r); free(rh); free(p); free(v); free(s); free(t); free(tmp);
     return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* solver: CG on the normal equations                                                    */
+/* ------------------------------------------------------------------------------------ */
+/* gamma_5 applied to every site of a spinor field, from the matrix built in gamma_init */
+static void apply_g5(const geom_t *g, const cx *in, cx *out)
+{
+    for (long s = 0; s < g->V; ++s)
+        for (int a = 0; a < 4; ++a)
+            for (int c = 0; c < 3; ++c) {
+                cx acc = 0;
+                for (int b = 0; b < 4; ++b) acc += GAM5[a][b] * in[s * 12 + b * 3 + c];
+                out[s * 12 + a * 3 + c] = acc;
+            }
+}
+
+/* D^dag in = gamma_5 D gamma_5 in.  That D is gamma_5-hermitian is itself a checked
+ * property of the operator (the dense D against its conjugate transpose). */
+static void apply_Ddag(const geom_t *g, const cx *U, const cx *A, double kappa, const cx *in, cx *out, cx *tmp,
+                       cx *tmp2)
+{
+    apply_g5(g, in, tmp2);
+    apply_D(g, U, A, kappa, tmp2, out, tmp);
+    apply_g5(g, out, tmp2);
+    memcpy(out, tmp2, sizeof(cx) * 12 * (size_t)g->V);
+}
+
+/* CG applied to D^dag D x = D^dag b, in the form that carries the residual r = b - D x of
+ * the original system (CGNR; Saad, Iterative Methods for Sparse Linear Systems, 2nd ed.,
+ * Sec. 8.3):
+ *   r = b - D x,  z = D^dag r,  p = z
+ *   repeat:  w = D p;  alpha = |z|^2 / |w|^2;  x += alpha p;  r -= alpha w;
+ *            z' = D^dag r;  beta = |z'|^2 / |z|^2;  p = z' + beta p
+ * `iters` steps from the given x (no restart); returns the iterations taken, stopping
+ * early when |r| <= target. */
+static int cgnr_steps(const geom_t *g, const cx *U, const cx *A, double kappa, const cx *b, cx *x, int iters,
+                      double target, double *resid_hist, double bn)
+{
+    size_t n = (size_t)g->V * 12;
+    cx *r = malloc(n * sizeof(cx)), *z = malloc(n * sizeof(cx)), *p = malloc(n * sizeof(cx)),
+       *w = malloc(n * sizeof(cx)), *tmp = malloc(n * sizeof(cx)), *tmp2 = malloc(n * sizeof(cx));
+    if (!r || !z || !p || !w || !tmp || !tmp2) return -3;
+    apply_D(g, U, A, kappa, x, r, tmp);
+    for (size_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
+    apply_Ddag(g, U, A, kappa, r, z, tmp, tmp2);
+    memcpy(p, z, n * sizeof(cx));
+    double zz = norm2(z, n);
+    int it = 0;
+    while (it < iters && zz > 0.0) {
+        apply_D(g, U, A, kappa, p, w, tmp);
+        double ww = norm2(w, n);
+        if (ww == 0.0) break;
+        double alpha = zz / ww;
+        for (size_t i = 0; i < n; ++i) {
+            x[i] += alpha * p[i];
+            r[i] -= alpha * w[i];
+        }
+        ++it;
+        double rn = sqrt(norm2(r, n));
+        if (resid_hist) resid_hist[it - 1] = rn / bn;
+        if (rn <= target) break;
+        apply_Ddag(g, U, A, kappa, r, z, tmp, tmp2);
+        double zz_new = norm2(z, n);
+        double beta = zz_new / zz;
+        for (size_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        zz = zz_new;
+    }
+    free(r); free(z); free(p); free(w); free(tmp); free(tmp2);
+    return it;
+}
+
+/* X_i = D^{-1} eta_i by CGNR, restarted from the current iterate on the true residual
+ * until ||eta - D X|| <= tol ||eta||; info as for orc_solve. */
+int orc_solve_cgnr(const int *dims, int tbc, const double *U, const double *A, double kappa, int nrhs,
+                   const double *eta, double *X, double tol, int maxit, double *info)
+{
+    geom_t g;
+    if (geom_init(&g, dims, tbc)) return -1;
+    gamma_init();
+    size_t n = (size_t)g.V * 12;
+    cx *tmp = malloc(n * sizeof(cx)), *r = malloc(n * sizeof(cx));
+    if (!tmp || !r) return -3;
+    int bad = 0;
+    for (int i = 0; i < nrhs; ++i) {
+        const cx *b = (const cx *)eta + i * n;
+        cx *x = (cx *)X + i * n;
+        memset(x, 0, n * sizeof(cx));
+        double bn = sqrt(norm2(b, n)), rel = 0.0;
+        int iters = 0, restarts = 0, conv = 0;
+        for (;;) {
+            apply_D(&g, (const cx *)U, (const cx *)A, kappa, x, r, tmp);
+            for (size_t k = 0; k < n; ++k) r[k] = b[k] - r[k];
+            rel = bn > 0 ? sqrt(norm2(r, n)) / bn : 0.0;
+            if (rel <= tol) {
+                conv = 1;
+                break;
+            }
+            if (iters >= maxit || restarts > 50) break;
+            ++restarts;
+            int k = cgnr_steps(&g, (const cx *)U, (const cx *)A, kappa, b, x, maxit - iters, 0.5 * tol * bn, NULL, bn);
+            if (k < 0) return k;
+            iters += k;
+        }
+        bad += !conv;
+        if (info) {
+            info[i * 4 + 0] = iters;
+            info[i * 4 + 1] = restarts;
+            info[i * 4 + 2] = conv;
+            info[i * 4 + 3] = rel;
+        }
+    }
+    free(tmp);
+    free(r);
+    return bad;
+}
+
+/* Exactly `iters` CGNR steps on one source from x = 0; the relative residual after each
+ * goes to resid_hist. */
+int orc_cgnr_fixed(const int *dims, int tbc, const double *U, const double *A, double kappa, const double *eta,
+                   double *X, int iters, double *resid_hist)
+{
+    geom_t g;
+    if (geom_init(&g, dims, tbc)) return -1;
+    gamma_init();
+    size_t n = (size_t)g.V * 12;
+    memset(X, 0, n * sizeof(cx));
+    double bn = sqrt(norm2((const cx *)eta, n));
+    int k = cgnr_steps(&g, (const cx *)U, (const cx *)A, kappa, (const cx *)eta, (cx *)X, iters, -1.0, resid_hist, bn);
+    return k < 0 ? k : 0;
 }
 
 /* ------------------------------------------------------------------------------------ */

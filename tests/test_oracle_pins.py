@@ -215,6 +215,60 @@ def test_solve_matches_dense_lu(orc, dims, tbc):
     assert np.linalg.norm(X - Xlu) / np.linalg.norm(Xlu) < 1e-12
 
 
+@pytest.mark.parametrize("dims,tbc", [((2, 2, 2, 2), -1), ((2, 2, 2, 4), 1)])
+def test_cgnr_matches_dense_lu(orc, dims, tbc):
+    U = inputs.gauge_field(dims, 0.4, seed=33)
+    kappa, csw = 0.125, 1.2
+    A = orc.clover(U, kappa, csw)
+    D = dense_operator(lambda v: orc.apply_D(U, A, kappa, v, tbc), dims)
+    eta = inputs.z2_noise(dims, 3, seed=34)
+    X, info = orc.solve_cgnr(U, A, kappa, eta, tbc, tol=1e-13)
+    Xlu = np.linalg.solve(D, eta.reshape(3, -1).T).T.reshape(eta.shape)
+    assert np.all(info[:, 3] <= 1e-13) and np.all(info[:, 2] == 1)
+    assert np.linalg.norm(X - Xlu) / np.linalg.norm(Xlu) < 1e-12
+
+
+def test_cgnr_iterate_minimises_residual_over_krylov_space(orc):
+    """After k steps from zero, CG on the normal equations gives the x of the Krylov space
+    K_k(D^dag D, D^dag b) with the smallest ||b - D x|| (its defining property): compared with
+    a dense least-squares fit over an orthonormal basis of that space, k = 1..6; the residual
+    history is non-increasing."""
+    dims, tbc = (2, 2, 2, 2), -1
+    U = inputs.gauge_field(dims, 0.5, seed=35)
+    kappa = 0.13
+    A = orc.clover(U, kappa, 1.5)
+    D = dense_operator(lambda v: orc.apply_D(U, A, kappa, v, tbc), dims)
+    b = inputs.z2_noise(dims, 1, seed=36)[0]
+    bf = b.ravel()
+    N = D.conj().T @ D
+    Q = np.zeros((bf.size, 0), complex)
+    v = D.conj().T @ bf
+    for k in range(1, 7):
+        for _ in range(2):  # Gram-Schmidt, twice
+            v = v - Q @ (Q.conj().T @ v)
+        Q = np.hstack([Q, (v / np.linalg.norm(v))[:, None]])
+        y, *_ = np.linalg.lstsq(D @ Q, bf, rcond=None)
+        xk = Q @ y
+        x, hist = orc.cgnr_fixed(U, A, kappa, b, tbc, k)
+        assert np.linalg.norm(x.ravel() - xk) / np.linalg.norm(xk) < 1e-10, k
+        assert abs(hist[-1] - np.linalg.norm(bf - D @ xk) / np.linalg.norm(bf)) < 1e-12
+        assert np.all(np.diff(hist) <= 1e-15)
+        v = N @ Q[:, -1]
+
+
+def test_cgnr_and_bicgstab_agree(orc):
+    dims, tbc = (4, 4, 4, 8), -1
+    U = inputs.gauge_field(dims, 0.35, seed=37)
+    kappa = 0.125
+    A = orc.clover(U, kappa, 1.5)
+    eta = inputs.z2_noise(dims, 2, seed=38)
+    Xb, ib = orc.solve(U, A, kappa, eta, tbc, tol=1e-12)
+    Xc, ic = orc.solve_cgnr(U, A, kappa, eta, tbc, tol=1e-12)
+    assert np.all(ic[:, 3] <= 1e-12) and np.all(ib[:, 3] <= 1e-12)
+    assert np.linalg.norm(Xc - Xb) / np.linalg.norm(Xb) < 1e-10
+    assert np.all(ic[:, 0] > ib[:, 0])  # the squared condition number costs iterations
+
+
 def test_schur_identity_against_dense_lu(orc):
     """x_o from the dense Schur system, x_e from reconstruction, equal the full LU solution;
     and the full residual of that assembled solution vanishes on both parities."""
