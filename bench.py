@@ -70,6 +70,8 @@ def main():
                     help="1: FP16/BF16 inner vectors in lane-interleaved groups (matrix-core stencil)")
     ap.add_argument("--mfma", type=int, default=1, help="0: interleaved groups use the per-thread stencil")
     ap.add_argument("--delta", type=float, default=0.03, help="reliable-update reduction factor")
+    ap.add_argument("--solver", default="bicgstab", choices=["bicgstab", "cgnr"],
+                    help="inner Krylov method (cgnr: CG on the normal equations)")
     ap.add_argument("--fp64-sources", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and stencil side measurements")
@@ -122,6 +124,7 @@ def main():
     ctx.set_option("interleave", args.interleave)
     ctx.set_option("mfma", args.mfma)
     ctx.set_option("delta", args.delta)
+    ctx.set_option("solver", a2a.SOLVER_CGNR if args.solver == "cgnr" else a2a.SOLVER_BICGSTAB)
 
     if args.stencil_only:
         stencil_only(args, ctx, links, dims, tbc, kappa, csw, V)
@@ -180,9 +183,13 @@ def main():
               "schur2": "k_hop_mfma<.., EPI_CLOV> (H_oe + A_oo + axpy + dot, matrix cores)"} if mfma else
              {"schur1": "k_hop<.., EPI_INV> (H_eo + A_ee^-1)",
               "schur2": "k_hop<.., EPI_CLOV> (H_oe + A_oo + axpy + dot)"})
-    names["xr"] = "k_vec_il<.., VK_BICG_XR> (x += alpha p + omega s; r = s - omega t; dots)"
-    names["p"] = "k_vec_il<.., VK_BICG_P> (p = r + beta (p - omega v))"
-    names["s"] = "k_vec_il<.., VK_BICG_S> (s = r - alpha v)"
+    if args.solver == "cgnr":
+        names["xr"] = "k_vec_il<.., VK_CG_XR> (x += alpha p; r' -= alpha g5 q; |r'|^2)"
+        names["p"] = "k_vec_il<.., VK_CG_P> (p = g5 u + beta p)"
+    else:
+        names["xr"] = "k_vec_il<.., VK_BICG_XR> (x += alpha p + omega s; r = s - omega t; dots)"
+        names["p"] = "k_vec_il<.., VK_BICG_P> (p = r + beta (p - omega v))"
+        names["s"] = "k_vec_il<.., VK_BICG_S> (s = r - alpha v)"
     roofline = {"bound": "hbm", "kernel": names[dom],
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -201,7 +208,7 @@ def main():
                       "tol": tol, "links": f"exp(i {w['eps']} H), seed {w['gauge_seed']}",
                       "noise": f"complex Z2 splitmix64 seed {w['noise_seed']}",
                       "precision": f"inner {args.prec} storage / f32 arithmetic, f64 reliable updates"
-                      if prec else "f64", "rhs_block": args.rhs_block,
+                      if prec else "f64", "rhs_block": args.rhs_block, "solver": args.solver,
                       "layout": "lane-interleaved groups, matrix-core stencil" if mfma else
                       ("lane-interleaved groups, per-thread stencil" if args.interleave and prec in (2, 3)
                        else "per-slot")},

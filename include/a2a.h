@@ -64,6 +64,11 @@ extern "C" {
 #define A2A_F16_F32 2    /* FP16 storage, FP32 arithmetic, FP64 reliable updates             */
 #define A2A_BF16_F32 3   /* BF16 storage, FP32 arithmetic, FP64 reliable updates             */
 
+/* ---- inner Krylov methods (option "solver") ------------------------------------------ */
+#define A2A_SOLVER_BICGSTAB 0  /* BiCGStab on the Schur system (van der Vorst 1992)             */
+#define A2A_SOLVER_CGNR 1      /* CG on the normal equations M^dag M x = M^dag b, with M^dag =
+                                  gamma_5 M gamma_5 (the Schur operator is gamma_5-hermitian)  */
+
 /* ---- operator selectors for a2a_dslash_clover ---------------------------------------- */
 #define A2A_OP_FULL_D 0  /* out = D in on the full lattice                                  */
 #define A2A_OP_SCHUR 1   /* odd sites: out_o = (A_oo - kappa^2 H_oe A_ee^{-1} H_eo) in_o; out_e = 0 */
@@ -89,6 +94,8 @@ typedef struct {
   int restarts;          /* Krylov restarts after a breakdown                           */
   double true_rel_residual; /* ||eta - D X||_2 / ||eta||_2 on the full lattice, in FP64  */
   double seconds;        /* wall time from admission to completion                      */
+  int solver;            /* A2A_SOLVER_* that finished the source (CGNR after a fallback) */
+  int reserved;
 } a2a_solve_info;
 
 /* ---- context ------------------------------------------------------------------------- */
@@ -109,7 +116,12 @@ const char *a2a_last_error(const a2a_ctx *ctx);
  * the budget given at a2a_init), "interleave" (0/1, default 1: FP16 / BF16 inner vectors of
  * the sources of one call or request in lane-interleaved groups of up to 48, which the stencil
  * applies on the matrix cores), "mfma" (0/1: 0 makes interleaved groups use the per-thread
- * stencil).
+ * stencil), "solver" (A2A_SOLVER_BICGSTAB (default) or A2A_SOLVER_CGNR: the inner method of
+ * later solve calls and engine submissions), "cgnr_fallback" (0/1, default 1: in solve calls,
+ * sources whose BiCGStab broke down repeatedly are solved again by CGNR from their current
+ * iterate; iterations count against the same max_iter), "force_breakdown" (0/1, default 0:
+ * a test hook that makes every BiCGStab source of a solve call report a breakdown at its first
+ * reliable update, so that the fallback runs).
  * Returns A2A_EINVAL for an unknown key. */
 int a2a_set_option(a2a_ctx *ctx, const char *key, double value);
 /* Bytes of device memory currently held by the context. */
@@ -150,8 +162,8 @@ int a2a_autotune(a2a_ctx *ctx, int clover_h, double kappa, int prec, int nrhs, i
 
 /* ---- solves (Sec. 7: X_i = D^{-1} eta_i) --------------------------------------------- */
 /* Solve D X_i = eta_i for nrhs sources with even-odd preconditioning (odd-site Schur
- * complement A_oo - kappa^2 H_oe A_ee^{-1} H_eo), batched BiCGStab in precision `prec`
- * and FP64 reliable updates, until the FP64 true residual of the full system satisfies
+ * complement A_oo - kappa^2 H_oe A_ee^{-1} H_eo), batched BiCGStab (or CGNR, option
+ * "solver") in precision `prec` and FP64 reliable updates, until the FP64 true residual of the full system satisfies
  * ||eta - D X||_2 <= tol ||eta||_2 for every source.  c_sw must equal the clover handle's.
  * x0_or_null: optional initial guess (resume); info: nrhs records (may be NULL).
  * A zero source gives X = 0, converged, residual 0.  Returns A2A_ENOTCONV if some source

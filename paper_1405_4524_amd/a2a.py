@@ -22,6 +22,7 @@ OK, EINVAL, ENOMEM, ENOTCONV, EBREAKDOWN, ENAN, EHANDLE, EDEVICE, EAGAIN = 0, -1
 F64, F32, F16_F32, BF16_F32 = 0, 1, 2, 3
 OP_FULL_D, OP_SCHUR, OP_HOP_EO, OP_HOP_OE = 0, 1, 2, 3
 PION_UNBIASED, PION_ALL_PAIRS = 0, 1
+SOLVER_BICGSTAB, SOLVER_CGNR = 0, 1
 PREC_NAMES = {F64: "f64", F32: "f32", F16_F32: "f16/f32", BF16_F32: "bf16/f32"}
 ERR_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOTCONV: "ENOTCONV", EBREAKDOWN: "EBREAKDOWN", ENAN: "ENAN",
              EHANDLE: "EHANDLE", EDEVICE: "EDEVICE", EAGAIN: "EAGAIN"}
@@ -39,7 +40,8 @@ class Geom(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("converged", ctypes.c_int),
-                ("restarts", ctypes.c_int), ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("restarts", ctypes.c_int), ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("solver", ctypes.c_int), ("reserved", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -68,6 +68,11 @@ enum VecKind {
   VK_ZERO_LO,       // lo[vout] = 0
   VK_FILL_LO,       // lo[vout] = deterministic pseudo-random values (benchmarks)
   VK_ZERO_X,        // inner x = 0
+  // CG on the normal equations, iterating r' = gamma5 r (so that M^dag r = gamma5 M r')
+  VK_CG_XR,         // x += alpha p; r' -= alpha gamma5 q; |r'|^2 -> RED_CG_R
+  VK_CG_P,          // p = gamma5 u + beta p  (u = M r')
+  VK_CG_INIT,       // r' = gamma5 r64/sigma; p = x_lo = 0 -> RED_CG_INIT
+  VK_CG_RESCALE,    // r' = gamma5 r64/sigma'; p *= sigma/sigma' -> RED_CG_RU
 };
 
 struct VecArgs {

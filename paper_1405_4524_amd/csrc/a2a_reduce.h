@@ -1,5 +1,5 @@
-// a2a_reduce.h -- deterministic per-slot global reductions in FP64 and the BiCGStab scalar
-// updates that consume them.
+// a2a_reduce.h -- deterministic per-slot global reductions in FP64 and the BiCGStab and
+// CGNR scalar updates that consume them.
 //
 // A reducing kernel block works on one site block of one or more slots (right-hand sides).
 // It reduces its per-thread FP64 values with a fixed shuffle tree and stores the block
@@ -26,6 +26,12 @@ enum RedKind {
   RED_RES_E,   // v = |r_e|^2
   RED_RES_O,   // v = |r_o|^2
   RED_NORM,    // v = |out|^2 into SC_TMP
+  // CG on the normal equations; gamma = |z|^2 of z = M^dag r lives in SC_RHO (real)
+  RED_CG_ALPHA,  // v[2] = |q|^2, q = M p          -> alpha = gamma / |q|^2
+  RED_CG_R,      // v[2] = |r|^2                   -> iterated residual norm
+  RED_CG_BETA,   // v[2] = |M gamma5 r|^2 = |z'|^2 -> beta = |z'|^2 / gamma, gamma = |z'|^2
+  RED_CG_INIT,   // v[2] = |r|^2                   -> fresh CGNR state (beta = 0 next)
+  RED_CG_RU,     // v[2] = |r|^2                   -> state after a reliable update
 };
 
 constexpr int RED_NV = 3;  // values stored per block partial
@@ -182,6 +188,37 @@ __device__ inline void finalize_slot(int kind, double* sc, const double* v, int 
       sc[SC_BETA + 1] = bi;
       sc[SC_RHO] = v[0];
       sc[SC_RHO + 1] = v[1];
+      sc[SC_RNORM2] = v[2];
+      sc[SC_SIGMA] = snew;
+    } break;
+    case RED_CG_ALPHA: {
+      if (v[2] == 0.0) {
+        sc[SC_FLAGS] = 1.0;
+        sc[SC_ALPHA] = 0.0;
+      } else {
+        sc[SC_ALPHA] = sc[SC_RHO] / v[2];
+      }
+      sc[SC_ALPHA + 1] = 0.0;
+    } break;
+    case RED_CG_R: sc[SC_RNORM2] = v[2]; break;
+    case RED_CG_BETA: {  // gamma == 0 marks a fresh start: p = z
+      sc[SC_BETA] = sc[SC_RHO] == 0.0 ? 0.0 : v[2] / sc[SC_RHO];
+      sc[SC_BETA + 1] = 0.0;
+      sc[SC_RHO] = v[2];
+      sc[SC_RHO + 1] = 0.0;
+    } break;
+    case RED_CG_INIT: {
+      sc[SC_RHO] = sc[SC_RHO + 1] = 0.0;
+      sc[SC_ALPHA] = sc[SC_ALPHA + 1] = 0.0;
+      sc[SC_BETA] = sc[SC_BETA + 1] = 0.0;
+      sc[SC_RNORM2] = v[2];
+      sc[SC_SIGMA] = sqrt(sc[SC_R64N2] / (12.0 * hv));
+      sc[SC_FLAGS] = 0.0;
+    } break;
+    case RED_CG_RU: {  // z and p carry over in the new units: gamma scales with the ratio squared
+      double snew = ru_scale(sc[SC_R64N2], sc[SC_SIGMA], hv);
+      double ratio = sc[SC_SIGMA] / snew;
+      sc[SC_RHO] *= ratio * ratio;
       sc[SC_RNORM2] = v[2];
       sc[SC_SIGMA] = snew;
     } break;

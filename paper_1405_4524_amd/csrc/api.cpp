@@ -154,6 +154,44 @@ int resolve_op(Ctx* c, int clover_h, double kappa, int prec, GaugeField** gf, Cl
   return A2A_OK;
 }
 
+// Sources whose BiCGStab broke down repeatedly start again with CG on the normal equations
+// (whose residual decreases monotonically and which needs no bi-orthogonality), from the
+// iterate the first pass wrote to their solution buffer when it is finite, else from zero.
+// Runs after the first pass has finished, so no slot is live in two solvers.
+static int cgnr_fallback(Ctx* c, Solver& first, std::vector<Slot>& slots, int clover_h, double kappa, KappaOp* kop,
+                         GaugeField* gf) {
+  std::vector<int> idx;
+  for (int i = 0; i < (int)slots.size(); ++i)
+    if (slots[i].state == SS_FAIL && slots[i].err == A2A_EBREAKDOWN && slots[i].iters < slots[i].max_iter)
+      idx.push_back(i);
+  if (idx.empty()) return A2A_OK;
+  A2A_TRY(c->sync());
+  Solver sv(c, first.prec, first.R);
+  sv.method = SOLVER_CGNR;
+  const int op = sv.op_index(clover_h, kappa, kop, gf);
+  for (int k = 0; k < (int)idx.size(); ++k) {
+    Slot& s = slots[idx[k]];
+    s.op = op;
+    s.x0 = std::isfinite(s.info.true_rel_residual) ? s.sol : nullptr;
+    s.state = SS_NEW;
+    s.err = A2A_OK;
+    s.restarts = s.stagn = 0;
+    s.last_r64 = INFINITY;
+    sv.add_slot(&s);
+  }
+  std::vector<int> all(idx.size());
+  for (int k = 0; k < (int)idx.size(); ++k) all[k] = k;
+  A2A_TRY(sv.setup(all));
+  std::vector<int> early;
+  for (int k : all)
+    if (sv.live[k]->state == SS_RUN && sv.live[k]->last_r64 <= sv.live[k]->target) early.push_back(k);
+  if (!early.empty()) {
+    A2A_TRY(sv.finalize(early));
+    for (int k : early) sv.live[k]->state = sv.live[k]->info.converged ? SS_DONE : SS_RUN;
+  }
+  return sv.run_until_done(1 << 30);
+}
+
 int solve_core(Ctx* c, int clover_h, const double* src, int nrhs, double kappa, double csw, double tol, int prec,
                int max_iter, const double* x0, double* sol, a2a_solve_info* info) {
   if (nrhs <= 0) return c->fail(A2A_EINVAL, "nrhs must be positive");
@@ -172,6 +210,7 @@ int solve_core(Ctx* c, int clover_h, const double* src, int nrhs, double kappa, 
   int R = effective_R(c, prec);
   if (c->autotune) A2A_TRY(autotune_R(c, clover_h, kappa, prec, nrhs, &R, nullptr));
   Solver sv(c, prec, R);
+  sv.method = c->solver;
   const int op = sv.op_index(clover_h, kappa, kop, gf);
   std::vector<Slot> slots(nrhs);
   int rc = A2A_OK;
@@ -204,6 +243,7 @@ int solve_core(Ctx* c, int clover_h, const double* src, int nrhs, double kappa, 
       }
     }
     if (!rc) rc = sv.run_until_done(1 << 30);
+    if (!rc && sv.method == SOLVER_BICGSTAB && c->cgnr_fallback) rc = cgnr_fallback(c, sv, slots, clover_h, kappa, kop, gf);
   }
   int worst = A2A_OK;
   for (int i = 0; i < nrhs; ++i) {
@@ -217,7 +257,7 @@ int solve_core(Ctx* c, int clover_h, const double* src, int nrhs, double kappa, 
   if (rc) return rc;
   if (rs) return rs;
   if (worst == A2A_ENOTCONV) c->fail(A2A_ENOTCONV, "some sources did not converge within max_iter");
-  if (worst == A2A_EBREAKDOWN) c->fail(A2A_EBREAKDOWN, "BiCGStab broke down repeatedly");
+  if (worst == A2A_EBREAKDOWN) c->fail(A2A_EBREAKDOWN, "the Krylov solver broke down repeatedly");
   if (worst == A2A_ENAN) c->fail(A2A_ENAN, "non-finite source");
   return worst;
 }
@@ -433,6 +473,13 @@ extern "C" int a2a_set_option(a2a_ctx* h, const char* key, double v) {
     c->interleave = v != 0;
   } else if (k == "mfma") {
     c->mfma = v != 0;
+  } else if (k == "solver") {
+    if (v != A2A_SOLVER_BICGSTAB && v != A2A_SOLVER_CGNR) return c->fail(A2A_EINVAL, "solver must be 0 or 1");
+    c->solver = (int)v;
+  } else if (k == "cgnr_fallback") {
+    c->cgnr_fallback = v != 0;
+  } else if (k == "force_breakdown") {
+    c->force_breakdown = v != 0;
   } else if (k == "hbm_budget") {
     if (!(v > 0)) return c->fail(A2A_EINVAL, "hbm_budget must be positive");
     c->budget = (size_t)v;
@@ -945,6 +992,7 @@ struct Request {
   double tol;
   int prec;
   int max_iter;
+  int method = SOLVER_BICGSTAB;
   int state = 0;  // 0 queued, 1 running, 2 done, -1 failed
   int err = A2A_OK;
   double t_submit = 0;
@@ -957,7 +1005,7 @@ struct a2a_engine {
   int max_queue = 4096;
   std::deque<Request*> queue;
   std::map<long long, std::unique_ptr<Request>> reqs;
-  std::unique_ptr<Solver> solvers[4];
+  std::unique_ptr<Solver> solvers[8];  // [method * 4 + precision]
   long long next_ticket = 1;
   int active = 0;
 };
@@ -997,6 +1045,7 @@ extern "C" int a2a_engine_submit(a2a_engine* e, int clover_h, double kappa, cons
   r->tol = tol;
   r->prec = prec;
   r->max_iter = max_iter;
+  r->method = c->solver;
   r->t_submit = now_seconds();
   e->queue.push_back(r.get());
   *ticket = r->ticket;
@@ -1018,8 +1067,11 @@ static int engine_admit(a2a_engine* e, Request* r) {
   KappaOp* kop;
   int rc = resolve_op(c, r->clover_h, r->kappa, r->prec, &gf, &cf, &kop);
   if (rc) return rc;
-  auto& sv = e->solvers[r->prec];
-  if (!sv) sv = std::make_unique<Solver>(c, r->prec, effective_R(c, r->prec));
+  auto& sv = e->solvers[r->method * 4 + r->prec];
+  if (!sv) {
+    sv = std::make_unique<Solver>(c, r->prec, effective_R(c, r->prec));
+    sv->method = r->method;
+  }
   const int op = sv->op_index(r->clover_h, r->kappa, kop, gf);
   const long long V = volume_of(gf->g);
   r->slots.assign(r->nsrc, Slot());
@@ -1086,23 +1138,9 @@ extern "C" int a2a_engine_step(a2a_engine* e, int iters, int* active) {
       for (auto& s : r->slots) s.state = SS_FAIL;
     }
   }
-  // iterate every active slot of every precision
-  for (int p = 0; p < 4; ++p) {
-    auto& sv = e->solvers[p];
-    if (!sv) continue;
-    A2A_TRY(sv->retire());
-    for (int k = 1; k <= iters && !sv->live.empty(); ++k) {
-      A2A_TRY(sv->rebuild());
-      A2A_TRY(sv->iteration());
-      if (k % c->check_every == 0 || k == iters) {
-        A2A_TRY(sv->check());
-        A2A_TRY(sv->retire());
-        A2A_TRY(sv->rebuild());
-        if (sv->live.empty()) break;
-      }
-      A2A_TRY(sv->vec(false, sv->n_vec_tiles, VK_BICG_P));
-    }
-  }
+  // iterate every active slot of every precision and method
+  for (auto& sv : e->solvers)
+    if (sv) A2A_TRY(sv->run_steps(iters));
   // retire finished requests
   for (auto& kv : e->reqs) {
     Request* r = kv.second.get();

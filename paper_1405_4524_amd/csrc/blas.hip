@@ -1,4 +1,4 @@
-// blas.hip -- BiCGStab vector updates with fused FP64 block reductions, the reliable-update
+// blas.hip -- BiCGStab and CGNR vector updates with fused FP64 block reductions, the reliable-update
 // (mixed-precision defect correction) kernels, site-local clover application, the
 // canonical <-> even-odd layout kernels and the reduction finalize kernel.
 //
@@ -39,7 +39,8 @@ __device__ __forceinline__ void round_to(Spinor<A>& s) {
 // kinds whose result feeds a reduction
 template <int KIND>
 struct VecRed {
-  static constexpr bool on = KIND == VK_BICG_XR || KIND == VK_RU_RESCALE || KIND == VK_INIT;
+  static constexpr bool on = KIND == VK_BICG_XR || KIND == VK_RU_RESCALE || KIND == VK_INIT || KIND == VK_CG_XR ||
+                             KIND == VK_CG_INIT || KIND == VK_CG_RESCALE;
 };
 
 // One site of one slot.  Reducing kinds add their (rhat, r), |r|^2 contributions to v3.
@@ -88,6 +89,57 @@ __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, in
     Spinor<A> rh;
     vload<S, A>(lw, VL_RHAT, site, rh);
     dot3(rh, s, v3);
+  } else if (KIND == VK_CG_XR) {  // x += alpha p; r' -= alpha gamma5 q; |r'|^2
+    const A al = (A)sc[SC_ALPHA];
+    Spinor<A> x, p, r, q;
+    xload<SX, A>(sd, VL_X, site, x);
+    vload<S, A>(lw, VL_P, site, p);
+    vload<S, A>(lw, VL_R, site, r);
+    vload<S, A>(lw, VL_V, site, q);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      x.v[k] = x.v[k] + al * p.v[k];
+      r.v[k] = k < 6 ? r.v[k] - al * q.v[k] : r.v[k] + al * q.v[k];
+    }
+    xstore<SX, A>(sd, VL_X, site, x);
+    vstore<S, A>(lw, VL_R, site, r);
+    round_to<S>(r);
+    dot3(r, r, v3);
+  } else if (KIND == VK_CG_P) {  // p = gamma5 u + beta p
+    const A be = (A)sc[SC_BETA];
+    Spinor<A> u, p;
+    vload<S, A>(lw, VL_S, site, u);
+    vload<S, A>(lw, VL_P, site, p);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p.v[k] = (k < 6 ? u.v[k] : mk(-u.v[k].re, -u.v[k].im)) + be * p.v[k];
+    vstore<S, A>(lw, VL_P, site, p);
+  } else if (KIND == VK_CG_INIT || KIND == VK_CG_RESCALE) {  // r' = gamma5 r64 / sigma'
+    const double snew =
+        KIND == VK_CG_INIT ? sqrt(sc[SC_R64N2] / (12.0 * hv)) : ru_scale(sc[SC_R64N2], sc[SC_SIGMA], hv);
+    const double inv = (snew > 0.0) ? 1.0 / snew : 0.0;
+    Spinor<double> rh64;
+    load_spinor<double, double>(HI(VH_R), hv, site, rh64);
+    Spinor<A> r;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const double f = k < 6 ? inv : -inv;
+      r.v[k] = mk((A)(rh64.v[k].re * f), (A)(rh64.v[k].im * f));
+    }
+    vstore<S, A>(lw, VL_R, site, r);
+    round_to<S>(r);
+    Spinor<A> p;
+    if (KIND == VK_CG_INIT) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) p.v[k] = mk((A)0, (A)0);
+      xstore<SX, A>(sd, VL_X, site, p);
+    } else {
+      const A ratio = (A)(sc[SC_SIGMA] * inv);
+      vload<S, A>(lw, VL_P, site, p);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) p.v[k] = ratio * p.v[k];
+    }
+    vstore<S, A>(lw, VL_P, site, p);
+    dot3(r, r, v3);
   } else if (KIND == VK_RU_ACCUM) {  // x64 += sigma x_lo; x_lo = 0
     const double sg = sc[SC_SIGMA];
     Spinor<A> xl;
@@ -251,13 +303,18 @@ static void launch_vec_il_p(const VecArgs& a, int n, hipStream_t s) {
     case VK_ZERO_X: hipLaunchKernelGGL((k_vec_il<P, VK_ZERO_X>), g, b, 0, s, a); break;
     case VK_ZERO_LO: hipLaunchKernelGGL((k_vec_il<P, VK_ZERO_LO>), g, b, 0, s, a); break;
     case VK_FILL_LO: hipLaunchKernelGGL((k_vec_il<P, VK_FILL_LO>), g, b, 0, s, a); break;
+    case VK_CG_XR: hipLaunchKernelGGL((k_vec_il<P, VK_CG_XR>), g, b, 0, s, a); break;
+    case VK_CG_P: hipLaunchKernelGGL((k_vec_il<P, VK_CG_P>), g, b, 0, s, a); break;
+    case VK_CG_INIT: hipLaunchKernelGGL((k_vec_il<P, VK_CG_INIT>), g, b, 0, s, a); break;
+    case VK_CG_RESCALE: hipLaunchKernelGGL((k_vec_il<P, VK_CG_RESCALE>), g, b, 0, s, a); break;
     default: break;
   }
 }
 
 bool vec_kind_il(int kind) {
   return kind == VK_BICG_S || kind == VK_BICG_XR || kind == VK_BICG_P || kind == VK_RU_ACCUM ||
-         kind == VK_RU_RESCALE || kind == VK_INIT || kind == VK_ZERO_X || kind == VK_ZERO_LO || kind == VK_FILL_LO;
+         kind == VK_RU_RESCALE || kind == VK_INIT || kind == VK_ZERO_X || kind == VK_ZERO_LO || kind == VK_FILL_LO ||
+         kind == VK_CG_XR || kind == VK_CG_P || kind == VK_CG_INIT || kind == VK_CG_RESCALE;
 }
 
 void launch_vec_il(int prec, const VecArgs& a, int ntiles, hipStream_t s) {
@@ -284,6 +341,10 @@ static void launch_vec_p(const VecArgs& a, int n, hipStream_t s) {
     case VK_ZERO_X: hipLaunchKernelGGL((k_vec<P, VK_ZERO_X>), g, b, 0, s, a); break;
     case VK_ZERO_LO: hipLaunchKernelGGL((k_vec<P, VK_ZERO_LO>), g, b, 0, s, a); break;
     case VK_FILL_LO: hipLaunchKernelGGL((k_vec<P, VK_FILL_LO>), g, b, 0, s, a); break;
+    case VK_CG_XR: hipLaunchKernelGGL((k_vec<P, VK_CG_XR>), g, b, 0, s, a); break;
+    case VK_CG_P: hipLaunchKernelGGL((k_vec<P, VK_CG_P>), g, b, 0, s, a); break;
+    case VK_CG_INIT: hipLaunchKernelGGL((k_vec<P, VK_CG_INIT>), g, b, 0, s, a); break;
+    case VK_CG_RESCALE: hipLaunchKernelGGL((k_vec<P, VK_CG_RESCALE>), g, b, 0, s, a); break;
     default: break;
   }
 }

@@ -710,7 +710,7 @@ int Solver::finalize_red(bool sub, int kind) {
 
 int Solver::hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par, int vin, int vout, int vaux1,
                 int vaux2, int vrhat, double ca, double cb, double gsign, int gpow, int inv, int red,
-                const char* cls) {
+                const char* cls, int fin) {
   HopArgs a{};
   a.ops = d_ops;
   a.slots = d_slots;
@@ -778,7 +778,7 @@ int Solver::hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par,
   } else if (cls) {
     A2A_TRY(ctx->timing_end(c, ev, 0.0));
   }
-  if (red != RED_NONE) A2A_TRY(finalize_red(sub, red));
+  if (red != RED_NONE) A2A_TRY(finalize_red(sub, fin >= 0 ? fin : red));
   return A2A_OK;
 }
 
@@ -793,9 +793,10 @@ int Solver::vec(bool sub, int n_tiles, int kind, int par, int use_inv, int vin, 
   a.vin = vin;
   a.vout = vout;
   a.rb = ctx->redbuf();
-  const bool timed = !sub && (kind == VK_BICG_S || kind == VK_BICG_XR || kind == VK_BICG_P);
+  const bool timed = !sub && (kind == VK_BICG_S || kind == VK_BICG_XR || kind == VK_BICG_P || kind == VK_CG_XR ||
+                              kind == VK_CG_P);
   hipEvent_t ev = nullptr;
-  const int tcls = kind == VK_BICG_XR ? 2 : kind == VK_BICG_P ? 3 : 4;
+  const int tcls = (kind == VK_BICG_XR || kind == VK_CG_XR) ? 2 : (kind == VK_BICG_P || kind == VK_CG_P) ? 3 : 4;
   if (timed) A2A_TRY(ctx->timing_begin(tcls, &ev));
   const int n_il = sub ? sub_ni : n_il_tiles;
   if (vec_kind_il(kind) && n_il > 0) {  // interleaved slots with the lane mapping, the rest per slot
@@ -812,15 +813,26 @@ int Solver::vec(bool sub, int n_tiles, int kind, int par, int use_inv, int vin, 
   if (timed) {
     // compulsory bytes per site and RHS: s = r - alpha v reads 2 and writes 1 inner vector;
     // p = r + beta (p - omega v) reads 3, writes 1; the x / r update reads p, s, t, rhat and x
-    // and writes r and x (x is FP32 in FP16 mode)
+    // and writes r and x (x is FP32 in FP16 mode); CGNR: x += alpha p, r -= alpha gamma5 q
+    // reads p, r, q and x and writes r and x; p = gamma5 u + beta p reads 2 and writes 1
     const double sz = prec == 0 ? 8.0 : prec == 1 ? 4.0 : 2.0;
     const double szx = prec == 0 ? 8.0 : prec == 3 ? 2.0 : 4.0;
-    const double per = kind == VK_BICG_S ? 3 * sz : kind == VK_BICG_P ? 4 * sz : 5 * sz + 2 * szx;
+    const double per = kind == VK_BICG_S   ? 3 * sz
+                       : kind == VK_BICG_P ? 4 * sz
+                       : kind == VK_CG_P   ? 3 * sz
+                       : kind == VK_CG_XR  ? 4 * sz + 2 * szx
+                                           : 5 * sz + 2 * szx;
     double bytes = 0;
     for (Slot* s : live) bytes += (double)ops[s->op].dev.g.hv * 24 * per;
     A2A_TRY(ctx->timing_end(tcls, ev, bytes));
   }
-  const int red = kind == VK_BICG_XR ? RED_RHO : kind == VK_RU_RESCALE ? RED_RU : kind == VK_INIT ? RED_INIT : RED_NONE;
+  const int red = kind == VK_BICG_XR       ? RED_RHO
+                  : kind == VK_RU_RESCALE  ? RED_RU
+                  : kind == VK_INIT        ? RED_INIT
+                  : kind == VK_CG_XR       ? RED_CG_R
+                  : kind == VK_CG_INIT     ? RED_CG_INIT
+                  : kind == VK_CG_RESCALE  ? RED_CG_RU
+                                           : RED_NONE;
   if (red != RED_NONE) A2A_TRY(finalize_red(sub, red));
   return A2A_OK;
 }
@@ -859,9 +871,18 @@ int Solver::layout_out(bool sub, int n_tiles, int psel, int kprec, int ve, int v
   return A2A_OK;
 }
 
-// One BiCGStab step for every live slot, up to and including the x / r update.
+// One Krylov step for every live slot, up to and including the x / r update.
 int Solver::iteration() {
   const int H = n_hop_tiles, Vn = n_vec_tiles;
+  if (method == SOLVER_CGNR) {
+    // q = M p, alpha = gamma / |q|^2; x += alpha p, r' -= alpha gamma5 q
+    A2A_TRY(hop(false, H, R, 0, prec, 0, VL_P, VL_TE, -1, -1, -1, 0, 0, 1.0, 0, 1, RED_NONE, "1"));
+    A2A_TRY(hop(false, H, R, 0, prec, 1, VL_TE, VL_V, -1, VL_P, -1, 0, 1.0, -1.0, 2, 0, RED_OMEGA, "2",
+                RED_CG_ALPHA));
+    A2A_TRY(vec(false, Vn, VK_CG_XR));
+    for (Slot* s : live) s->iters++;
+    return A2A_OK;
+  }
   // v = M p
   A2A_TRY(hop(false, H, R, 0, prec, 0, VL_P, VL_TE, -1, -1, -1, 0, 0, 1.0, 0, 1, RED_NONE, "1"));
   A2A_TRY(hop(false, H, R, 0, prec, 1, VL_TE, VL_V, -1, VL_P, VL_RHAT, 0, 1.0, -1.0, 2, 0, RED_ALPHA, "2"));
@@ -872,6 +893,17 @@ int Solver::iteration() {
   A2A_TRY(vec(false, Vn, VK_BICG_XR));
   for (Slot* s : live) s->iters++;
   return A2A_OK;
+}
+
+// CGNR search direction: u = M r' (r' = gamma5 r, so gamma5 u = M^dag r), beta = |u|^2 /
+// gamma, p = gamma5 u + beta p.  Runs before every CGNR step, so that a fresh start
+// (gamma = 0) and a reliable update (r' replaced, p rescaled) need nothing else.
+int Solver::cg_direction() {
+  const int H = n_hop_tiles, Vn = n_vec_tiles;
+  A2A_TRY(hop(false, H, R, 0, prec, 0, VL_R, VL_TE, -1, -1, -1, 0, 0, 1.0, 0, 1, RED_NONE, "1"));
+  A2A_TRY(hop(false, H, R, 0, prec, 1, VL_TE, VL_S, -1, VL_R, -1, 0, 1.0, -1.0, 2, 0, RED_OMEGA, "2",
+              RED_CG_BETA));
+  return vec(false, Vn, VK_CG_P);
 }
 
 // FP64: x64 is current; r64 = b - M x64 and |r64|^2 for a subset (uploaded by the caller).
@@ -902,7 +934,7 @@ int Solver::setup(const std::vector<int>& idx) {
     A2A_TRY(upload_subset(idx, R64));
   }
   A2A_TRY(true_residual(idx));
-  A2A_TRY(vec(true, nv, VK_INIT));
+  A2A_TRY(vec(true, nv, init_kind()));
   A2A_TRY(ctx->read_scal());
   for (int i : idx) {
     Slot* s = live[i];
@@ -944,6 +976,7 @@ int Solver::finalize(const std::vector<int>& idx) {
     s->info.iters = s->iters;
     s->info.reliable_updates = s->rus;
     s->info.restarts = s->restarts;
+    s->info.solver = method;
     s->info.converged = (s->info.true_rel_residual <= s->tol) ? 1 : 0;
     s->info.seconds = t - s->t_submit;
   }
@@ -1002,6 +1035,13 @@ int Solver::check() {
       s->last_r64 = r;
       continue;
     }
+    if (ctx->force_breakdown && method == SOLVER_BICGSTAB) {  // test hook: a breakdown at the first update
+      s->state = SS_FAIL;
+      s->err = A2A_EBREAKDOWN;
+      s->last_r64 = r;
+      done.push_back(i);
+      continue;
+    }
     if (was_restart || r > 0.9 * s->last_r64) {
       s->stagn++;
       s->restarts++;
@@ -1019,11 +1059,11 @@ int Solver::check() {
   }
   if (!rescale.empty()) {
     A2A_TRY(upload_subset(rescale, 1));
-    A2A_TRY(vec(true, sub_nv, VK_RU_RESCALE));
+    A2A_TRY(vec(true, sub_nv, method == SOLVER_CGNR ? VK_CG_RESCALE : VK_RU_RESCALE));
   }
   if (!reinit.empty()) {
     A2A_TRY(upload_subset(reinit, 1));
-    A2A_TRY(vec(true, sub_nv, VK_INIT));
+    A2A_TRY(vec(true, sub_nv, init_kind()));
   }
   if (!done.empty()) {
     A2A_TRY(finalize(done));
@@ -1043,7 +1083,7 @@ int Solver::check() {
     }
     if (!again.empty()) {
       A2A_TRY(upload_subset(again, 1));
-      A2A_TRY(vec(true, sub_nv, VK_INIT));
+      A2A_TRY(vec(true, sub_nv, init_kind()));
     }
   }
   return A2A_OK;
@@ -1059,24 +1099,26 @@ int Solver::retire() {
   return A2A_OK;
 }
 
-// Iterate every live slot until all are done (or fail).
-int Solver::run_until_done(int max_outer_iters) {
-  int k = 0;
+// Up to `iters` steps of every live slot, with residual checks every check_every steps and
+// after the last; stops early when no slot is left.
+int Solver::run_steps(int iters) {
   A2A_TRY(retire());
-  while (!live.empty()) {
+  for (int k = 1; k <= iters && !live.empty(); ++k) {
     A2A_TRY(rebuild());
+    if (method == SOLVER_CGNR) A2A_TRY(cg_direction());
     A2A_TRY(iteration());
-    ++k;
-    if (k % ctx->check_every == 0 || k >= max_outer_iters) {
+    if (k % ctx->check_every == 0 || k == iters) {
       A2A_TRY(check());
       A2A_TRY(retire());
       A2A_TRY(rebuild());
       if (live.empty()) break;
     }
-    A2A_TRY(vec(false, n_vec_tiles, VK_BICG_P));
-    if (k >= max_outer_iters) break;
+    if (method == SOLVER_BICGSTAB) A2A_TRY(vec(false, n_vec_tiles, VK_BICG_P));
   }
   return A2A_OK;
 }
+
+// Iterate every live slot until all are done (or fail).
+int Solver::run_until_done(int max_outer_iters) { return run_steps(max_outer_iters); }
 
 }  // namespace a2a

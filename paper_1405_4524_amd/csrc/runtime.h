@@ -75,6 +75,7 @@ struct OpEntry {
 };
 
 enum SlotState { SS_NEW = 0, SS_RUN, SS_DONE, SS_FAIL };
+enum SolverKind { SOLVER_BICGSTAB = A2A_SOLVER_BICGSTAB, SOLVER_CGNR = A2A_SOLVER_CGNR };
 
 struct Slot {
   int sid = -1;
@@ -105,6 +106,7 @@ struct Solver {
   int prec;
   int R;    // RHS per thread in the stencil
   int R64;  // RHS per thread in the FP64 stencils of setup, reliable updates and reconstruction
+  int method = SOLVER_BICGSTAB;  // inner Krylov method of every slot of this solver
   std::vector<OpEntry> ops;
   std::vector<Slot*> live;  // slots in the device tables (running)
   // device tables
@@ -147,11 +149,15 @@ struct Solver {
   int finalize_red(bool sub, int kind);
   // kernel sequences
   int hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par, int vin, int vout, int vaux1, int vaux2,
-          int vrhat, double ca, double cb, double gsign, int gpow, int inv, int red, const char* cls);
+          int vrhat, double ca, double cb, double gsign, int gpow, int inv, int red, const char* cls,
+          int fin = -1);  // fin: finalize kind of the reduction (default: red itself)
   int vec(bool sub, int n_tiles, int kind, int par = 0, int use_inv = 0, int vin = -1, int vout = -1);
   int layout_in(bool sub, int n_tiles, int which_in, int psel, int kprec, int ve, int vo, int g5, int red);
   int layout_out(bool sub, int n_tiles, int psel, int kprec, int ve, int vo, int g5);
   int iteration();
+  int cg_direction();
+  int run_steps(int iters);
+  int init_kind() const { return method == SOLVER_CGNR ? VK_CG_INIT : VK_INIT; }
   int setup(const std::vector<int>& idx);
   int check();
   int true_residual(const std::vector<int>& idx);
@@ -191,6 +197,9 @@ struct Ctx {
   int autotune = 0;                  // pick the stencil RHS-block width per workload
   int interleave = 1;                // FP16/BF16 inner vectors in the interleaved group layout
   int mfma = 1;                      // interleaved groups use the matrix-core stencil
+  int solver = SOLVER_BICGSTAB;      // inner Krylov method of solves and engine requests
+  int cgnr_fallback = 1;             // BiCGStab breakdowns are finished by CGNR (solve calls)
+  int force_breakdown = 0;           // test hook: BiCGStab slots break down at their first update
   std::map<std::string, int> tuned;  // tune key -> RHS-block width
   std::string tune_path;             // A2A_TUNE_CACHE: JSON file of tuned widths
   // reduction scratch

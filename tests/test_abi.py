@@ -43,8 +43,9 @@ def test_binding_covers_header():
 
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(a2a.Geom) == 5 * 4
-    # 4 ints then 2 doubles
-    assert ctypes.sizeof(a2a.SolveInfo) == 4 * 4 + 2 * 8
+    # 4 ints, 2 doubles, then the solver kind and a reserved int
+    assert ctypes.sizeof(a2a.SolveInfo) == 4 * 4 + 2 * 8 + 2 * 4
+    assert a2a.SolveInfo.solver.offset == 32
     assert a2a.SolveInfo.true_rel_residual.offset == 16
 
 
