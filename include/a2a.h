@@ -226,8 +226,8 @@ int a2a_engine_destroy(a2a_engine *eng);
 /* With option "kernel_timing" = 1 the solver brackets every inner-solver launch with HIP
  * events on the context stream.  For kernel class `name` ("schur1": hop to even sites with
  * the A_ee^{-1} epilogue; "schur2": hop to odd sites with the A_oo, axpy and dot-product
- * epilogue; "xr", "p", "s": the BiCGStab updates of x and r, of p, of s; "blas": the three
- * updates together) returns the launches, their total
+ * epilogue; "xr", "p", "s": the BiCGStab updates of x and r, of p, of s (CGNR's x/r and p
+ * updates count as "xr" and "p"); "blas": the three updates together) returns the launches, their total
  * milliseconds and their total algorithmic bytes (links and clover once per site, each
  * spinor stream once per right-hand side) since the last reset; resets if reset != 0. */
 int a2a_kernel_stats(a2a_ctx *ctx, const char *name, long long *launches, double *total_ms, double *alg_bytes,
