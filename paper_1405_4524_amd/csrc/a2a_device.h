@@ -190,8 +190,38 @@ struct Geo {
   int Xh;   // X / 2
   int hv;   // sites per parity
   int tbc;  // +1 periodic, -1 antiperiodic fermions in time
-  int pad;
+  // 4D site bricks of the stencil sweeps (extents in xh, y, z, t dividing Xh, Y, Z, T)
+  unsigned char bxh, by, bz, bt;
 };
+
+// cb index of position p of a stencil sweep: bricks in lexicographic order, inside a brick x
+// fastest (YFAST = false) or y fastest (YFAST = true), then z and t.  A bijection of [0, hv).
+template <bool YFAST>
+HD int brick_site(const Geo& g, int p) {
+  const int bxh = g.bxh, by = g.by, bz = g.bz, bt = g.bt;
+  const int B = bxh * by * bz * bt;
+  int br = p / B, r = p - br * B;
+  int rx, ry;
+  if (YFAST) {
+    ry = r % by;
+    r /= by;
+    rx = r % bxh;
+    r /= bxh;
+  } else {
+    rx = r % bxh;
+    r /= bxh;
+    ry = r % by;
+    r /= by;
+  }
+  const int rz = r % bz, rt = r / bz;
+  const int nbx = g.Xh / bxh, nby = g.Y / by, nbz = g.Z / bz;
+  const int ix = br % nbx;
+  br /= nbx;
+  const int iy = br % nby;
+  br /= nby;
+  const int iz = br % nbz, it = br / nbz;
+  return (((it * bt + rt) * g.Z + iz * bz + rz) * g.Y + iy * by + ry) * g.Xh + ix * bxh + rx;
+}
 
 HD void cb_coords(const Geo& g, int cb, int par, int c[4]) {
   int xh = cb % g.Xh;

@@ -27,6 +27,7 @@ struct HopArgs {
   int gpow;
   int inv;
   int red;
+  int brick;          // site blocks are 4D bricks (several RHS groups per block), else linear
   RedBuf rb;
 };
 
@@ -36,7 +37,6 @@ constexpr int IL_LANES = 48;  // RHS per interleaved group (three tiles of 16 la
 struct ILGroupDev {
   int op;
   int nt;                  // lane tiles in use
-  int bxh, by, bz, bt;     // site bricks of the stencil sweep (divide Xh, Y, Z, T)
   char* base;             // arena: [vector][site][tile][3 chunks][16 lanes] of 16-byte chunks
   long long vs;           // bytes per vector
   int slot[IL_LANES];     // slot-table index of each lane, -1 = idle
@@ -83,7 +83,7 @@ struct VecArgs {
   int kind;
   int par;        // parity for VK_CLOVER
   int use_inv;    // VK_CLOVER: 1 -> A^{-1}
-  int vin, vout;  // VK_CLOVER / VK_ZERO_HI
+  int vin, vout;  // VK_CLOVER / VK_ZERO_HI; vin >= 0: FP64 residual source of the INIT / RESCALE kinds
   RedBuf rb;
 };
 

@@ -118,7 +118,7 @@ __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, in
         KIND == VK_CG_INIT ? sqrt(sc[SC_R64N2] / (12.0 * hv)) : ru_scale(sc[SC_R64N2], sc[SC_SIGMA], hv);
     const double inv = (snew > 0.0) ? 1.0 / snew : 0.0;
     Spinor<double> rh64;
-    load_spinor<double, double>(HI(VH_R), hv, site, rh64);
+    load_spinor<double, double>(HI(a.vin >= 0 ? a.vin : VH_R), hv, site, rh64);
     Spinor<A> r;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -159,7 +159,7 @@ __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, in
         KIND == VK_INIT ? sqrt(sc[SC_R64N2] / (12.0 * hv)) : ru_scale(sc[SC_R64N2], sc[SC_SIGMA], hv);
     const double inv = (snew > 0.0) ? 1.0 / snew : 0.0;
     Spinor<double> rh64;
-    load_spinor<double, double>(HI(VH_R), hv, site, rh64);
+    load_spinor<double, double>(HI(a.vin >= 0 ? a.vin : VH_R), hv, site, rh64);
     Spinor<A> r;
 #pragma unroll
     for (int k = 0; k < 12; ++k) r.v[k] = mk((A)(rh64.v[k].re * inv), (A)(rh64.v[k].im * inv));

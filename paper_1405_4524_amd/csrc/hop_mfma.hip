@@ -216,30 +216,18 @@ __device__ __forceinline__ void site_neighbours(const Geo& g, int site, int po, 
 
 // A block takes one 16-lane tile of a group over BS sites (64 per wave) of a 4D brick of the
 // lattice (the whole x row, then y, z, t extents), so that most neighbours of a block's sites
-// are sites of the same block; bricks follow in lexicographic order.  Blocks run tile-major
+// are sites of the same block; bricks follow in lexicographic order.  Inside a brick the sweep
+// runs y fastest, then x, then z and t: the waves of a block take (z, t) planes of the brick
+// at the same (x, y) positions, so that a neighbour spinor is used by the z and t neighbours
+// of other waves at about the same time, by its y neighbours two positions apart and by its x
+// neighbours a few positions apart, while it is still in the L2 (x fastest put the y uses a
+// whole row apart and cost a quarter more L2 misses).  Blocks run tile-major
 // (all site blocks of tile 0, then tile 1, ...) and are not grouped by XCD, so the chip sweeps
 // one window of the lattice at a time with a per-site footprint of 768 bytes.  The links,
 // clover and neighbour data of site i + 2 are requested while site i is computed (a ring of
 // three register buffers), and the matrix fragments are read from LDS right before their
 // products.
 
-// cb index of position p of the brick sweep
-__device__ __forceinline__ int brick_site(const Geo& g, int bxh, int by, int bz, int bt, int p) {
-  const int B = bxh * by * bz * bt;
-  int br = p / B, r = p - br * B;
-  const int rx = r % bxh;
-  r /= bxh;
-  const int ry = r % by;
-  r /= by;
-  const int rz = r % bz, rt = r / bz;
-  const int nbx = g.Xh / bxh, nby = g.Y / by, nbz = g.Z / bz;
-  const int ix = br % nbx;
-  br /= nbx;
-  const int iy = br % nby;
-  br /= nby;
-  const int iz = br % nbz, it = br / nbz;
-  return (((it * bt + rt) * g.Z + iz * bz + rz) * g.Y + iy * by + ry) * g.Xh + ix * bxh + rx;
-}
 template <class P, int EPI, int RED>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_hop_mfma(HopMArgs a) {
   using S = typename P::S;
@@ -349,8 +337,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 
   // prefetch cursor: site pk
   int pk = 0;
-  const int bxh = grp.bxh, bby = grp.by, bbz = grp.bz, bbt = grp.bt;
-  auto site_at = [&](int p) { return __builtin_amdgcn_readfirstlane(brick_site(g, bxh, bby, bbz, bbt, p)); };
+  auto site_at = [&](int p) { return __builtin_amdgcn_readfirstlane(brick_site<true>(g, p)); };
   // Loads and stores in the sweep are unconditional (positions past the wave's range are clamped
   // to its last site, whose values are then recomputed and rewritten unchanged), so the number
   // of memory operations in flight is the same on every path and the waits on them stay exact.

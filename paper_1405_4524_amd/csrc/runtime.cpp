@@ -36,7 +36,23 @@ int geom_to_geo(const a2a_geom* geom, Geo* g) {
   g->Xh = g->X / 2;
   g->hv = (int)(V / 2);
   g->tbc = geom->t_bc;
-  g->pad = 0;
+  // stencil bricks: the whole x row (xh extent up to 16), then extents in y, z, t that divide
+  // the lattice, aiming at BS sites per brick with the extra extent spread over y, z and t
+  int bx = g->Xh;
+  while (bx > 16 && bx % 2 == 0) bx /= 2;
+  g->bxh = (unsigned char)bx;
+  g->by = g->bz = g->bt = 1;
+  const int target = std::max(1, BS / bx);
+  static const int cand[][3] = {{4, 2, 2}, {2, 2, 4}, {2, 4, 2}, {4, 4, 1}, {2, 2, 2}, {4, 2, 1},
+                                {2, 2, 1}, {4, 1, 1}, {2, 1, 1}, {1, 1, 1}};
+  for (const auto& c : cand) {
+    if (c[0] * c[1] * c[2] > target) continue;
+    if (g->Y % c[0] || g->Z % c[1] || g->T % c[2]) continue;
+    g->by = (unsigned char)c[0];
+    g->bz = (unsigned char)c[1];
+    g->bt = (unsigned char)c[2];
+    break;
+  }
   return A2A_OK;
 }
 
@@ -463,27 +479,6 @@ void Solver::gc_ops() {
   dirty = true;
 }
 
-// Site bricks of the matrix-core stencil's sweep: the whole x row (xh extent up to 16), then
-// extents in y, z, t that divide the lattice, aiming at BS sites per brick with the extra
-// extent spread over y, z and t.
-static void brick_dims(const Geo& g, int* bxh, int* by, int* bz, int* bt) {
-  int bx = g.Xh;
-  while (bx > 16 && bx % 2 == 0) bx /= 2;
-  *bxh = bx;
-  *by = *bz = *bt = 1;
-  const int target = std::max(1, BS / bx);
-  static const int cand[][3] = {{4, 2, 2}, {2, 2, 4}, {2, 4, 2}, {4, 4, 1}, {2, 2, 2}, {4, 2, 1},
-                                {2, 2, 1}, {4, 1, 1}, {2, 1, 1}, {1, 1, 1}};
-  for (const auto& c : cand) {
-    if (c[0] * c[1] * c[2] > target) continue;
-    if (g.Y % c[0] || g.Z % c[1] || g.T % c[2]) continue;
-    *by = c[0];
-    *bz = c[1];
-    *bt = c[2];
-    return;
-  }
-}
-
 // Vector-kernel tile lists for the slots idx (indices into live): per-slot tiles of every
 // slot, per-slot tiles of the slots outside interleaved groups, and the interleaved lane
 // tiles (16 lanes of one group tile) with their site blocks.
@@ -602,7 +597,6 @@ int Solver::rebuild() {
         ILGroupDev d{};
         d.op = o;
         d.nt = s->il_nt;
-        brick_dims(ops[o].dev.g, &d.bxh, &d.by, &d.bz, &d.bt);
         d.base = s->il_base;
         d.vs = (long long)s->lo_stride;
         for (int l = 0; l < IL_LANES; ++l) d.slot[l] = -1;
@@ -729,6 +723,9 @@ int Solver::hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par,
   a.gpow = gpow;
   a.inv = inv;
   a.red = red;
+  long blocks = 0;  // site blocks of all operators: more tiles means several groups per block
+  for (const OpEntry& e : ops) blocks += e.nblk;
+  a.brick = n_tiles > blocks;
   a.rb = ctx->redbuf();
   const int c = (cls && cls[0] == '1') ? 0 : 1;
   hipEvent_t ev = nullptr;
@@ -757,6 +754,7 @@ int Solver::hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par,
     launch_hop_mfma(kprec, m, n_il_hop_tiles, inv, clov, ctx->stream);
     a.groups = d_groups_nonil;
     a.tiles = d_hop_nonil;
+    a.brick = n_hop_nonil > blocks;
     launch_hop(kprec, Rk, a, n_hop_nonil, ctx->stream);
   } else {
     launch_hop(kprec, Rk, a, n_tiles, ctx->stream);
@@ -926,15 +924,19 @@ int Solver::setup(const std::vector<int>& idx) {
   int nh = sub_nh, nv = sub_nv;
   A2A_TRY(layout_in(true, nv, 0, 1, 0, VH_ETA_E, VH_ETA_O, 0, RED_ETA));
   A2A_TRY(vec(true, nv, VK_CLOVER, 0, 1, VH_ETA_E, VH_TE));
-  A2A_TRY(hop(true, nh, R64, 1, 0, 1, VH_TE, VH_BHAT, VH_ETA_O, -1, -1, 1.0, 0, 1.0, 1, 0, RED_NONE, nullptr));
+  // without initial guesses r = b - M 0 = b: the b-hat stencil reduces |b|^2 and the inner
+  // state starts from b, so no FP64 Schur operator is applied here
+  const bool zero_x0 = with_x0.empty();
+  A2A_TRY(hop(true, nh, R64, 1, 0, 1, VH_TE, VH_BHAT, VH_ETA_O, -1, -1, 1.0, 0, 1.0, 1, 0,
+              zero_x0 ? RED_R64 : RED_NONE, nullptr));
   A2A_TRY(vec(true, nv, VK_ZERO_HI, 0, 0, -1, VH_X));
-  if (!with_x0.empty()) {
+  if (!zero_x0) {
     A2A_TRY(upload_subset(with_x0, 1));
     A2A_TRY(layout_in(true, sub_nv, 1, 1, 0, VH_TE, VH_X, 0, RED_NONE));
     A2A_TRY(upload_subset(idx, R64));
+    A2A_TRY(true_residual(idx));
   }
-  A2A_TRY(true_residual(idx));
-  A2A_TRY(vec(true, nv, init_kind()));
+  A2A_TRY(vec(true, nv, init_kind(), 0, 0, zero_x0 ? VH_BHAT : VH_R));
   A2A_TRY(ctx->read_scal());
   for (int i : idx) {
     Slot* s = live[i];
