@@ -12,7 +12,9 @@ and returning numpy complex128 arrays in the canonical layouts:
 Parity status of every function: pinned by the ``-m "not gpu"`` tests in
 ``tests/test_oracle_*.py`` (free-field closed form, gamma5-hermiticity, gauge covariance,
 a hand-computed clover, dense LU solves, the exact correlator from unit sources, the
-free-field correlator closed form, estimator statistics).
+free-field correlator closed form, estimator statistics; the outer-product fill by the dense
+inverse under full dilution, a hand-built dagger block and the Gram-matrix form of its
+contraction).
 """
 from __future__ import annotations
 
@@ -293,3 +295,38 @@ def reconstruct_even(U, Ainv, kappa, eta, x_odd, tbc):
     h = hop(U, xo, tbc)
     xe = site_matvec(Ainv, np.where(odd, 0, eta + kappa * h))
     return np.where(odd, xo, xe)
+
+
+# ---------------------------------------------------------------------------------------
+# outer-product fill of the all-to-all propagator (Sec. 7, eq. Sfill) and its contraction
+# ---------------------------------------------------------------------------------------
+def fill_propagator(eta, X, t_src, t, dagger=False):
+    """S(t, z; t_src, x)_{ab} = (1/N) sum_i X_i(t, z)_a conj(eta_i(t_src, x)_b) (Sec. 7, eq. Sfill),
+    as a (12 L^3) x (12 L^3) matrix with row (z, a) and column (x, b): spatial sites in the
+    canonical order (x fastest), a = 3 spin + colour.  dagger=True gives the spin-colour dagger
+    of every 12 x 12 block, S(t, z; t_src, x)^dag (Sec. 7: the dagger acts on spin and colour
+    only; the site indices are already exchanged)."""
+    eta, X = _c(eta), _c(X)
+    N = eta.shape[0]
+    n = X[0, t].size
+    S = np.zeros((n, n), np.complex128)
+    for i in range(N):  # one outer product per source, summed in source order
+        S += np.outer(X[i, t].ravel(), np.conj(eta[i, t_src].ravel()))
+    S /= N
+    if dagger:
+        m = n // 12
+        S = np.conj(S.reshape(m, 12, m, 12).transpose(0, 3, 2, 1)).reshape(n, n)
+    return S
+
+
+def contract_fill(eta1, X1, eta2, X2, t_src):
+    """C(t) = sum_{z, x} tr[S1(t, z; t_src, x) S2(t, z; t_src, x)^dag] for every sink timeslice t,
+    with S1 filled from (eta1, X1) and S2 from an independent set (eta2, X2) (the paper's
+    "sum_x sum_z tr S_s S_s^dag" with independent noise for the two propagators, Sec. 7)."""
+    T = _c(X1).shape[1]
+    C = np.empty(T, np.complex128)
+    for t in range(T):
+        S1 = fill_propagator(eta1, X1, t_src, t)
+        S2 = fill_propagator(eta2, X2, t_src, t)
+        C[t] = np.sum(S1 * np.conj(S2))  # tr[S1 S2^dag] summed over both sites
+    return C
