@@ -196,6 +196,28 @@ int a2a_contract_pipi_2pt_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *
                               const double *solutions_dev, int nrhs, double *diagrams_host,
                               double *vac_pieces_host, double *pion_or_null);
 
+/* ---- outer-product fill of the all-to-all propagator (Sec. 7, eq. Sfill) -------------- */
+/* All three take device arrays in the canonical spinor layout: sol = solutions X_i, src =
+ * sources eta_i, nrhs of each.  M = 12 X Y Z (spin-colour components of a timeslice).
+ *
+ * S (device, complex [M][M], owned by the caller) receives, for sink timeslice t and source
+ * timeslice t_src, S(t, z; t_src, x)_{ab} = (1/nrhs) sum_i X_i(t, z)_a conj(eta_i(t_src, x)_b)
+ * at row 12 z + a, column 12 x + b (z, x spatial site indices, x fastest; a = 3 spin + colour);
+ * with dagger = 1 every 12 x 12 block is replaced by its spin-colour dagger (Sec. 7: the
+ * paper's "S_s^dag fill").  Computed on the FP64 matrix cores. */
+int a2a_fill_propagator_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *sol_dev, const double *src_dev,
+                            int nrhs, int t_src, int t, int dagger, double *S_dev);
+/* corr (host, complex [T]) = sum_{z, x} tr[S1(t, z; t_src, x) S2(t, z; t_src, x)^dag] for every t,
+ * with S1 from (sol1, src1) and S2 from an independent set (sol2, src2) (the paper's
+ * "sum_x sum_z tr S_s S_s^dag" with independent noise for the two propagators, Sec. 7).
+ * _fill_ builds each product tile by tile on the matrix cores (cost ~ 8 T M^2 nrhs flop) without
+ * storing S; _gram_ evaluates the same sum as (1/nrhs^2) sum_ij <eta1_i, eta2_j>_{t_src}
+ * <X2_j, X1_i>_t (cost ~ 8 T M nrhs^2 flop).  The two agree to rounding. */
+int a2a_contract_fill_2pt_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *sol1_dev, const double *src1_dev,
+                              const double *sol2_dev, const double *src2_dev, int nrhs, int t_src, double *corr_host);
+int a2a_contract_gram_2pt_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *sol1_dev, const double *src1_dev,
+                              const double *sol2_dev, const double *src2_dev, int nrhs, int t_src, double *corr_host);
+
 /* ---- synthetic inputs ---------------------------------------------------------------- */
 /* Complex-Z2 noise (Sec. 7 "Z2 noise", here (+-1 +- i)/sqrt 2) written to a canonical
  * device array of nsrc sources: component k of the flattened array (global source index

@@ -71,6 +71,9 @@ _SIG = {
     "a2a_contract_pipi_2pt": (I, [P, ctypes.POINTER(Geom), P, P, I, P, P, P]),
     "a2a_contract_pipi_2pt_dev": (I, [P, ctypes.POINTER(Geom), P, P, I, P, P, P]),
     "a2a_z2_noise_dev": (I, [P, ctypes.POINTER(Geom), ULL, LL, I, P]),
+    "a2a_fill_propagator_dev": (I, [P, ctypes.POINTER(Geom), P, P, I, I, I, I, P]),
+    "a2a_contract_fill_2pt_dev": (I, [P, ctypes.POINTER(Geom), P, P, P, P, I, I, P]),
+    "a2a_contract_gram_2pt_dev": (I, [P, ctypes.POINTER(Geom), P, P, P, P, I, I, P]),
     "a2a_engine_create": (I, [P, ctypes.c_char_p, ctypes.POINTER(P)]),
     "a2a_engine_submit": (I, [P, I, D, P, I, D, I, I, P, ctypes.POINTER(LL)]),
     "a2a_engine_step": (I, [P, I, ctypes.POINTER(I)]),
@@ -339,6 +342,20 @@ class Context:
         g = geom(dims, 1)
         self._chk(lib().a2a_z2_noise_dev(self._c, ctypes.byref(g), ctypes.c_ulonglong(int(seed)),
                                          ctypes.c_longlong(int(src_offset)), int(nsrc), _tptr(out_t)))
+
+    # ---- outer-product fill (device tensors in the canonical spinor layout)
+    def fill_propagator_dev(self, sol_t, src_t, nrhs, dims, t_src, t, S_t, dagger=False, t_bc=-1):
+        g = geom(dims, t_bc)
+        self._chk(lib().a2a_fill_propagator_dev(self._c, ctypes.byref(g), _tptr(sol_t), _tptr(src_t), int(nrhs),
+                                                int(t_src), int(t), int(bool(dagger)), _tptr(S_t)))
+
+    def contract_fill_2pt_dev(self, sol1_t, src1_t, sol2_t, src2_t, nrhs, dims, t_src, t_bc=-1, method="fill"):
+        g = geom(dims, t_bc)
+        corr = np.empty(dims[3], np.complex128)
+        f = lib().a2a_contract_fill_2pt_dev if method == "fill" else lib().a2a_contract_gram_2pt_dev
+        self._chk(f(self._c, ctypes.byref(g), _tptr(sol1_t), _tptr(src1_t), _tptr(sol2_t), _tptr(src2_t), int(nrhs),
+                    int(t_src), corr.ctypes.data_as(P)))
+        return corr
 
     # ---- engine / instrumentation
     def engine_create(self, policy_json=""):

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT, "liba2a.so")
-SOURCES = ["hop.hip", "hop_mfma.hip", "blas.hip", "fields.hip", "contract.hip", "runtime.cpp", "api.cpp"]
+SOURCES = ["hop.hip", "hop_mfma.hip", "blas.hip", "fields.hip", "contract.hip", "fill.hip", "runtime.cpp", "api.cpp"]
 ARCH = "gfx950"
 FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -136,8 +136,28 @@ void launch_clover_convert(int prec, long hv, const double* src, void* dst, hipS
 void launch_z2_noise(long V, int nsrc, unsigned long long seed, long long src_offset, double* out, hipStream_t s);
 
 // stochastic operators O[t][a][b] (Sec. 7, eq. stoop) and the correlators built from them
+// (g5 = 0: without gamma_5, the Gram matrices <eta_a, X_b>_t; timeslices t_first .. + nt)
 void launch_stoch_ops(const Geo& g, int n, const double* eta, const double* X, double* partial, int nchunk,
-                      double* O, hipStream_t s);
+                      double* O, hipStream_t s, int g5 = 1, int t_first = 0, int nt = -1);
+void launch_gram_corr(int T, int n, const double* E, const double* F, double* corr, hipStream_t s);
+
+// outer-product fill (Sec. 7, eq. Sfill) on the FP64 matrix cores:
+// C(m, n) = scale sum_k P(m, k) conj(Q(n, k)), complex operands with element strides
+struct FillArgs {
+  const double* P[2];  // operand pairs: [0] the product to store or S1, [1] S2 (contract mode)
+  const double* Q[2];
+  long long pm, pk, qm, qk;  // P(m, k) = P[m pm + k pk], Q(n, k) = Q[n qm + k qk] (complex elements)
+  long long pz, qz;          // operand offsets per grid.y index (sink timeslice)
+  int M, N, K;
+  double scale;
+  double* out;               // fill mode: C(m, n) at out[z oz + m om + n on]
+  long long om, on, oz;
+  int dagger;                // store the spin-colour dagger of every 12 x 12 block
+  double* partial;           // contract mode: [z][block] complex partials of sum C1 conj(C2)
+};
+long long fill_blocks(int M, int N);
+void launch_fill(const FillArgs& a, int nz, hipStream_t s);
+void launch_fill_contract(const FillArgs& a, int nz, double* corr, hipStream_t s);
 void launch_pion_corr(int T, int n, const double* O, int mode, double* corr, hipStream_t s);
 void launch_pipi(int T, int n, const double* O, double* diag, double* vac, hipStream_t s);
 

@@ -980,6 +980,122 @@ extern "C" int a2a_kernel_stats(a2a_ctx* h, const char* name, long long* launche
 }
 
 // =========================================================================================
+// outer-product fill of the all-to-all propagator (Sec. 7, eq. Sfill) and the two routes to
+// sum_{z,x} tr[S1 S2^dag]: through the filled propagators (the paper's method, cost ~ T (12
+// L^3)^2 N) and through Gram matrices of sources and solutions (cost ~ T 12 L^3 N^2)
+// =========================================================================================
+static int fill_geo(Ctx* c, const a2a_geom* geom, int nrhs, int t_src, Geo* g) {
+  if (geom_to_geo(geom, g)) return c->fail(A2A_EINVAL, "bad lattice geometry");
+  if (nrhs < 1) return c->fail(A2A_EINVAL, "nrhs must be positive");
+  if (t_src < 0 || t_src >= g->T) return c->fail(A2A_EINVAL, "source timeslice out of range");
+  // M = 12 X Y Z rows and columns of the fill: (M / 64)^2 tiles must fit one launch
+  if (12LL * g->X * g->Y * g->Z > (1LL << 21)) return c->fail(A2A_EINVAL, "timeslice too large for the fill");
+  return A2A_OK;
+}
+
+extern "C" int a2a_fill_propagator_dev(a2a_ctx* h, const a2a_geom* geom, const double* sol, const double* src,
+                                       int nrhs, int t_src, int t, int dagger, double* S) {
+  if (!h || !sol || !src || !S) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  Geo g;
+  A2A_TRY(fill_geo(c, geom, nrhs, t_src, &g));
+  if (t < 0 || t >= g.T) return c->fail(A2A_EINVAL, "sink timeslice out of range");
+  const long long M = 12LL * g.X * g.Y * g.Z, col = M * g.T;  // complex per timeslice, per source
+  FillArgs a{};
+  a.P[0] = sol + 2 * t * M;
+  a.Q[0] = src + 2 * t_src * M;
+  a.pm = a.qm = 1;
+  a.pk = a.qk = col;
+  a.M = a.N = (int)M;
+  a.K = nrhs;
+  a.scale = 1.0 / nrhs;
+  a.out = S;
+  a.om = M;
+  a.on = 1;
+  a.dagger = dagger != 0;
+  launch_fill(a, 1, c->stream);
+  A2A_HIP(c, hipGetLastError());
+  return c->sync();
+}
+
+extern "C" int a2a_contract_fill_2pt_dev(a2a_ctx* h, const a2a_geom* geom, const double* sol1, const double* src1,
+                                         const double* sol2, const double* src2, int nrhs, int t_src,
+                                         double* corr) {
+  if (!h || !sol1 || !src1 || !sol2 || !src2 || !corr) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  Geo g;
+  A2A_TRY(fill_geo(c, geom, nrhs, t_src, &g));
+  const long long M = 12LL * g.X * g.Y * g.Z, col = M * g.T;
+  FillArgs a{};
+  a.P[0] = sol1;
+  a.P[1] = sol2;
+  a.Q[0] = src1 + 2 * t_src * M;
+  a.Q[1] = src2 + 2 * t_src * M;
+  a.pm = a.qm = 1;
+  a.pk = a.qk = col;
+  a.pz = M;  // one sink timeslice per grid row
+  a.M = a.N = (int)M;
+  a.K = nrhs;
+  a.scale = 1.0 / nrhs;
+  const long long nb = fill_blocks(a.M, a.N);
+  void *part = nullptr, *dc = nullptr;
+  A2A_TRY(c->dalloc(&part, sizeof(double) * 2 * (size_t)nb * g.T));
+  int rc = c->dalloc(&dc, sizeof(double) * 2 * g.T);
+  if (!rc) {
+    a.partial = (double*)part;
+    launch_fill_contract(a, g.T, (double*)dc, c->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) rc = c->fail(A2A_EDEVICE, std::string("fill contraction: ") + hipGetErrorString(e));
+    if (!rc) rc = copy_to_host(c, corr, dc, sizeof(double) * 2 * g.T);
+  }
+  c->sync();
+  c->dfree(part);
+  c->dfree(dc);
+  return rc;
+}
+
+extern "C" int a2a_contract_gram_2pt_dev(a2a_ctx* h, const a2a_geom* geom, const double* sol1, const double* src1,
+                                         const double* sol2, const double* src2, int nrhs, int t_src,
+                                         double* corr) {
+  if (!h || !sol1 || !src1 || !sol2 || !src2 || !corr) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  Geo g;
+  A2A_TRY(fill_geo(c, geom, nrhs, t_src, &g));
+  const int n = nrhs;
+  const long K = 12L * g.X * g.Y * g.Z;
+  const int ntb = (n + 63) / 64;
+  auto chunks = [&](int nt) {
+    long want = 4096 / std::max(1, nt * ntb * ntb);
+    return (int)std::max(1L, std::min(want, (K + 255) / 256));
+  };
+  const int ce = chunks(1), cf = chunks(g.T);
+  const size_t nn = (size_t)n * n;
+  void *part = nullptr, *E = nullptr, *F = nullptr, *dc = nullptr;
+  A2A_TRY(c->dalloc(&part, sizeof(double) * 2 * std::max((size_t)ce, (size_t)g.T * cf) * nn));
+  int rc = c->dalloc(&E, sizeof(double) * 2 * nn);
+  if (!rc) rc = c->dalloc(&F, sizeof(double) * 2 * nn * g.T);
+  if (!rc) rc = c->dalloc(&dc, sizeof(double) * 2 * g.T);
+  if (!rc) {
+    // E[i][j] = <eta1_i, eta2_j> on t_src; F[t][j][i] = <X2_j, X1_i> on t
+    launch_stoch_ops(g, n, src1, src2, (double*)part, ce, (double*)E, c->stream, 0, t_src, 1);
+    launch_stoch_ops(g, n, sol2, sol1, (double*)part, cf, (double*)F, c->stream, 0, 0, g.T);
+    launch_gram_corr(g.T, n, (const double*)E, (const double*)F, (double*)dc, c->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) rc = c->fail(A2A_EDEVICE, std::string("Gram contraction: ") + hipGetErrorString(e));
+    if (!rc) rc = copy_to_host(c, corr, dc, sizeof(double) * 2 * g.T);
+  }
+  c->sync();
+  c->dfree(part);
+  c->dfree(E);
+  c->dfree(F);
+  c->dfree(dc);
+  return rc;
+}
+
+// =========================================================================================
 // serving engine: continuous batching
 // =========================================================================================
 struct Request {

@@ -15,12 +15,12 @@ namespace a2a {
 constexpr int CT = 64;   // output tile edge
 constexpr int KC = 16;   // complex elements per K step
 
-__global__ __launch_bounds__(256) void k_stoch_partial(int n, long V, int V3, int nchunk, int kchunk,
-                                                        const double* __restrict__ eta,
+__global__ __launch_bounds__(256) void k_stoch_partial(int n, long V, int V3, int nchunk, int kchunk, int g5,
+                                                        int t_first, const double* __restrict__ eta,
                                                         const double* __restrict__ X, double* partial) {
   __shared__ double2 Es[CT][KC + 1];
   __shared__ double2 Xs[CT][KC + 1];
-  const int chunk = blockIdx.x, t = blockIdx.y;
+  const int chunk = blockIdx.x, tl = blockIdx.y, t = t_first + tl;
   const int ntb = (n + CT - 1) / CT;
   const int ta = blockIdx.z / ntb, tb = blockIdx.z % ntb;
   const int a0 = ta * CT, b0 = tb * CT;
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256) void k_stoch_partial(int n, long V, int V3, in
         }
         if (b0 + row < n) {
           const double* p = X + 2 * ((size_t)(b0 + row) * src_stride + tbase + k);
-          const double sg = ((k % 12) >= 6) ? -1.0 : 1.0;  // gamma_5 = diag(1,1,-1,-1)
+          const double sg = (g5 && (k % 12) >= 6) ? -1.0 : 1.0;  // gamma_5 = diag(1,1,-1,-1)
           xv = make_double2(sg * p[0], sg * p[1]);
         }
       }
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_stoch_partial(int n, long V, int V3, in
     }
     __syncthreads();
   }
-  double* out = partial + (((size_t)t * nchunk + chunk) * n) * n * 2;
+  double* out = partial + (((size_t)tl * nchunk + chunk) * n) * n * 2;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -104,17 +104,42 @@ __global__ void k_stoch_sum(int n, int T, int nchunk, const double* partial, dou
 }
 
 void launch_stoch_ops(const Geo& g, int n, const double* eta, const double* X, double* partial, int nchunk,
-                      double* O, hipStream_t s) {
+                      double* O, hipStream_t s, int g5, int t_first, int nt) {
   const int V3 = g.X * g.Y * g.Z;
   const long V = (long)V3 * g.T;
   const long K = 12L * V3;
+  if (nt < 0) nt = g.T;
   long kchunk = (K + nchunk - 1) / nchunk;
   kchunk = ((kchunk + KC - 1) / KC) * KC;
   const int ntb = (n + CT - 1) / CT;
-  dim3 grid(nchunk, g.T, ntb * ntb);
-  hipLaunchKernelGGL(k_stoch_partial, grid, dim3(256), 0, s, n, V, V3, nchunk, (int)kchunk, eta, X, partial);
-  const long tot = (long)g.T * n * n;
-  hipLaunchKernelGGL(k_stoch_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, g.T, nchunk, partial, O);
+  dim3 grid(nchunk, nt, ntb * ntb);
+  hipLaunchKernelGGL(k_stoch_partial, grid, dim3(256), 0, s, n, V, V3, nchunk, (int)kchunk, g5, t_first, eta, X,
+                     partial);
+  const long tot = (long)nt * n * n;
+  hipLaunchKernelGGL(k_stoch_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, nt, nchunk, partial, O);
+}
+
+// Gram form of sum_{z,x} tr[S1 S2^dag]: corr[t] = (1/n^2) sum_ij E[i][j] F[t][j][i] with
+// E = <eta1_i, eta2_j> on the source timeslice and F[t] = <X2_j, X1_i> on timeslice t.
+__global__ __launch_bounds__(256) void k_gram_corr(int n, const double* E, const double* F, double* corr) {
+  const int t = blockIdx.x;
+  const long per = (long)n * n;
+  const double* Ft = F + 2 * (size_t)t * per;
+  double v[2] = {0.0, 0.0};
+  for (long e = threadIdx.x; e < per; e += 256) {
+    const long i = e / n, j = e % n;
+    const double er = E[2 * (i * n + j)], ei = E[2 * (i * n + j) + 1];
+    const double fr = Ft[2 * (j * n + i)], fi = Ft[2 * (j * n + i) + 1];
+    v[0] += er * fr - ei * fi;
+    v[1] += er * fi + ei * fr;
+  }
+  block_sum_n<2, 256>(v);
+  const double inv = 1.0 / ((double)n * n);
+  if (threadIdx.x < 2) corr[2 * t + threadIdx.x] = (threadIdx.x == 0 ? v[0] : v[1]) * inv;
+}
+
+void launch_gram_corr(int T, int n, const double* E, const double* F, double* corr, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_corr, dim3((unsigned)T), dim3(256), 0, s, n, E, F, corr);
 }
 
 // ------------------------------------------------------------------------------------
