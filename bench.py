@@ -86,6 +86,11 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--mixed", action="store_true",
                     help="mixed-lattice batch: 8^3x16, 16^3x32, 24^3x48 with 8-32 sources each in one batch")
+    ap.add_argument("--fill", action="store_true",
+                    help="outer-product fill of the all-to-all propagator against the Gram-matrix route, "
+                         "L^3 x 2L lattices, and the fill kernel's matrix-core roofline")
+    ap.add_argument("--fill-sizes", default="4,6,8,10,12")
+    ap.add_argument("--fill-sources", default="16,64,256,1024")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
@@ -99,6 +104,9 @@ def main():
 
     if args.serve or args.mixed:
         serve_or_mixed(args)
+        return
+    if args.fill:
+        fill_study(args)
         return
 
     w = inputs.WORKLOADS[args.workload]
@@ -262,6 +270,82 @@ def main():
 
 
 SERVE_LATTICES = [((8, 8, 8, 16), 11), ((16, 16, 16, 32), 12), ((24, 24, 24, 48), 13)]
+
+
+FP64_PEAK_TFS = 78.6  # MI355X dense FP64 (matrix and vector)
+
+
+def fill_study(args):
+    """The paper's outer-product fill (Sec. 7, eq. Sfill) on the FP64 matrix cores against the
+    stochastic-operator route, for the same quantity C(t) = sum_{z,x} tr[S1 S2^dag] (source
+    timeslice 0, two independent sets of N sources / solutions) on L^3 x 2L lattices.  The fill
+    route costs 2 x 8 T M^2 N flop (M = 12 L^3), the Gram route 8 (T + 1) M N^2 + 8 T N^2, so
+    the fill wins only when N > ~M.  Fields are synthetic (counter-hash noise, also for the
+    "solutions": the cost does not depend on the values); both routes are checked to agree.
+    Also times one fill of S at 8^3x16 with 1024 sources for the kernel's roofline."""
+    import numpy as np
+    import torch
+
+    from paper_1405_4524_amd import a2a
+
+    ctx = a2a.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+    out = {"mode": "fill", "quantity": "C(t) = sum_{z,x} tr[S1(t,z;0,x) S2(t,z;0,x)^dag], FP64",
+           "peak_fp64_tflops": FP64_PEAK_TFS, "rows": []}
+
+    def fields(L, N, seed):
+        dims = (L, L, L, 2 * L)
+        fs = []
+        for k in range(4):
+            f = torch.empty((N, 2 * L, L, L, L, 4, 3, 2), dtype=torch.float64, device="cuda")
+            ctx.z2_noise_dev(dims, seed + k, 0, N, f)
+            fs.append(f)
+        torch.cuda.synchronize()
+        return dims, fs
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, r
+
+    for L in [int(x) for x in args.fill_sizes.split(",")]:
+        for N in [int(x) for x in args.fill_sources.split(",")]:
+            M, T = 12 * L ** 3, 2 * L
+            if 4 * N * M * T * 16 > 64e9:
+                continue
+            dims, (X1, e1, X2, e2) = fields(L, N, 100)
+            fl_fill = 2 * 8 * T * M * M * N
+            fl_gram = 8 * (T + 1) * M * N * N + 8 * T * N * N
+            reps_f = 1 if fl_fill > 2e13 else 3
+            tf, cf = timed(lambda: ctx.contract_fill_2pt_dev(X1, e1, X2, e2, N, dims, 0, method="fill"), reps_f)
+            tg, cg = timed(lambda: ctx.contract_fill_2pt_dev(X1, e1, X2, e2, N, dims, 0, method="gram"), 3)
+            agree = float(np.max(np.abs(cf - cg)) / np.max(np.abs(cg)))
+            row = {"L": L, "N": N, "M": M, "fill_s": round(tf, 5), "gram_s": round(tg, 5),
+                   "fill_over_gram": round(tf / tg, 2), "fill_tflops": round(fl_fill / tf / 1e12, 2),
+                   "gram_tflops": round(fl_gram / tg / 1e12, 2), "rel_diff": agree}
+            out["rows"].append(row)
+            log(f"fill study L={L} N={N}: fill {tf:.4f}s gram {tg:.4f}s ({row['fill_tflops']} / "
+                f"{row['gram_tflops']} TF/s), agree {agree:.1e}")
+            del X1, e1, X2, e2
+            torch.cuda.empty_cache()
+    # the fill kernel alone: one S at 8^3x16 from 1024 sources
+    L, N = 8, 1024
+    dims, (X1, e1, _, _) = fields(L, N, 200)
+    M = 12 * L ** 3
+    S = torch.empty((M, M, 2), dtype=torch.float64, device="cuda")
+    ts, _ = timed(lambda: ctx.fill_propagator_dev(X1, e1, N, dims, 0, 3, S), 10)
+    fl = 8 * M * M * N
+    byts = 2 * M * N * 16 + M * M * 16
+    out["fill_kernel"] = {"workload": "S(t=3, z; 0, x) at 8^3x16 from 1024 sources", "M": M, "K": N,
+                          "ms": round(ts * 1e3, 4), "flop": fl, "compulsory_bytes": byts,
+                          "roofline": {"bound": "mfma", "achieved": round(fl / ts / 1e12, 2),
+                                       "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                                       "frac": round(fl / ts / 1e12 / FP64_PEAK_TFS, 4)}}
+    log(f"fill kernel: {ts * 1e3:.3f} ms, {fl / ts / 1e12:.2f} TF/s")
+    print(json.dumps(out))
 
 
 def serve_or_mixed(args):
