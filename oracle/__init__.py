@@ -14,7 +14,8 @@ Parity status of every function: pinned by the ``-m "not gpu"`` tests in
 a hand-computed clover, dense LU solves, the exact correlator from unit sources, the
 free-field correlator closed form, estimator statistics; the outer-product fill by the dense
 inverse under full dilution, a hand-built dagger block and the Gram-matrix form of its
-contraction).
+contraction; dilution by its partition of the noise, momentum-projected operators by the C
+oracle at zero momentum and by dense-inverse traces with phases under full dilution).
 """
 from __future__ import annotations
 
@@ -329,4 +330,82 @@ def contract_fill(eta1, X1, eta2, X2, t_src):
         S1 = fill_propagator(eta1, X1, t_src, t)
         S2 = fill_propagator(eta2, X2, t_src, t)
         C[t] = np.sum(S1 * np.conj(S2))  # tr[S1 S2^dag] summed over both sites
+    return C
+
+
+# ---------------------------------------------------------------------------------------
+# dilution and momentum projection (Sec. 7: time-spin-colour dilution; Sec. 5 momentum
+# projection of the pion operators)
+# ---------------------------------------------------------------------------------------
+DILUTE_NONE, DILUTE_T, DILUTE_SC, DILUTE_TSC = 0, 1, 2, 3
+
+
+def dilution_size(scheme, T):
+    return {DILUTE_NONE: 1, DILUTE_T: T, DILUTE_SC: 12, DILUTE_TSC: 12 * T}[scheme]
+
+
+def dilute(eta, scheme):
+    """Diluted sources: every noise vector eta_i is split into pieces with disjoint supports
+    (one timeslice, one spin-colour component, or both), in the order noise vector, then
+    piece d = t, d = 3 spin + colour, or d = 12 t + 3 spin + colour.  The pieces of one noise
+    vector sum to it."""
+    eta = _c(eta)
+    N, T = eta.shape[0], eta.shape[1]
+    D = dilution_size(scheme, T)
+    out = np.zeros((N * D,) + eta.shape[1:], np.complex128)
+    for i in range(N):
+        for d in range(D):
+            v = out[i * D + d]
+            if scheme == DILUTE_NONE:
+                v[...] = eta[i]
+            elif scheme == DILUTE_T:
+                v[d] = eta[i, d]
+            elif scheme == DILUTE_SC:
+                v[..., d // 3, d % 3] = eta[i, ..., d // 3, d % 3]
+            else:
+                t, sc = d // 12, d % 12
+                v[t, ..., sc // 3, sc % 3] = eta[i, t, ..., sc // 3, sc % 3]
+    return out
+
+
+def momentum_phase(dims, p):
+    """exp(-i p.y) on the spatial sites (z, y, x), p = 2 pi (n_x / X, n_y / Y, n_z / Z)."""
+    X, Y, Z = dims[0], dims[1], dims[2]
+    z, y, x = np.meshgrid(np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    return np.exp(-2j * np.pi * (p[0] * x / X + p[1] * y / Y + p[2] * z / Z))
+
+
+def stochastic_operators_mom(eta, X, p):
+    """O[t, a, b] = sum_{y in t} exp(-i p.y) eta_a(y)^dag gamma_5 X_b(y) (eq. stoop with the
+    momentum projection of the operator at the source)."""
+    eta, X = _c(eta), _c(X)
+    T = eta.shape[1]
+    dims = (eta.shape[4], eta.shape[3], eta.shape[2], T)
+    ph = momentum_phase(dims, p)
+    g5 = np.real(np.diag(gamma(4)))
+    O = np.empty((T, eta.shape[0], X.shape[0]), np.complex128)
+    for t in range(T):
+        O[t] = np.einsum("azyxsc,zyx,s,bzyxsc->ab", np.conj(eta[:, t]), ph, g5, X[:, t])
+    return O
+
+
+def pion_mom(eta, X, p, group=1, mode=MODE_UNBIASED):
+    """C(dt, p) = sum_{t0} sum_{a, b} O_ab(t0 + dt, p) O_ba(t0, -p) over pairs of sources from
+    different noise vectors (sources a and b belong to noise vectors a // group, b // group;
+    group = pieces per noise vector after dilution), normalised by 1 / (T n (n - 1)) with n
+    noise vectors; MODE_RAW_ALL sums every pair without normalisation."""
+    Op = stochastic_operators_mom(eta, X, p)
+    Om = stochastic_operators_mom(eta, X, [-q for q in p])
+    T, N, _ = Op.shape
+    noise = np.arange(N) // group
+    keep = np.ones((N, N)) if mode == MODE_RAW_ALL else (noise[:, None] != noise[None, :]).astype(float)
+    C = np.empty(T, np.complex128)
+    for dt in range(T):
+        acc = 0j
+        for t0 in range(T):
+            acc += np.sum(keep * Op[(t0 + dt) % T] * Om[t0].T)
+        C[dt] = acc
+    if mode != MODE_RAW_ALL:
+        n = N // group
+        C /= T * n * (n - 1)
     return C
