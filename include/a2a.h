@@ -75,6 +75,12 @@ extern "C" {
 #define A2A_OP_HOP_EO 2  /* out_e = (H in)_e from in_o; out_o = 0                           */
 #define A2A_OP_HOP_OE 3  /* out_o = (H in)_o from in_e; out_e = 0                           */
 
+/* ---- dilution schemes (a2a_dilute_dev) ----------------------------------------------- */
+#define A2A_DILUTE_NONE 0  /* D = 1: the noise vector itself                                  */
+#define A2A_DILUTE_T 1     /* D = T: one timeslice per piece, d = t                            */
+#define A2A_DILUTE_SC 2    /* D = 12: one spin-colour component per piece, d = 3 spin + colour */
+#define A2A_DILUTE_TSC 3   /* D = 12 T: both, d = 12 t + 3 spin + colour                       */
+
 /* ---- correlator normalisation modes -------------------------------------------------- */
 #define A2A_PION_UNBIASED 0   /* C(dt) = 1/(T N (N-1)) sum_t0 sum_{a != b} O_ab(t0+dt) O_ba(t0) */
 #define A2A_PION_ALL_PAIRS 1  /* C(dt) = 1/(T N^2) sum_t0 sum_{a, b} ... (the printed Sec. 7 form)  */
@@ -217,6 +223,25 @@ int a2a_contract_fill_2pt_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *
                               const double *sol2_dev, const double *src2_dev, int nrhs, int t_src, double *corr_host);
 int a2a_contract_gram_2pt_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *sol1_dev, const double *src1_dev,
                               const double *sol2_dev, const double *src2_dev, int nrhs, int t_src, double *corr_host);
+
+/* ---- dilution and momentum projection (Sec. 7 dilution; Sec. 5 momentum states) -------- */
+/* out (device, canonical, nnoise * D sources) = every noise vector split into D pieces with
+ * disjoint supports (scheme A2A_DILUTE_*; pieces of noise vector i are sources i D .. i D + D-1,
+ * in the order of d).  The pieces of one noise vector sum to it. */
+int a2a_dilute_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *noise_dev, int nnoise, int scheme,
+                   double *out_dev);
+/* Pion correlator projected onto momentum p = 2 pi (n_x / X, n_y / Y, n_z / Z) for each of the
+ * nmom integer triples in moms (host, [nmom][3]):
+ *   O_ab(t, p) = sum_{y in t} exp(-i p.y) eta_a(y)^dag gamma_5 X_b(y),
+ *   corr[m][dt] = sum_t0 sum_{a, b} O_ab(t0 + dt, p) O_ba(t0, -p)
+ * over pairs of sources from different noise vectors (sources a and b belong to noise vectors
+ * a / group and b / group: group = D after dilution, 1 without), normalised by
+ * 1 / (T n (n - 1)) with n = nrhs / group (mode 0), or over all pairs without normalisation
+ * (mode 3, e.g. for full dilution).  corr: host complex [nmom][T].  With group = 1, p = 0 and
+ * mode 0 this is a2a_contract_pion_2pt's unbiased correlator. */
+int a2a_contract_pion_mom_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *sources_dev,
+                              const double *solutions_dev, int nrhs, int group, int nmom, const int *moms,
+                              int mode, double *corr_host);
 
 /* ---- synthetic inputs ---------------------------------------------------------------- */
 /* Complex-Z2 noise (Sec. 7 "Z2 noise", here (+-1 +- i)/sqrt 2) written to a canonical

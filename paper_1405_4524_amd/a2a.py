@@ -23,6 +23,7 @@ F64, F32, F16_F32, BF16_F32 = 0, 1, 2, 3
 OP_FULL_D, OP_SCHUR, OP_HOP_EO, OP_HOP_OE = 0, 1, 2, 3
 PION_UNBIASED, PION_ALL_PAIRS = 0, 1
 SOLVER_BICGSTAB, SOLVER_CGNR = 0, 1
+DILUTE_NONE, DILUTE_T, DILUTE_SC, DILUTE_TSC = 0, 1, 2, 3
 PREC_NAMES = {F64: "f64", F32: "f32", F16_F32: "f16/f32", BF16_F32: "bf16/f32"}
 ERR_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOTCONV: "ENOTCONV", EBREAKDOWN: "EBREAKDOWN", ENAN: "ENAN",
              EHANDLE: "EHANDLE", EDEVICE: "EDEVICE", EAGAIN: "EAGAIN"}
@@ -72,6 +73,8 @@ _SIG = {
     "a2a_contract_pipi_2pt_dev": (I, [P, ctypes.POINTER(Geom), P, P, I, P, P, P]),
     "a2a_z2_noise_dev": (I, [P, ctypes.POINTER(Geom), ULL, LL, I, P]),
     "a2a_fill_propagator_dev": (I, [P, ctypes.POINTER(Geom), P, P, I, I, I, I, P]),
+    "a2a_dilute_dev": (I, [P, ctypes.POINTER(Geom), P, I, I, P]),
+    "a2a_contract_pion_mom_dev": (I, [P, ctypes.POINTER(Geom), P, P, I, I, I, P, I, P]),
     "a2a_contract_fill_2pt_dev": (I, [P, ctypes.POINTER(Geom), P, P, P, P, I, I, P]),
     "a2a_contract_gram_2pt_dev": (I, [P, ctypes.POINTER(Geom), P, P, P, P, I, I, P]),
     "a2a_engine_create": (I, [P, ctypes.c_char_p, ctypes.POINTER(P)]),
@@ -355,6 +358,21 @@ class Context:
         f = lib().a2a_contract_fill_2pt_dev if method == "fill" else lib().a2a_contract_gram_2pt_dev
         self._chk(f(self._c, ctypes.byref(g), _tptr(sol1_t), _tptr(src1_t), _tptr(sol2_t), _tptr(src2_t), int(nrhs),
                     int(t_src), corr.ctypes.data_as(P)))
+        return corr
+
+    # ---- dilution and momentum projection (device tensors in the canonical spinor layout)
+    def dilute_dev(self, noise_t, nnoise, dims, scheme, out_t, t_bc=-1):
+        g = geom(dims, t_bc)
+        self._chk(lib().a2a_dilute_dev(self._c, ctypes.byref(g), _tptr(noise_t), int(nnoise), int(scheme),
+                                       _tptr(out_t)))
+
+    def contract_pion_mom_dev(self, src_t, sol_t, nrhs, dims, moms, group=1, mode=PION_UNBIASED, t_bc=-1):
+        g = geom(dims, t_bc)
+        m = np.ascontiguousarray(np.asarray(moms, dtype=np.int32).reshape(-1, 3))
+        corr = np.empty((m.shape[0], dims[3]), np.complex128)
+        self._chk(lib().a2a_contract_pion_mom_dev(self._c, ctypes.byref(g), _tptr(src_t), _tptr(sol_t), int(nrhs),
+                                                  int(group), m.shape[0], m.ctypes.data_as(P), int(mode),
+                                                  corr.ctypes.data_as(P)))
         return corr
 
     # ---- engine / instrumentation

@@ -1096,6 +1096,99 @@ extern "C" int a2a_contract_gram_2pt_dev(a2a_ctx* h, const a2a_geom* geom, const
 }
 
 // =========================================================================================
+// dilution and momentum projection (Sec. 7: time-spin-colour dilution; Sec. 5: pions projected
+// onto momentum states)
+// =========================================================================================
+static int dilution_size(int scheme, int T) {
+  return scheme == A2A_DILUTE_NONE ? 1 : scheme == A2A_DILUTE_T ? T : scheme == A2A_DILUTE_SC ? 12 : 12 * T;
+}
+
+extern "C" int a2a_dilute_dev(a2a_ctx* h, const a2a_geom* geom, const double* noise, int nnoise, int scheme,
+                              double* out) {
+  if (!h || !noise || !out) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  Geo g;
+  if (geom_to_geo(geom, &g)) return c->fail(A2A_EINVAL, "bad lattice geometry");
+  if (nnoise < 1) return c->fail(A2A_EINVAL, "nnoise must be positive");
+  if (scheme < A2A_DILUTE_NONE || scheme > A2A_DILUTE_TSC) return c->fail(A2A_EINVAL, "unknown dilution scheme");
+  launch_dilute(g, nnoise, scheme, dilution_size(scheme, g.T), noise, out, c->stream);
+  A2A_HIP(c, hipGetLastError());
+  return c->sync();
+}
+
+// exp(-i p.y) on the spatial sites of a timeslice (x fastest), the angle reduced exactly
+static void momentum_phase(const Geo& g, const int* p, std::vector<double>& ph) {
+  const long V3 = (long)g.X * g.Y * g.Z;
+  ph.resize(2 * V3);
+  const double two_pi = 6.283185307179586476925;
+  long s = 0;
+  for (int z = 0; z < g.Z; ++z)
+    for (int y = 0; y < g.Y; ++y)
+      for (int x = 0; x < g.X; ++x, ++s) {
+        const long ax = (((long)p[0] * x) % g.X + g.X) % g.X, ay = (((long)p[1] * y) % g.Y + g.Y) % g.Y,
+                   az = (((long)p[2] * z) % g.Z + g.Z) % g.Z;
+        const double f = (double)ax / g.X + (double)ay / g.Y + (double)az / g.Z;
+        ph[2 * s] = std::cos(two_pi * f);
+        ph[2 * s + 1] = -std::sin(two_pi * f);
+      }
+}
+
+extern "C" int a2a_contract_pion_mom_dev(a2a_ctx* h, const a2a_geom* geom, const double* src, const double* sol,
+                                         int nrhs, int group, int nmom, const int* moms, int mode,
+                                         double* corr) {
+  if (!h || !src || !sol || !moms || !corr) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  Geo g;
+  if (geom_to_geo(geom, &g)) return c->fail(A2A_EINVAL, "bad lattice geometry");
+  if (group < 1 || nrhs < 1 || nrhs % group) return c->fail(A2A_EINVAL, "nrhs must be a positive multiple of group");
+  if (mode != 0 && mode != 3) return c->fail(A2A_EINVAL, "mode must be 0 (unbiased) or 3 (raw, all pairs)");
+  if (mode == 0 && nrhs / group < 2) return c->fail(A2A_EINVAL, "the unbiased estimator needs two noise vectors");
+  if (nmom < 1) return c->fail(A2A_EINVAL, "nmom must be positive");
+  const int n = nrhs;
+  const long K = 12L * g.X * g.Y * g.Z;
+  const int ntb = (n + 63) / 64;
+  long want = 4096 / std::max(1, g.T * ntb * ntb);
+  const int nchunk = (int)std::max(1L, std::min(want, (K + 255) / 256));
+  const size_t nn = (size_t)n * n;
+  const size_t V3 = (size_t)g.X * g.Y * g.Z;
+  void *part = nullptr, *Op = nullptr, *Om = nullptr, *ph = nullptr, *dc = nullptr;
+  A2A_TRY(c->dalloc(&part, sizeof(double) * 2 * (size_t)g.T * nchunk * nn));
+  int rc = c->dalloc(&Op, sizeof(double) * 2 * (size_t)g.T * nn);
+  if (!rc) rc = c->dalloc(&Om, sizeof(double) * 2 * (size_t)g.T * nn);
+  if (!rc) rc = c->dalloc(&ph, sizeof(double) * 4 * V3);
+  if (!rc) rc = c->dalloc(&dc, sizeof(double) * 2 * g.T);
+  std::vector<double> hp, hm;
+  for (int m = 0; m < nmom && !rc; ++m) {
+    const int* p = moms + 3 * m;
+    const int q[3] = {-p[0], -p[1], -p[2]};
+    momentum_phase(g, p, hp);
+    momentum_phase(g, q, hm);
+    double* php = (double*)ph;
+    double* phm = php + 2 * V3;
+    if (hipMemcpyAsync(php, hp.data(), sizeof(double) * 2 * V3, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(phm, hm.data(), sizeof(double) * 2 * V3, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+      rc = c->fail(A2A_EDEVICE, "phase upload failed");
+      break;
+    }
+    launch_stoch_ops(g, n, src, sol, (double*)part, nchunk, (double*)Op, c->stream, 1, 0, g.T, php);
+    launch_stoch_ops(g, n, src, sol, (double*)part, nchunk, (double*)Om, c->stream, 1, 0, g.T, phm);
+    launch_pion_mom(g.T, n, group, mode, (const double*)Op, (const double*)Om, (double*)dc, c->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) rc = c->fail(A2A_EDEVICE, std::string("momentum contraction: ") + hipGetErrorString(e));
+    if (!rc) rc = copy_to_host(c, corr + 2 * (size_t)m * g.T, dc, sizeof(double) * 2 * g.T);
+  }
+  c->sync();
+  c->dfree(part);
+  c->dfree(Op);
+  c->dfree(Om);
+  c->dfree(ph);
+  c->dfree(dc);
+  return rc;
+}
+
+// =========================================================================================
 // serving engine: continuous batching
 // =========================================================================================
 struct Request {

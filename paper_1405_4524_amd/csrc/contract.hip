@@ -17,7 +17,8 @@ constexpr int KC = 16;   // complex elements per K step
 
 __global__ __launch_bounds__(256) void k_stoch_partial(int n, long V, int V3, int nchunk, int kchunk, int g5,
                                                         int t_first, const double* __restrict__ eta,
-                                                        const double* __restrict__ X, double* partial) {
+                                                        const double* __restrict__ X,
+                                                        const double* __restrict__ phase, double* partial) {
   __shared__ double2 Es[CT][KC + 1];
   __shared__ double2 Xs[CT][KC + 1];
   const int chunk = blockIdx.x, tl = blockIdx.y, t = t_first + tl;
@@ -47,6 +48,10 @@ __global__ __launch_bounds__(256) void k_stoch_partial(int n, long V, int V3, in
         if (a0 + row < n) {
           const double* p = eta + 2 * ((size_t)(a0 + row) * src_stride + tbase + k);
           ev = make_double2(p[0], p[1]);
+          if (phase) {  // eta conj(f) with f = exp(-i p.y): the product below takes conj(eta) f
+            const double fr = phase[2 * (k / 12)], fi = phase[2 * (k / 12) + 1];
+            ev = make_double2(ev.x * fr + ev.y * fi, ev.y * fr - ev.x * fi);
+          }
         }
         if (b0 + row < n) {
           const double* p = X + 2 * ((size_t)(b0 + row) * src_stride + tbase + k);
@@ -104,7 +109,7 @@ __global__ void k_stoch_sum(int n, int T, int nchunk, const double* partial, dou
 }
 
 void launch_stoch_ops(const Geo& g, int n, const double* eta, const double* X, double* partial, int nchunk,
-                      double* O, hipStream_t s, int g5, int t_first, int nt) {
+                      double* O, hipStream_t s, int g5, int t_first, int nt, const double* phase) {
   const int V3 = g.X * g.Y * g.Z;
   const long V = (long)V3 * g.T;
   const long K = 12L * V3;
@@ -114,7 +119,7 @@ void launch_stoch_ops(const Geo& g, int n, const double* eta, const double* X, d
   const int ntb = (n + CT - 1) / CT;
   dim3 grid(nchunk, nt, ntb * ntb);
   hipLaunchKernelGGL(k_stoch_partial, grid, dim3(256), 0, s, n, V, V3, nchunk, (int)kchunk, g5, t_first, eta, X,
-                     partial);
+                     phase, partial);
   const long tot = (long)nt * n * n;
   hipLaunchKernelGGL(k_stoch_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, nt, nchunk, partial, O);
 }
@@ -140,6 +145,36 @@ __global__ __launch_bounds__(256) void k_gram_corr(int n, const double* E, const
 
 void launch_gram_corr(int T, int n, const double* E, const double* F, double* corr, hipStream_t s) {
   hipLaunchKernelGGL(k_gram_corr, dim3((unsigned)T), dim3(256), 0, s, n, E, F, corr);
+}
+
+// Momentum-projected pion from O(t, p) and O(t, -p): corr[dt] = sum_t0 sum_{a, b}
+// Op[t0 + dt][a][b] Om[t0][b][a] over pairs of sources from different noise vectors (a / group
+// != b / group), normalised by 1 / (T n (n - 1)) with n = N / group noise vectors (mode 0), or
+// over all pairs without normalisation (mode 3).
+__global__ __launch_bounds__(256) void k_pion_mom(int T, int N, int group, int mode, const double* Op,
+                                                  const double* Om, double* corr) {
+  const int dt = blockIdx.x;
+  const long per = (long)N * N;
+  double v[2] = {0.0, 0.0};
+  for (long e = threadIdx.x; e < (long)T * per; e += 256) {
+    const int t0 = (int)(e / per);
+    const int a = (int)((e % per) / N), b = (int)(e % N);
+    if (mode == 0 && a / group == b / group) continue;
+    const int t1 = (t0 + dt) % T;
+    const double* x = Op + 2 * ((size_t)t1 * per + (size_t)a * N + b);
+    const double* y = Om + 2 * ((size_t)t0 * per + (size_t)b * N + a);
+    v[0] += x[0] * y[0] - x[1] * y[1];
+    v[1] += x[0] * y[1] + x[1] * y[0];
+  }
+  block_sum_n<2, 256>(v);
+  const double nv = (double)(N / group);
+  const double norm = mode == 0 ? 1.0 / ((double)T * nv * (nv - 1.0)) : 1.0;
+  if (threadIdx.x < 2) corr[2 * dt + threadIdx.x] = (threadIdx.x == 0 ? v[0] : v[1]) * norm;
+}
+
+void launch_pion_mom(int T, int N, int group, int mode, const double* Op, const double* Om, double* corr,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_pion_mom, dim3((unsigned)T), dim3(256), 0, s, T, N, group, mode, Op, Om, corr);
 }
 
 // ------------------------------------------------------------------------------------

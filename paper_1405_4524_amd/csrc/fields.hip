@@ -412,4 +412,31 @@ void launch_z2_noise(long V, int nsrc, unsigned long long seed, long long src_of
                      (long long)(src_offset * 12 * V), out);
 }
 
+// Dilution (Sec. 7, "time-spin-colour dilution"): output source i D + d is noise vector i
+// restricted to piece d -- one timeslice (scheme 1, d = t), one spin-colour component (scheme 2,
+// d = 3 spin + colour) or both (scheme 3, d = 12 t + 3 spin + colour); zero elsewhere.
+// Scheme 0 copies.  One thread per complex output element.
+__global__ __launch_bounds__(BS) void k_dilute(long total, long V3, int T, int D, int scheme, const double* noise,
+                                               double* out) {
+  const long e = (long)blockIdx.x * BS + threadIdx.x;
+  if (e >= total) return;
+  const long per = 12L * V3 * T;  // complex per source
+  const long src = e / per, k = e % per;
+  const long i = src / D;
+  const int d = (int)(src % D);
+  const int sc = (int)(k % 12), t = (int)(k / (12L * V3));
+  const bool on = scheme == 0 || (scheme == 1 && t == d) || (scheme == 2 && sc == d) || (scheme == 3 && 12 * t + sc == d);
+  const double* in = noise + 2 * (i * per + k);
+  out[2 * e] = on ? in[0] : 0.0;
+  out[2 * e + 1] = on ? in[1] : 0.0;
+}
+
+void launch_dilute(const Geo& g, int nnoise, int scheme, int D, const double* noise, double* out, hipStream_t s) {
+  const long V3 = (long)g.X * g.Y * g.Z;
+  const long total = (long)nnoise * D * 12 * V3 * g.T;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_dilute, dim3((unsigned)((total + BS - 1) / BS)), dim3(BS), 0, s, total, V3, g.T, D, scheme,
+                     noise, out);
+}
+
 }  // namespace a2a
