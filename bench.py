@@ -90,6 +90,10 @@ def main():
                     help="outer-product fill of the all-to-all propagator against the Gram-matrix route, "
                          "L^3 x 2L lattices, and the fill kernel's matrix-core roofline")
     ap.add_argument("--fill-sizes", default="4,6,8,10,12")
+    ap.add_argument("--dilution", action="store_true",
+                    help="time-spin-colour dilution against undiluted noise at the same number of solves, "
+                         "with momentum-projected pion correlators (8^3x16)")
+    ap.add_argument("--dil-noise", type=int, default=4, help="noise vectors of the diluted set")
     ap.add_argument("--fill-sources", default="16,64,256,1024")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -107,6 +111,9 @@ def main():
         return
     if args.fill:
         fill_study(args)
+        return
+    if args.dilution:
+        dilution_study(args)
         return
 
     w = inputs.WORKLOADS[args.workload]
@@ -345,6 +352,95 @@ def fill_study(args):
                                        "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
                                        "frac": round(fl / ts / 1e12 / FP64_PEAK_TFS, 4)}}
     log(f"fill kernel: {ts * 1e3:.3f} ms, {fl / ts / 1e12:.2f} TF/s")
+    print(json.dumps(out))
+
+
+DIL_MOMS = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 1, 1)]
+
+
+def dilution_study(args):
+    """Time-spin-colour dilution (Sec. 7) at 8^3x16 (kappa 0.125, c_sw 1.2, links exp(i 0.3 H)):
+    n noise vectors, each split into 12 T = 192 pieces, are solved (FP16 inner, FP64 reliable
+    updates, tol 1e-10) and contracted into pion correlators at six momenta; an undiluted set of
+    as many noise vectors as there are diluted pieces is solved and contracted the same way.
+    Reported: solve and contraction times, and the jackknife error of C(dt, p = 0) over noise
+    vectors for both sets, i.e. the statistical error at equal cost in solves."""
+    import numpy as np
+    import torch
+
+    from paper_1405_4524_amd import a2a, inputs
+
+    dims, kappa, csw, tbc, eps = (8, 8, 8, 16), 0.125, 1.2, -1, 0.3
+    X, Y, Z, T = dims
+    nv = args.dil_noise
+    D = 12 * T
+    n = nv * D
+    ctx = a2a.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+    ctx.set_option("rhs_block", args.rhs_block)
+    g = ctx.load_gauge(inputs.gauge_field(dims, eps, 1), tbc)
+    c = ctx.load_clover(g, csw)
+    shape = (T, Z, Y, X, 4, 3, 2)
+    out = {"mode": "dilution", "dims": list(dims), "kappa": kappa, "c_sw": csw, "noise_vectors": nv,
+           "pieces_per_noise_vector": D, "solves_per_set": n, "moms": DIL_MOMS}
+
+    def solve(src):
+        sol = torch.zeros_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info, rc = ctx.solve_propagators_dev(c, src, sol, src.shape[0], kappa, csw, tol=1e-10, prec=a2a.F16_F32,
+                                             allow=())
+        torch.cuda.synchronize()
+        return sol, time.perf_counter() - t0, max(x["true_rel_residual"] for x in info)
+
+    noise = torch.empty((nv,) + shape, dtype=torch.float64, device="cuda")
+    ctx.z2_noise_dev(dims, 51, 0, nv, noise)
+    src_d = torch.empty((n,) + shape, dtype=torch.float64, device="cuda")
+    ctx.dilute_dev(noise, nv, dims, a2a.DILUTE_TSC, src_d)
+    sol_d, ts_d, res_d = solve(src_d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    C_d = ctx.contract_pion_mom_dev(src_d, sol_d, n, dims, DIL_MOMS, scheme=a2a.DILUTE_TSC)
+    tc_d = time.perf_counter() - t0
+    loo = []
+    for k in range(nv):  # jackknife over noise vectors
+        keep = torch.cat([src_d[i * D:(i + 1) * D] for i in range(nv) if i != k])
+        keepx = torch.cat([sol_d[i * D:(i + 1) * D] for i in range(nv) if i != k])
+        loo.append(ctx.contract_pion_mom_dev(keep, keepx, n - D, dims, DIL_MOMS[:1], scheme=a2a.DILUTE_TSC)[0])
+        del keep, keepx
+    loo = np.array(loo)
+    err_d = np.sqrt((nv - 1) / nv * np.sum(np.abs(loo - loo.mean(axis=0)) ** 2, axis=0))
+    del src_d, sol_d
+    torch.cuda.empty_cache()
+
+    src_u = torch.empty((n,) + shape, dtype=torch.float64, device="cuda")
+    ctx.z2_noise_dev(dims, 52, 0, n, src_u)
+    sol_u, ts_u, res_u = solve(src_u)
+    t0 = time.perf_counter()
+    C_u, O = ctx.contract_pion_2pt_dev(src_u, sol_u, n, dims, want_O=True)
+    tc_u = time.perf_counter() - t0
+    # leave-one-out from O: remove the pairs that involve source k
+    P = np.stack([np.einsum("tab,tba->", np.roll(O, -dt, axis=0), O) for dt in range(T)])  # all pairs
+    diagp = np.stack([np.einsum("taa,taa->a", np.roll(O, -dt, axis=0), O) for dt in range(T)])  # a == b
+    rowk = np.stack([np.einsum("tkb,tbk->k", np.roll(O, -dt, axis=0), O) for dt in range(T)])  # a == k
+    colk = np.stack([np.einsum("tak,tka->k", np.roll(O, -dt, axis=0), O) for dt in range(T)])  # b == k
+    tot = P - diagp.sum(axis=1)
+    loo_u = (tot[:, None] - (rowk - diagp) - (colk - diagp)) / (T * (n - 1) * (n - 2))
+    err_u = np.sqrt((n - 1) / n * np.sum(np.abs(loo_u - loo_u.mean(axis=1, keepdims=True)) ** 2, axis=1))
+    rows = []
+    for dt in range(1, T // 2 + 1):
+        rows.append({"dt": dt, "C_diluted": round(C_d[0][dt].real, 8), "err_diluted": float(f"{err_d[dt]:.3e}"),
+                     "C_undiluted": round(C_u[dt].real, 8), "err_undiluted": float(f"{err_u[dt]:.3e}"),
+                     "error_ratio": round(float(err_u[dt] / err_d[dt]), 2)})
+    out.update({"solve_s_diluted": round(ts_d, 3), "solve_s_undiluted": round(ts_u, 3),
+                "rhs_per_s": round(n / ts_d, 1), "max_true_rel_residual": max(res_d, res_u),
+                "contract_s_diluted_6_moms": round(tc_d, 3), "contract_s_undiluted_p0": round(tc_u, 3),
+                "pion_p0": rows,
+                "pion_moms_dt1": {str(p): round(C_d[m][1].real, 8) for m, p in enumerate(DIL_MOMS)}})
+    log(f"dilution: {n} solves {ts_d:.2f}s / {ts_u:.2f}s; contraction {tc_d:.3f}s (6 momenta) / {tc_u:.3f}s")
+    for r in rows[:6]:
+        log(f"  dt {r['dt']}: diluted {r['C_diluted']:.4e} +- {r['err_diluted']:.1e}, undiluted "
+            f"{r['C_undiluted']:.4e} +- {r['err_undiluted']:.1e}")
+    ctx.unload(g)
     print(json.dumps(out))
 
 

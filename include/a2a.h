@@ -234,13 +234,15 @@ int a2a_dilute_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *noise_dev, 
  * nmom integer triples in moms (host, [nmom][3]):
  *   O_ab(t, p) = sum_{y in t} exp(-i p.y) eta_a(y)^dag gamma_5 X_b(y),
  *   corr[m][dt] = sum_t0 sum_{a, b} O_ab(t0 + dt, p) O_ba(t0, -p)
- * over pairs of sources from different noise vectors (sources a and b belong to noise vectors
- * a / group and b / group: group = D after dilution, 1 without), normalised by
- * 1 / (T n (n - 1)) with n = nrhs / group (mode 0), or over all pairs without normalisation
- * (mode 3, e.g. for full dilution).  corr: host complex [nmom][T].  With group = 1, p = 0 and
- * mode 0 this is a2a_contract_pion_2pt's unbiased correlator. */
+ * over pairs of sources from different noise vectors, the sources being the output of
+ * a2a_dilute_dev with this scheme (nrhs = n D; sources a and b belong to noise vectors a / D
+ * and b / D), normalised by 1 / (T n (n - 1)) (mode 0), or over all pairs without
+ * normalisation (mode 3, e.g. for full dilution).  With time dilution (A2A_DILUTE_T, _TSC)
+ * only the pieces on timeslice t enter O(t), which cuts the work by T.  corr: host complex
+ * [nmom][T].  With A2A_DILUTE_NONE, p = 0 and mode 0 this is a2a_contract_pion_2pt's
+ * unbiased correlator. */
 int a2a_contract_pion_mom_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *sources_dev,
-                              const double *solutions_dev, int nrhs, int group, int nmom, const int *moms,
+                              const double *solutions_dev, int nrhs, int scheme, int nmom, const int *moms,
                               int mode, double *corr_host);
 
 /* ---- synthetic inputs ---------------------------------------------------------------- */

@@ -366,12 +366,12 @@ class Context:
         self._chk(lib().a2a_dilute_dev(self._c, ctypes.byref(g), _tptr(noise_t), int(nnoise), int(scheme),
                                        _tptr(out_t)))
 
-    def contract_pion_mom_dev(self, src_t, sol_t, nrhs, dims, moms, group=1, mode=PION_UNBIASED, t_bc=-1):
+    def contract_pion_mom_dev(self, src_t, sol_t, nrhs, dims, moms, scheme=DILUTE_NONE, mode=PION_UNBIASED, t_bc=-1):
         g = geom(dims, t_bc)
         m = np.ascontiguousarray(np.asarray(moms, dtype=np.int32).reshape(-1, 3))
         corr = np.empty((m.shape[0], dims[3]), np.complex128)
         self._chk(lib().a2a_contract_pion_mom_dev(self._c, ctypes.byref(g), _tptr(src_t), _tptr(sol_t), int(nrhs),
-                                                  int(group), m.shape[0], m.ctypes.data_as(P), int(mode),
+                                                  int(scheme), m.shape[0], m.ctypes.data_as(P), int(mode),
                                                   corr.ctypes.data_as(P)))
         return corr
 

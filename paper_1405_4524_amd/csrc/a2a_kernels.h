@@ -138,9 +138,12 @@ void launch_z2_noise(long V, int nsrc, unsigned long long seed, long long src_of
 // stochastic operators O[t][a][b] (Sec. 7, eq. stoop) and the correlators built from them
 // (g5 = 0: without gamma_5, the Gram matrices <eta_a, X_b>_t; timeslices t_first .. + nt)
 // phase (complex per spatial site, or null): momentum projection O = sum_y phase(y) eta^dag g5 X
+// rows (or null), [T][na]: row r of O(t) is source rows[t na + r] (time-diluted sources)
 void launch_stoch_ops(const Geo& g, int n, const double* eta, const double* X, double* partial, int nchunk,
                       double* O, hipStream_t s, int g5 = 1, int t_first = 0, int nt = -1,
-                      const double* phase = nullptr);
+                      const double* phase = nullptr, const int* rows = nullptr, int na = 0);
+void launch_pion_mom_rows(int T, int N, int na, const int* rows, int group, int mode, const double* Op,
+                          const double* Om, double* corr, hipStream_t s);
 void launch_pion_mom(int T, int N, int group, int mode, const double* Op, const double* Om, double* corr,
                      hipStream_t s);
 void launch_dilute(const Geo& g, int nnoise, int scheme, int D, const double* noise, double* out, hipStream_t s);

@@ -1135,30 +1135,49 @@ static void momentum_phase(const Geo& g, const int* p, std::vector<double>& ph) 
 }
 
 extern "C" int a2a_contract_pion_mom_dev(a2a_ctx* h, const a2a_geom* geom, const double* src, const double* sol,
-                                         int nrhs, int group, int nmom, const int* moms, int mode,
+                                         int nrhs, int scheme, int nmom, const int* moms, int mode,
                                          double* corr) {
   if (!h || !src || !sol || !moms || !corr) return A2A_EINVAL;
   Ctx* c = &h->c;
   (void)hipSetDevice(c->device);
   Geo g;
   if (geom_to_geo(geom, &g)) return c->fail(A2A_EINVAL, "bad lattice geometry");
-  if (group < 1 || nrhs < 1 || nrhs % group) return c->fail(A2A_EINVAL, "nrhs must be a positive multiple of group");
+  if (scheme < A2A_DILUTE_NONE || scheme > A2A_DILUTE_TSC) return c->fail(A2A_EINVAL, "unknown dilution scheme");
+  const int group = dilution_size(scheme, g.T);
+  if (nrhs < 1 || nrhs % group) return c->fail(A2A_EINVAL, "nrhs must be a positive multiple of the dilution size");
   if (mode != 0 && mode != 3) return c->fail(A2A_EINVAL, "mode must be 0 (unbiased) or 3 (raw, all pairs)");
   if (mode == 0 && nrhs / group < 2) return c->fail(A2A_EINVAL, "the unbiased estimator needs two noise vectors");
   if (nmom < 1) return c->fail(A2A_EINVAL, "nmom must be positive");
-  const int n = nrhs;
+  const int n = nrhs, nv = nrhs / group;
+  // time-diluted pieces live on one timeslice: O(t) keeps only the rows of the pieces on t
+  const bool by_time = scheme == A2A_DILUTE_T || scheme == A2A_DILUTE_TSC;
+  const int per_t = scheme == A2A_DILUTE_TSC ? 12 : 1;
+  const int na = by_time ? nv * per_t : n;
+  std::vector<int> rows;
+  if (by_time) {
+    rows.resize((size_t)g.T * na);
+    for (int t = 0; t < g.T; ++t)
+      for (int i = 0; i < nv; ++i)
+        for (int q = 0; q < per_t; ++q) rows[(size_t)t * na + i * per_t + q] = i * group + per_t * t + q;
+  }
   const long K = 12L * g.X * g.Y * g.Z;
-  const int ntb = (n + 63) / 64;
-  long want = 4096 / std::max(1, g.T * ntb * ntb);
+  const int ntb = (n + 63) / 64, nta = (na + 63) / 64;
+  long want = 4096 / std::max(1, g.T * ntb * nta);
   const int nchunk = (int)std::max(1L, std::min(want, (K + 255) / 256));
-  const size_t nn = (size_t)n * n;
+  const size_t nn = (size_t)na * n;
   const size_t V3 = (size_t)g.X * g.Y * g.Z;
-  void *part = nullptr, *Op = nullptr, *Om = nullptr, *ph = nullptr, *dc = nullptr;
+  void *part = nullptr, *Op = nullptr, *Om = nullptr, *ph = nullptr, *dc = nullptr, *drows = nullptr;
   A2A_TRY(c->dalloc(&part, sizeof(double) * 2 * (size_t)g.T * nchunk * nn));
   int rc = c->dalloc(&Op, sizeof(double) * 2 * (size_t)g.T * nn);
   if (!rc) rc = c->dalloc(&Om, sizeof(double) * 2 * (size_t)g.T * nn);
   if (!rc) rc = c->dalloc(&ph, sizeof(double) * 4 * V3);
   if (!rc) rc = c->dalloc(&dc, sizeof(double) * 2 * g.T);
+  if (!rc && by_time) {
+    rc = c->dalloc(&drows, sizeof(int) * rows.size());
+    if (!rc && hipMemcpyAsync(drows, rows.data(), sizeof(int) * rows.size(), hipMemcpyHostToDevice, c->stream) !=
+                   hipSuccess)
+      rc = c->fail(A2A_EDEVICE, "row table upload failed");
+  }
   std::vector<double> hp, hm;
   for (int m = 0; m < nmom && !rc; ++m) {
     const int* p = moms + 3 * m;
@@ -1172,9 +1191,14 @@ extern "C" int a2a_contract_pion_mom_dev(a2a_ctx* h, const a2a_geom* geom, const
       rc = c->fail(A2A_EDEVICE, "phase upload failed");
       break;
     }
-    launch_stoch_ops(g, n, src, sol, (double*)part, nchunk, (double*)Op, c->stream, 1, 0, g.T, php);
-    launch_stoch_ops(g, n, src, sol, (double*)part, nchunk, (double*)Om, c->stream, 1, 0, g.T, phm);
-    launch_pion_mom(g.T, n, group, mode, (const double*)Op, (const double*)Om, (double*)dc, c->stream);
+    const int* dr = (const int*)drows;
+    launch_stoch_ops(g, n, src, sol, (double*)part, nchunk, (double*)Op, c->stream, 1, 0, g.T, php, dr, na);
+    launch_stoch_ops(g, n, src, sol, (double*)part, nchunk, (double*)Om, c->stream, 1, 0, g.T, phm, dr, na);
+    if (by_time)
+      launch_pion_mom_rows(g.T, n, na, dr, group, mode, (const double*)Op, (const double*)Om, (double*)dc,
+                           c->stream);
+    else
+      launch_pion_mom(g.T, n, group, mode, (const double*)Op, (const double*)Om, (double*)dc, c->stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) rc = c->fail(A2A_EDEVICE, std::string("momentum contraction: ") + hipGetErrorString(e));
     if (!rc) rc = copy_to_host(c, corr + 2 * (size_t)m * g.T, dc, sizeof(double) * 2 * g.T);
@@ -1185,6 +1209,7 @@ extern "C" int a2a_contract_pion_mom_dev(a2a_ctx* h, const a2a_geom* geom, const
   c->dfree(Om);
   c->dfree(ph);
   c->dfree(dc);
+  c->dfree(drows);
   return rc;
 }
 

@@ -15,10 +15,13 @@ namespace a2a {
 constexpr int CT = 64;   // output tile edge
 constexpr int KC = 16;   // complex elements per K step
 
-__global__ __launch_bounds__(256) void k_stoch_partial(int n, long V, int V3, int nchunk, int kchunk, int g5,
-                                                        int t_first, const double* __restrict__ eta,
+// rows (optional, [T][na]): row r of timeslice t is source rows[t na + r] (sources supported on
+// that timeslice only, e.g. after time dilution); without it na = n and row r is source r.
+__global__ __launch_bounds__(256) void k_stoch_partial(int n, int na, long V, int V3, int nchunk, int kchunk,
+                                                        int g5, int t_first, const double* __restrict__ eta,
                                                         const double* __restrict__ X,
-                                                        const double* __restrict__ phase, double* partial) {
+                                                        const double* __restrict__ phase,
+                                                        const int* __restrict__ rows, double* partial) {
   __shared__ double2 Es[CT][KC + 1];
   __shared__ double2 Xs[CT][KC + 1];
   const int chunk = blockIdx.x, tl = blockIdx.y, t = t_first + tl;
@@ -45,8 +48,9 @@ __global__ __launch_bounds__(256) void k_stoch_partial(int n, long V, int V3, in
       const long k = k0 + kk;
       double2 ev = make_double2(0.0, 0.0), xv = make_double2(0.0, 0.0);
       if (k < k_end) {
-        if (a0 + row < n) {
-          const double* p = eta + 2 * ((size_t)(a0 + row) * src_stride + tbase + k);
+        if (a0 + row < na) {
+          const int ar = rows ? rows[(size_t)t * na + a0 + row] : a0 + row;
+          const double* p = eta + 2 * ((size_t)ar * src_stride + tbase + k);
           ev = make_double2(p[0], p[1]);
           if (phase) {  // eta conj(f) with f = exp(-i p.y): the product below takes conj(eta) f
             const double fr = phase[2 * (k / 12)], fi = phase[2 * (k / 12) + 1];
@@ -80,22 +84,22 @@ __global__ __launch_bounds__(256) void k_stoch_partial(int n, long V, int V3, in
     }
     __syncthreads();
   }
-  double* out = partial + (((size_t)tl * nchunk + chunk) * n) * n * 2;
+  double* out = partial + (((size_t)tl * nchunk + chunk) * na) * n * 2;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int a = a0 + ty * 4 + i, b = b0 + tx * 4 + j;
-      if (a < n && b < n) {
+      if (a < na && b < n) {
         out[2 * ((size_t)a * n + b)] = accr[i][j];
         out[2 * ((size_t)a * n + b) + 1] = acci[i][j];
       }
     }
 }
 
-__global__ void k_stoch_sum(int n, int T, int nchunk, const double* partial, double* O) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;  // over T*n*n complex
-  const long per = (long)n * n;
+__global__ void k_stoch_sum(int n, int na, int T, int nchunk, const double* partial, double* O) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;  // over T*na*n complex
+  const long per = (long)na * n;
   if (i >= (long)T * per) return;
   const long t = i / per, ab = i % per;
   double sr = 0.0, si = 0.0;
@@ -109,19 +113,22 @@ __global__ void k_stoch_sum(int n, int T, int nchunk, const double* partial, dou
 }
 
 void launch_stoch_ops(const Geo& g, int n, const double* eta, const double* X, double* partial, int nchunk,
-                      double* O, hipStream_t s, int g5, int t_first, int nt, const double* phase) {
+                      double* O, hipStream_t s, int g5, int t_first, int nt, const double* phase, const int* rows,
+                      int na) {
   const int V3 = g.X * g.Y * g.Z;
   const long V = (long)V3 * g.T;
   const long K = 12L * V3;
   if (nt < 0) nt = g.T;
   long kchunk = (K + nchunk - 1) / nchunk;
   kchunk = ((kchunk + KC - 1) / KC) * KC;
-  const int ntb = (n + CT - 1) / CT;
-  dim3 grid(nchunk, nt, ntb * ntb);
-  hipLaunchKernelGGL(k_stoch_partial, grid, dim3(256), 0, s, n, V, V3, nchunk, (int)kchunk, g5, t_first, eta, X,
-                     phase, partial);
-  const long tot = (long)nt * n * n;
-  hipLaunchKernelGGL(k_stoch_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, nt, nchunk, partial, O);
+  if (!rows) na = n;
+  const int ntb = (n + CT - 1) / CT, nta = (na + CT - 1) / CT;
+  dim3 grid(nchunk, nt, nta * ntb);
+  hipLaunchKernelGGL(k_stoch_partial, grid, dim3(256), 0, s, n, na, V, V3, nchunk, (int)kchunk, g5, t_first, eta, X,
+                     phase, rows, partial);
+  const long tot = (long)nt * na * n;
+  hipLaunchKernelGGL(k_stoch_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, na, nt, nchunk, partial,
+                     O);
 }
 
 // Gram form of sum_{z,x} tr[S1 S2^dag]: corr[t] = (1/n^2) sum_ij E[i][j] F[t][j][i] with
@@ -175,6 +182,35 @@ __global__ __launch_bounds__(256) void k_pion_mom(int T, int N, int group, int m
 void launch_pion_mom(int T, int N, int group, int mode, const double* Op, const double* Om, double* corr,
                      hipStream_t s) {
   hipLaunchKernelGGL(k_pion_mom, dim3((unsigned)T), dim3(256), 0, s, T, N, group, mode, Op, Om, corr);
+}
+
+// The same for time-diluted sources, from the compact operators Op[t][r][b] of the na sources
+// rows[t][r] supported on timeslice t: a source a contributes to O(t) only at its own timeslice.
+__global__ __launch_bounds__(256) void k_pion_mom_rows(int T, int N, int na, const int* rows, int group, int mode,
+                                                       const double* Op, const double* Om, double* corr) {
+  const int dt = blockIdx.x;
+  const long per = (long)na * na;
+  double v[2] = {0.0, 0.0};
+  for (long e = threadIdx.x; e < (long)T * per; e += 256) {
+    const int t0 = (int)(e / per);
+    const int r1 = (int)((e % per) / na), r0 = (int)(e % na);
+    const int t1 = (t0 + dt) % T;
+    const int a = rows[(size_t)t1 * na + r1], b = rows[(size_t)t0 * na + r0];
+    if (mode == 0 && a / group == b / group) continue;
+    const double* x = Op + 2 * (((size_t)t1 * na + r1) * N + b);
+    const double* y = Om + 2 * (((size_t)t0 * na + r0) * N + a);
+    v[0] += x[0] * y[0] - x[1] * y[1];
+    v[1] += x[0] * y[1] + x[1] * y[0];
+  }
+  block_sum_n<2, 256>(v);
+  const double nv = (double)(N / group);
+  const double norm = mode == 0 ? 1.0 / ((double)T * nv * (nv - 1.0)) : 1.0;
+  if (threadIdx.x < 2) corr[2 * dt + threadIdx.x] = (threadIdx.x == 0 ? v[0] : v[1]) * norm;
+}
+
+void launch_pion_mom_rows(int T, int N, int na, const int* rows, int group, int mode, const double* Op,
+                          const double* Om, double* corr, hipStream_t s) {
+  hipLaunchKernelGGL(k_pion_mom_rows, dim3((unsigned)T), dim3(256), 0, s, T, N, na, rows, group, mode, Op, Om, corr);
 }
 
 // ------------------------------------------------------------------------------------

@@ -44,7 +44,7 @@ def test_dilution_bit_exact(ctx, orc, scheme):
     assert np.array_equal(host(out, 3 * D), orc.dilute(eta, scheme))
 
 
-@pytest.mark.parametrize("scheme", [0, 1, 3])
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
 def test_pion_mom_matches_oracle(ctx, orc, scheme):
     print(f"[gpu] momentum pion scheme={scheme}", flush=True)
     dims = (4, 2, 2, 4)
@@ -54,7 +54,7 @@ def test_pion_mom_matches_oracle(ctx, orc, scheme):
     X = rng.normal(size=eta.shape) + 1j * rng.normal(size=eta.shape)
     n = eta.shape[0]
     for mode in (0, 3):
-        got = ctx.contract_pion_mom_dev(dev(eta), dev(X), n, dims, MOMS, group=G, mode=mode)
+        got = ctx.contract_pion_mom_dev(dev(eta), dev(X), n, dims, MOMS, scheme=scheme, mode=mode)
         for m, p in enumerate(MOMS):
             want = orc.pion_mom(eta, X, p, group=G, mode=mode)
             err = np.max(np.abs(got[m] - want)) / np.max(np.abs(want))
@@ -91,7 +91,7 @@ def test_diluted_solve_and_momentum_correlator_end_to_end(ctx, orc):
     c = ctx.load_clover(g, csw)
     info, rc = ctx.solve_propagators_dev(c, src, sol, 3 * G, kappa, csw, tol=1e-12, prec=a2a.F16_F32)
     assert rc == 0
-    got = ctx.contract_pion_mom_dev(src, sol, 3 * G, dims, MOMS, group=G)
+    got = ctx.contract_pion_mom_dev(src, sol, 3 * G, dims, MOMS, scheme=a2a.DILUTE_T)
     eta_d = orc.dilute(noise, orc.DILUTE_T)
     Xo, io = orc.solve(U, A, kappa, eta_d, tbc, tol=1e-12)
     assert np.all(io[:, 2] == 1)
