@@ -614,14 +614,13 @@ int Solver::rebuild() {
         size_t k = (size_t)gi * R + r;
         gnon.push_back(k < rest.size() ? rest[k] : -1);
       }
-    // matrix-core stencil: tile-major, one lane tile per block
+    // matrix-core stencil: one block per (group, site block), the group's lane tiles inside
     for (int e = e0; e < e1; ++e)
-      for (int t = 0; t < ilg[e].nt; ++t)
-        for (int b = 0; b < ops[o].nblk; ++b) ilh.push_back(make_int2(e * (IL_LANES / 16) + t, b));
+      for (int b = 0; b < ops[o].nblk; ++b) ilh.push_back(make_int2(e, b));
     for (int b = 0; b < ops[o].nblk; ++b)
       for (int gi = 0; gi < ng; ++gi) hnon.push_back(make_int2(g0 + gi, b));
   }
-  xcd_order(hnon, ctx->xcd_order);  // the matrix-core tiles stay in tile-major order, unslabbed
+  xcd_order(hnon, ctx->xcd_order);  // the matrix-core blocks stay in brick order, unslabbed
   A2A_TRY(grow(ctx, (void**)&d_ilgroups, &cap_ilg, sizeof(ILGroupDev) * std::max<size_t>(1, ilg.size())));
   A2A_TRY(grow(ctx, (void**)&d_il_hop_tiles, &cap_ilh, sizeof(int2) * std::max<size_t>(1, ilh.size())));
   A2A_TRY(grow(ctx, (void**)&d_groups_nonil, &cap_gnonil, sizeof(int) * std::max<size_t>(1, gnon.size())));
