@@ -86,11 +86,13 @@ struct Conv<bf16_t> {
 };
 
 // precision modes: storage type S and arithmetic type A
-// SX is the storage of the inner solution vector x: FP16 lacks the range for an iterate that
-// grows like |M^-1| times the (unit-scaled) residual, so FP16 mode keeps x in FP32.
+// SX is the storage of the inner solution vector x, the storage format in every mode: x only
+// holds the correction since the last reliable update (which adds it to the FP64 solution and
+// zeroes it), of order |M^-1| times the unit-RMS residual, well inside the FP16 range; its
+// rounding (2^-11 relative) is far below the reliable-update trigger (0.03).
 struct PrecF64 { using S = double;   using SX = double; using A = double; static constexpr int id = 0; };
 struct PrecF32 { using S = float;    using SX = float;  using A = float;  static constexpr int id = 1; };
-struct PrecF16 { using S = _Float16; using SX = float;  using A = float;  static constexpr int id = 2; };
+struct PrecF16 { using S = _Float16; using SX = _Float16; using A = float; static constexpr int id = 2; };
 struct PrecB16 { using S = bf16_t;   using SX = bf16_t; using A = float;  static constexpr int id = 3; };
 
 // ------------------------------------------------------------------------------------
@@ -511,8 +513,7 @@ enum {
 };
 
 // low-precision (inner) vectors of a slot, all half-lattice sized
-// (VL_X spans two vector strides so that it can hold an FP32 x when S is FP16)
-enum { VL_R = 0, VL_RHAT, VL_P, VL_V, VL_S, VL_T, VL_TE, VL_X, NVEC_LO = VL_X + 2 };
+enum { VL_R = 0, VL_RHAT, VL_P, VL_V, VL_S, VL_T, VL_TE, VL_X, NVEC_LO };
 // FP64 vectors of a slot
 enum { VH_ETA_E = 0, VH_ETA_O, VH_BHAT, VH_X, VH_R, VH_TE, NVEC_HI };
 

@@ -97,8 +97,8 @@ int il_alloc(Ctx* c, Slot* slots, int n, long hv, int nlo) {
       s.lo_stride = vs;
       s.lss = 768LL * nt;
       s.lcs = 256;
-      s.lss_x = 2 * 768LL * nt;
-      s.lxoff = 768LL * tile;
+      s.lss_x = s.lss;  // the inner iterate in the storage format, laid out like the other vectors
+      s.lxoff = 0;
       s.il_base = (char*)p;
       s.il_nt = nt;
       s.il_lane = j;

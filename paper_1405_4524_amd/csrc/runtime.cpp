@@ -810,10 +810,10 @@ int Solver::vec(bool sub, int n_tiles, int kind, int par, int use_inv, int vin, 
   if (timed) {
     // compulsory bytes per site and RHS: s = r - alpha v reads 2 and writes 1 inner vector;
     // p = r + beta (p - omega v) reads 3, writes 1; the x / r update reads p, s, t, rhat and x
-    // and writes r and x (x is FP32 in FP16 mode); CGNR: x += alpha p, r -= alpha gamma5 q
+    // and writes r and x; CGNR: x += alpha p, r -= alpha gamma5 q
     // reads p, r, q and x and writes r and x; p = gamma5 u + beta p reads 2 and writes 1
     const double sz = prec == 0 ? 8.0 : prec == 1 ? 4.0 : 2.0;
-    const double szx = prec == 0 ? 8.0 : prec == 3 ? 2.0 : 4.0;
+    const double szx = sz;  // x is stored like the other inner vectors
     const double per = kind == VK_BICG_S   ? 3 * sz
                        : kind == VK_BICG_P ? 4 * sz
                        : kind == VK_CG_P   ? 3 * sz
