@@ -94,6 +94,12 @@ def main():
                     help="time-spin-colour dilution against undiluted noise at the same number of solves, "
                          "with momentum-projected pion correlators (8^3x16)")
     ap.add_argument("--dil-noise", type=int, default=4, help="noise vectors of the diluted set")
+    ap.add_argument("--noise-study", action="store_true",
+                    help="one noise set for both propagators against two independent sets (4^3x8), "
+                         "against the exact all-to-all from full dilution")
+    ap.add_argument("--noise-counts", default="16,64,256,1024")
+    ap.add_argument("--ensemble", type=int, default=0,
+                    help="pi-pi diagrams with vacuum subtraction over this many synthetic 8^3x16 configurations")
     ap.add_argument("--fill-sources", default="16,64,256,1024")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -114,6 +120,12 @@ def main():
         return
     if args.dilution:
         dilution_study(args)
+        return
+    if args.noise_study:
+        noise_study(args)
+        return
+    if args.ensemble:
+        ensemble_study(args)
         return
 
     w = inputs.WORKLOADS[args.workload]
@@ -441,6 +453,118 @@ def dilution_study(args):
         log(f"  dt {r['dt']}: diluted {r['C_diluted']:.4e} +- {r['err_diluted']:.1e}, undiluted "
             f"{r['C_undiluted']:.4e} +- {r['err_undiluted']:.1e}")
     ctx.unload(g)
+    print(json.dumps(out))
+
+
+def noise_study(args):
+    """The paper's comparison of one noise set for both propagators against two independent sets
+    (Sec. 7, Figs. rel1k / rel20k), on the synthetic 4^3x8 field (eps 0.2, kappa 0.120, c_sw 1.0):
+    Q(t) = sum_{z, x} tr[S(t, z; 0, x) S(t, z; 0, x)^dag], the all-to-all piece of diagram 0.
+    Exact: full dilution of timeslice 0 (12 L^3 unit sources, solved to 1e-10), for which the
+    raw sum is exact.  Stochastic: S1, S2 from N_r complex-Z2 noise vectors each; E1 uses S1 for
+    both propagators, E2 the independent S2 for the second.  Reported: relative error
+    |Q_est - Q| / Q averaged over t, for each N_r, on the GPU path end to end."""
+    import numpy as np
+    import torch
+
+    from paper_1405_4524_amd import a2a, inputs
+
+    w = inputs.WORKLOADS["tiny_4c8"]
+    dims, tbc, kappa, csw = w["dims"], w["tbc"], w["kappa"], w["csw"]
+    X, Y, Z, T = dims
+    ctx = a2a.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+    g = ctx.load_gauge(inputs.gauge_field(dims, w["eps"], w["gauge_seed"]), tbc)
+    c = ctx.load_clover(g, csw)
+    shape = (T, Z, Y, X, 4, 3, 2)
+
+    def solve(src):
+        sol = torch.zeros_like(src)
+        info, rc = ctx.solve_propagators_dev(c, src, sol, src.shape[0], kappa, csw, tol=1e-10, prec=a2a.F16_F32,
+                                             allow=())
+        return sol
+
+    M = 12 * X * Y * Z
+    unit = torch.zeros((M,) + shape, dtype=torch.float64, device="cuda")
+    unit.view(M, T, M, 2)[torch.arange(M), 0, torch.arange(M), 0] = 1.0  # e_k on timeslice 0
+    t0 = time.perf_counter()
+    Xu = solve(unit)
+    exact = M * M * ctx.contract_fill_2pt_dev(Xu, unit, Xu, unit, M, dims, 0, method="gram").real
+    t_exact = time.perf_counter() - t0
+    rows = []
+    seed = 300
+    for nr in [int(x) for x in args.noise_counts.split(",")]:
+        e1 = torch.empty((nr,) + shape, dtype=torch.float64, device="cuda")
+        e2 = torch.empty_like(e1)
+        ctx.z2_noise_dev(dims, seed, 0, nr, e1)
+        ctx.z2_noise_dev(dims, seed + 1, 0, nr, e2)
+        seed += 2
+        X1, X2 = solve(e1), solve(e2)
+        q1 = ctx.contract_fill_2pt_dev(X1, e1, X1, e1, nr, dims, 0, method="gram").real
+        q2 = ctx.contract_fill_2pt_dev(X1, e1, X2, e2, nr, dims, 0, method="gram").real
+        r1 = float(np.mean(np.abs(q1 - exact) / np.abs(exact)))
+        r2 = float(np.mean(np.abs(q2 - exact) / np.abs(exact)))
+        rows.append({"N_r": nr, "rel_err_one_set": round(r1, 4), "rel_err_two_sets": round(r2, 4),
+                     "ratio": round(r1 / r2, 2)})
+        log(f"noise study N_r={nr}: one set {r1:.4f}, two sets {r2:.4f}")
+        del e1, e2, X1, X2
+    out = {"mode": "noise_study", "dims": list(dims), "kappa": kappa, "c_sw": csw,
+           "quantity": "sum_{z,x} tr[S(t,z;0,x) S(t,z;0,x)^dag], mean over t of the relative error",
+           "exact_solves": M, "exact_s": round(t_exact, 3), "exact_Q": [round(float(v), 6) for v in exact],
+           "rows": rows}
+    ctx.unload(g)
+    print(json.dumps(out))
+
+
+def ensemble_study(args):
+    """Zero-momentum pi-pi correlator over an ensemble of synthetic configurations (8^3x16,
+    eps 0.3, kappa 0.125, c_sw 1.2, seeds 1000 + k): per configuration 64 complex-Z2 sources in
+    four independent groups are solved (FP16 inner, tol 1e-10) and contracted into diagrams
+    D0..D3, the timeslice loop L(t, t) and the pion; the vacuum part of diagram 1 is subtracted
+    with the ensemble average of the loop: C(dt) = <D0 + D1 - D2 - D3> - <L>^2 (Secs. 5 and 8).
+    Jackknife errors over configurations.  The fields are not a thermalised ensemble: this
+    exercises the machinery, it is not a physics result."""
+    import numpy as np
+    import torch
+
+    from paper_1405_4524_amd import a2a, inputs
+
+    dims, kappa, csw, tbc, eps, nsrc = (8, 8, 8, 16), 0.125, 1.2, -1, 0.3, 64
+    X, Y, Z, T = dims
+    ctx = a2a.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+    src = torch.empty((nsrc, T, Z, Y, X, 4, 3, 2), dtype=torch.float64, device="cuda")
+    sol = torch.zeros_like(src)
+    D, V, Pn = [], [], []
+    t0 = time.perf_counter()
+    for k in range(args.ensemble):
+        g = ctx.load_gauge(inputs.gauge_field(dims, eps, 1000 + k), tbc)
+        c = ctx.load_clover(g, csw)
+        ctx.z2_noise_dev(dims, 2000 + k, 0, nsrc, src)
+        sol.zero_()
+        info, rc = ctx.solve_propagators_dev(c, src, sol, nsrc, kappa, csw, tol=1e-10, prec=a2a.F16_F32, allow=())
+        d, v, pc = ctx.contract_pipi_2pt_dev(src, sol, nsrc, dims, tbc, want_pion=True)
+        D.append(d.real)
+        V.append(v.real)
+        Pn.append(pc.real)
+        ctx.unload(g)
+    el = time.perf_counter() - t0
+    D, V, Pn = np.array(D), np.array(V), np.array(Pn)
+    n = len(D)
+
+    def est(idx):
+        d = D[idx].mean(axis=0)
+        vac = V[idx].mean()
+        return d[0] + d[1] - d[2] - d[3] - vac * vac, d[1] - vac * vac, Pn[idx].mean(axis=0)
+
+    full = est(np.arange(n))
+    loo = [est(np.array([j for j in range(n) if j != k])) for k in range(n)]
+    errs = [np.sqrt((n - 1) / n * np.sum([(l[q] - np.mean([m[q] for m in loo], axis=0)) ** 2 for l in loo],
+                                         axis=0)) for q in range(3)]
+    rows = [{"dt": dt, "pipi": float(f"{full[0][dt]:.6e}"), "pipi_err": float(f"{errs[0][dt]:.2e}"),
+             "D1_subtracted": float(f"{full[1][dt]:.4e}"), "pion": float(f"{full[2][dt]:.6e}"),
+             "pion_err": float(f"{errs[2][dt]:.2e}")} for dt in range(T // 2 + 1)]
+    out = {"mode": "ensemble", "configurations": n, "dims": list(dims), "sources_per_config": nsrc,
+           "seconds": round(el, 2), "loop_mean": float(V.mean()), "rows": rows}
+    log(f"ensemble of {n}: {el:.1f}s; <L> = {V.mean():.4e}")
     print(json.dumps(out))
 
 

@@ -80,3 +80,32 @@ def test_fill_errors(ctx):
     with pytest.raises(a2a.A2AError) as e:
         ctx.fill_propagator_dev(dev(X), dev(eta), 0, dims, 0, 0, S)
     assert e.value.code == a2a.EINVAL
+
+
+def test_full_dilution_fill_is_exact(ctx, orc):
+    """Unit sources on the source timeslice, solved on the GPU: M^2 sum tr[S S^dag] through both
+    routes equals the squared Frobenius norm of the dense inverse's block (LAPACK), per t."""
+    import torch
+
+    from paper_1405_4524_amd import a2a, inputs
+    from tests.test_oracle_pins import dense_operator
+
+    print("[gpu] full dilution fill", flush=True)
+    dims, tbc, kappa, csw = (2, 2, 2, 4), -1, 0.125, 1.3
+    X_, Y, Z, T = dims
+    M = 12 * X_ * Y * Z
+    U = inputs.gauge_field(dims, 0.4, seed=71)
+    A = orc.clover(U, kappa, csw)
+    Dinv = np.linalg.inv(dense_operator(lambda v: orc.apply_D(U, A, kappa, v, tbc), dims))
+    want = np.array([np.sum(np.abs(Dinv[t * M:(t + 1) * M, 0:M]) ** 2) for t in range(T)])
+    unit = torch.zeros((M, T, Z, Y, X_, 4, 3, 2), dtype=torch.float64, device="cuda")
+    unit.view(M, T, M, 2)[torch.arange(M), 0, torch.arange(M), 0] = 1.0
+    sol = torch.zeros_like(unit)
+    g = ctx.load_gauge(U, tbc)
+    c = ctx.load_clover(g, csw)
+    info, rc = ctx.solve_propagators_dev(c, unit, sol, M, kappa, csw, tol=1e-12, prec=a2a.F64)
+    assert rc == 0
+    for method in ("fill", "gram"):
+        got = M * M * ctx.contract_fill_2pt_dev(sol, unit, sol, unit, M, dims, 0, method=method)
+        assert np.max(np.abs(got - want)) < 1e-9 * np.max(want), method
+    ctx.unload(g)
