@@ -34,9 +34,9 @@ STORAGE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
 # copy (fetch x2.0, write x1.0). Valid only for the kernel sources they were taken on (hash of the
 # stencil's sources) and for the same workload, precision, RHS block and kernel class.
 TRAFFIC = {
-    ("schur2", "l32t64", "f16", "rb2"): {"src": "5f8469b6a4acbdb8", "bytes": 1.3466e10,
+    ("schur2", "l32t64", "f16", "rb2"): {"src": "af099bd1d74b6542", "bytes": 1.3509e10,
                                          "profile": "profiles/bench_l32t64_f16_rb2_hbm_counters.txt"},
-    ("schur2", "l32t64", "f16", "il"): {"src": "156cdddb787c990a", "bytes": 1.4127e10,
+    ("schur2", "l32t64", "f16", "il"): {"src": "7d8be83dceca86ae", "bytes": 1.6092e10,
                                         "profile": "profiles/bench_l32t64_f16_interleaved_hbm_counters.txt"},
 }
 STENCIL_SOURCES = {"per-thread": ("hop.hip", "a2a_device.h", "a2a_reduce.h", "a2a_kernels.h"),
