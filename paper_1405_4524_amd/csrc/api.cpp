@@ -460,6 +460,9 @@ extern "C" int a2a_set_option(a2a_ctx* h, const char* key, double v) {
   } else if (k == "delta_bf16") {
     if (!(v > 0 && v < 1)) return c->fail(A2A_EINVAL, "delta_bf16 must be in (0, 1)");
     c->delta_bf16 = v;
+  } else if (k == "delta_cgnr") {
+    if (!(v > 0 && v < 1)) return c->fail(A2A_EINVAL, "delta_cgnr must be in (0, 1)");
+    c->delta_cgnr = v;
   } else if (k == "delta64") {
     if (!(v > 0 && v < 1)) return c->fail(A2A_EINVAL, "delta64 must be in (0, 1)");
     c->delta_64 = v;

@@ -988,7 +988,12 @@ int Solver::finalize(const std::vector<int>& idx) {
 int Solver::check() {
   A2A_TRY(ctx->read_scal());
   std::vector<int> ru, restart;
-  const double delta = prec == 0 ? ctx->delta_64 : prec == 3 ? ctx->delta_bf16 : ctx->delta_lo;
+  // CGNR with FP16 storage: its iterate accumulates about three times as many FP16-rounded
+  // updates between reliable updates as BiCGStab's, so it is flushed at 0.1 like BF16
+  const double delta = prec == 0                                 ? ctx->delta_64
+                       : prec == 3                                 ? ctx->delta_bf16
+                       : (prec == 2 && method == SOLVER_CGNR)      ? ctx->delta_cgnr
+                                                                   : ctx->delta_lo;
   for (int i = 0; i < (int)live.size(); ++i) {
     Slot* s = live[i];
     if (s->state != SS_RUN) continue;
