@@ -409,3 +409,65 @@ def pion_mom(eta, X, p, group=1, mode=MODE_UNBIASED):
         n = N // group
         C /= T * n * (n - 1)
     return C
+
+
+# ---------------------------------------------------------------------------------------
+# point-source propagators and the pi-pi diagrams that combine them with stochastic ones
+# (Sec. 8: diagram 2 from point propagators at the origin and stochastic propagators sourced
+# at (t, z); diagram 1 from a stochastic timeslice loop and a point loop at the source)
+# ---------------------------------------------------------------------------------------
+def point_sources(dims, t0, x0):
+    """The 12 unit sources at the site (t0, x0), x0 = (x, y, z): source k is 1 in spin-colour
+    component k = 3 spin + colour there and 0 everywhere else."""
+    X, Y, Z, T = dims
+    e = np.zeros((12, T, Z, Y, X, 4, 3), np.complex128)
+    for k in range(12):
+        e[k, t0, x0[2], x0[1], x0[0], k // 3, k % 3] = 1.0
+    return e
+
+
+def _point_blocks(Sp, t):
+    """S_p(t, y) for every spatial site y of timeslice t as [y][a][k]: a = sink spin-colour,
+    k = source spin-colour (the solution of point source k)."""
+    return np.moveaxis(Sp[:, t].reshape(12, -1, 12), 0, 2)
+
+
+def pipi_mixed(Sp, t0, eta1, X1, eta2, X2):
+    """The pi-pi diagrams with point propagators S_p(w) = S(w; t0, x0) (Sp = the solutions of
+    the 12 point sources at (t0, x0)) and stochastic all-to-all propagators S1, S2 filled from
+    two noise sets (eq. Sfill, normalised by 1/N1 and 1/N2), on one configuration, for every
+    separation dt with t = t0 + dt (mod T):
+
+      Cp(dt) = sum_y tr[S_p(t, y) S_p(t, y)^dag]                       point pion
+      Cs(dt) = sum_{z, x} tr[S1(t, z; t0, x) S2(t, z; t0, x)^dag]      all-to-all pion
+      L(dt)  = sum_{z, y} tr[S1(t, z; t, y) S2(t, z; t, y)^dag]        timeslice loop at t
+      D0 = Cp Cs,  D1 = L Cp(0)                                        (Sec. 7 and Sec. 8)
+      D2(dt) = sum_{x, y, z} tr[S_p(t0, x)^dag S1(t0, x; t, z) S2(t, y; t, z)^dag S_p(t, y)]
+      D3 = conj(D2)
+
+    (daggers on spin and colour only).  D0 and D1 are unsubtracted; their vacuum parts need
+    ensemble averages of the pieces.  Returns (diagrams[4, T], pieces[3, T] = Cp, Cs, L)."""
+    Sp = _c(Sp)
+    T = Sp.shape[1]
+    m = Sp[0, 0].size // 12  # spatial sites per timeslice
+    P0 = _point_blocks(Sp, t0)
+    cp0 = np.sum(np.abs(P0) ** 2)
+    diagrams = np.zeros((4, T), np.complex128)
+    pieces = np.zeros((3, T), np.complex128)
+    for dt in range(T):
+        t = (t0 + dt) % T
+        Pt = _point_blocks(Sp, t)
+        cp = np.sum(np.abs(Pt) ** 2)
+        # tr[A B^dag] summed over both site indices is sum A conj(B) over all entries
+        cs = np.sum(fill_propagator(eta1, X1, t0, t) * np.conj(fill_propagator(eta2, X2, t0, t)))
+        S1tt = fill_propagator(eta1, X1, t, t)
+        S2tt = fill_propagator(eta2, X2, t, t)
+        loop = np.sum(S1tt * np.conj(S2tt))
+        S1 = fill_propagator(eta1, X1, t, t0).reshape(m, 12, m, 12)  # S1(t0, x; t, z): [x][a][z][b]
+        S2 = S2tt.reshape(m, 12, m, 12)                                # S2(t, y; t, z): [y][c][z][d]
+        # tr[S_p(t0,x)^dag S1(t0,x;t,z) S2(t,y;t,z)^dag S_p(t,y)]: the (b, c) entry of the block
+        # S2(t,y;t,z)^dag is conj(S2[y][c][z][b])
+        d2 = np.einsum("xak,xazb,yczb,yck->", np.conj(P0), S1, np.conj(S2), Pt, optimize=True)
+        diagrams[:, dt] = (cp * cs, loop * cp0, d2, np.conj(d2))
+        pieces[:, dt] = (cp, cs, loop)
+    return diagrams, pieces
