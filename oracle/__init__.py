@@ -15,7 +15,9 @@ a hand-computed clover, dense LU solves, the exact correlator from unit sources,
 free-field correlator closed form, estimator statistics; the outer-product fill by the dense
 inverse under full dilution, a hand-built dagger block and the Gram-matrix form of its
 contraction; dilution by its partition of the noise, momentum-projected operators by the C
-oracle at zero momentum and by dense-inverse traces with phases under full dilution).
+oracle at zero momentum and by dense-inverse traces with phases under full dilution; the
+point-source pi-pi diagrams by closed gamma_5 loops of the dense inverse and by their
+factorised Gram form).
 """
 from __future__ import annotations
 
