@@ -246,6 +246,31 @@ int a2a_contract_pion_mom_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *
                               const double *solutions_dev, int nrhs, int scheme, int nmom, const int *moms,
                               int mode, double *corr_host);
 
+/* ---- point-source propagators and the pi-pi diagrams that use them (Sec. 8) ------------ */
+/* out (device, canonical, 12 sources) = the unit sources at the site (t0, x0[0..2] = x, y, z):
+ * source k = 3 spin + colour is 1 in component k there and 0 elsewhere.  Solving them gives
+ * the point propagator S_p(w) = S(w; t0, x0), column k = solution k.  A2A_EINVAL if the point
+ * is outside the lattice. */
+int a2a_point_sources_dev(a2a_ctx *ctx, const a2a_geom *geom, int t0, const int *x0, double *out_dev);
+/* The pi-pi diagrams of Sec. 8 from point propagators (point_sol: the 12 solutions of
+ * a2a_point_sources_dev at timeslice t0) and stochastic all-to-all propagators
+ * S1 = (1/n1) sum_i X1_i eta1_i^dag and S2 = (1/n2) sum_j X2_j eta2_j^dag (eq. Sfill) of two
+ * noise sets (pass the same set twice for the paper's one-set variant), for t = t0 + dt:
+ *   pieces[0][dt] = Cp = sum_y tr[S_p(t, y) S_p(t, y)^dag]                    point pion
+ *   pieces[1][dt] = Cs = sum_{z, x} tr[S1(t, z; t0, x) S2(t, z; t0, x)^dag]   all-to-all pion
+ *   pieces[2][dt] = L  = sum_{z, y} tr[S1(t, z; t, y) S2(t, z; t, y)^dag]     loop at t
+ *   diagrams[0][dt] = Cp Cs,  diagrams[1][dt] = L Cp(0)  (both unsubtracted)
+ *   diagrams[2][dt] = sum_{x, y, z} tr[S_p(t0, x)^dag S1(t0, x; t, z) S2(t, y; t, z)^dag S_p(t, y)]
+ *   diagrams[3][dt] = conj(diagrams[2][dt])
+ * (daggers on spin and colour only; total D0 + D1 - D2 - D3 after the ensemble subtractions).
+ * Evaluated from timeslice Gram matrices of the inputs (FP64, no propagator is stored; work
+ * ~ 8 T 12 X Y Z (n1 n2 + 12 (n1 + n2)) flop).  All arrays are canonical device spinors;
+ * diagrams (complex [4][T]) and pieces (complex [3][T], or NULL) are host arrays.  Temporary
+ * device memory ~ 16 T n1 n2 x (2 + a chunk factor) bytes. */
+int a2a_contract_pipi_mixed_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *point_sol_dev, int t0,
+                                const double *src1_dev, const double *sol1_dev, int n1, const double *src2_dev,
+                                const double *sol2_dev, int n2, double *diagrams_host, double *pieces_host);
+
 /* ---- synthetic inputs ---------------------------------------------------------------- */
 /* Complex-Z2 noise (Sec. 7 "Z2 noise", here (+-1 +- i)/sqrt 2) written to a canonical
  * device array of nsrc sources: component k of the flattened array (global source index

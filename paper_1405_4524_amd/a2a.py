@@ -77,6 +77,8 @@ _SIG = {
     "a2a_contract_pion_mom_dev": (I, [P, ctypes.POINTER(Geom), P, P, I, I, I, P, I, P]),
     "a2a_contract_fill_2pt_dev": (I, [P, ctypes.POINTER(Geom), P, P, P, P, I, I, P]),
     "a2a_contract_gram_2pt_dev": (I, [P, ctypes.POINTER(Geom), P, P, P, P, I, I, P]),
+    "a2a_point_sources_dev": (I, [P, ctypes.POINTER(Geom), I, P, P]),
+    "a2a_contract_pipi_mixed_dev": (I, [P, ctypes.POINTER(Geom), P, I, P, P, I, P, P, I, P, P]),
     "a2a_engine_create": (I, [P, ctypes.c_char_p, ctypes.POINTER(P)]),
     "a2a_engine_submit": (I, [P, I, D, P, I, D, I, I, P, ctypes.POINTER(LL)]),
     "a2a_engine_step": (I, [P, I, ctypes.POINTER(I)]),
@@ -374,6 +376,24 @@ class Context:
                                                   int(scheme), m.shape[0], m.ctypes.data_as(P), int(mode),
                                                   corr.ctypes.data_as(P)))
         return corr
+
+    # ---- point-source propagators and the pi-pi diagrams that use them
+    def point_sources_dev(self, dims, t0, x0, out_t, t_bc=-1):
+        g = geom(dims, t_bc)
+        x = (ctypes.c_int * 3)(*[int(v) for v in x0])
+        self._chk(lib().a2a_point_sources_dev(self._c, ctypes.byref(g), int(t0), x, _tptr(out_t)))
+
+    def contract_pipi_mixed_dev(self, point_sol_t, t0, src1_t, sol1_t, n1, src2_t, sol2_t, n2, dims, t_bc=-1):
+        """(diagrams[4, T] = D0..D3, pieces[3, T] = point pion, all-to-all pion, loop)."""
+        g = geom(dims, t_bc)
+        T = dims[3]
+        d = np.empty((4, T), np.complex128)
+        pc = np.empty((3, T), np.complex128)
+        self._chk(lib().a2a_contract_pipi_mixed_dev(self._c, ctypes.byref(g), _tptr(point_sol_t), int(t0),
+                                                    _tptr(src1_t), _tptr(sol1_t), int(n1), _tptr(src2_t),
+                                                    _tptr(sol2_t), int(n2), d.ctypes.data_as(P),
+                                                    pc.ctypes.data_as(P)))
+        return d, pc
 
     # ---- engine / instrumentation
     def engine_create(self, policy_json=""):

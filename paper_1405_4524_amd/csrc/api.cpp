@@ -1099,6 +1099,86 @@ extern "C" int a2a_contract_gram_2pt_dev(a2a_ctx* h, const a2a_geom* geom, const
 }
 
 // =========================================================================================
+// point-source propagators and the pi-pi diagrams that combine them with stochastic
+// propagators (Sec. 8)
+// =========================================================================================
+extern "C" int a2a_point_sources_dev(a2a_ctx* h, const a2a_geom* geom, int t0, const int* x0, double* out) {
+  if (!h || !x0 || !out) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  Geo g;
+  if (geom_to_geo(geom, &g)) return c->fail(A2A_EINVAL, "bad lattice geometry");
+  if (t0 < 0 || t0 >= g.T || x0[0] < 0 || x0[0] >= g.X || x0[1] < 0 || x0[1] >= g.Y || x0[2] < 0 || x0[2] >= g.Z)
+    return c->fail(A2A_EINVAL, "point outside the lattice");
+  const long site = (((long)t0 * g.Z + x0[2]) * g.Y + x0[1]) * g.X + x0[0];
+  launch_point_sources(g, site, out, c->stream);
+  A2A_HIP(c, hipGetLastError());
+  return c->sync();
+}
+
+extern "C" int a2a_contract_pipi_mixed_dev(a2a_ctx* h, const a2a_geom* geom, const double* point_sol, int t0,
+                                           const double* src1, const double* sol1, int n1, const double* src2,
+                                           const double* sol2, int n2, double* diagrams, double* pieces) {
+  if (!h || !point_sol || !src1 || !sol1 || !src2 || !sol2 || !diagrams) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  Geo g;
+  if (geom_to_geo(geom, &g)) return c->fail(A2A_EINVAL, "bad lattice geometry");
+  if (n1 < 1 || n2 < 1) return c->fail(A2A_EINVAL, "n1 and n2 must be positive");
+  if (t0 < 0 || t0 >= g.T) return c->fail(A2A_EINVAL, "source timeslice out of range");
+  const int T = g.T;
+  const long K = 12L * g.X * g.Y * g.Z;
+  // the timeslice Gram matrices <a_r, b_s>_t (no gamma_5): rows from `a`, columns from `b`
+  struct Gram {
+    const double* a;
+    int na;
+    const double* b;
+    int nb, t_first, nt, nchunk;
+    size_t elems;  // complex outputs
+  };
+  Gram gm[5] = {{point_sol, 12, point_sol, 12, 0, T, 0, 0},  // Pn[t][k][l] = <Sp_k, Sp_l>_t
+                {src1, n1, src2, n2, 0, T, 0, 0},             // G[t][i][j] = <eta1_i, eta2_j>_t
+                {sol1, n1, sol2, n2, 0, T, 0, 0},             // Fp[t][i][j] = <X1_i, X2_j>_t
+                {point_sol, 12, sol1, n1, t0, 1, 0, 0},       // A[k][i] = <Sp_k, X1_i>_t0
+                {sol2, n2, point_sol, 12, 0, T, 0, 0}};       // B[t][j][k] = <X2_j, Sp_k>_t
+  size_t part_elems = 0;
+  for (Gram& q : gm) {
+    const long tiles = (long)q.nt * ((q.na + 63) / 64) * ((q.nb + 63) / 64);
+    q.nchunk = (int)std::max(1L, std::min(4096 / std::max(1L, tiles), (K + 255) / 256));
+    q.elems = (size_t)q.nt * q.na * q.nb;
+    part_elems = std::max(part_elems, q.elems * q.nchunk);
+  }
+  const int nmix = pipi_mixed_chunks(n1);
+  void* part = nullptr;
+  void* out[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  void *mix = nullptr, *dd = nullptr;
+  A2A_TRY(c->dalloc(&part, sizeof(double) * 2 * part_elems));
+  int rc = A2A_OK;
+  for (int q = 0; q < 5 && !rc; ++q) rc = c->dalloc(&out[q], sizeof(double) * 2 * gm[q].elems);
+  if (!rc) rc = c->dalloc(&mix, sizeof(double) * 6 * (size_t)T * nmix);
+  if (!rc) rc = c->dalloc(&dd, sizeof(double) * 2 * 7 * (size_t)T);  // diagrams [4][T], pieces [3][T]
+  if (!rc) {
+    // one partial buffer: every Gram launch pair finishes before the next starts (one stream)
+    for (int q = 0; q < 5; ++q)
+      launch_stoch_ops(g, gm[q].nb, gm[q].a, gm[q].b, (double*)part, gm[q].nchunk, (double*)out[q], c->stream, 0,
+                       gm[q].t_first, gm[q].nt, nullptr, nullptr, gm[q].na);
+    double* d = (double*)dd;
+    launch_pipi_mixed(T, t0, n1, n2, (const double*)out[0], (const double*)out[1], (const double*)out[2],
+                      (const double*)out[3], (const double*)out[4], (double*)mix, d, d + 8 * T, c->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) rc = c->fail(A2A_EDEVICE, std::string("mixed pi-pi contraction: ") + hipGetErrorString(e));
+    if (!rc) rc = copy_to_host(c, diagrams, d, sizeof(double) * 8 * T);
+    if (!rc && pieces) rc = copy_to_host(c, pieces, d + 8 * T, sizeof(double) * 6 * T);
+  }
+  c->sync();
+  c->dfree(part);
+  for (void* p : out) c->dfree(p);
+  c->dfree(mix);
+  c->dfree(dd);
+  return rc;
+}
+
+// =========================================================================================
 // dilution and momentum projection (Sec. 7: time-spin-colour dilution; Sec. 5: pions projected
 // onto momentum states)
 // =========================================================================================

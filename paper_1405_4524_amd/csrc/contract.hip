@@ -121,7 +121,7 @@ void launch_stoch_ops(const Geo& g, int n, const double* eta, const double* X, d
   if (nt < 0) nt = g.T;
   long kchunk = (K + nchunk - 1) / nchunk;
   kchunk = ((kchunk + KC - 1) / KC) * KC;
-  if (!rows) na = n;
+  if (na <= 0) na = n;  // rows == null: eta rows 0 .. na - 1
   const int ntb = (n + CT - 1) / CT, nta = (na + CT - 1) / CT;
   dim3 grid(nchunk, nt, nta * ntb);
   hipLaunchKernelGGL(k_stoch_partial, grid, dim3(256), 0, s, n, na, V, V3, nchunk, (int)kchunk, g5, t_first, eta, X,
@@ -152,6 +152,108 @@ __global__ __launch_bounds__(256) void k_gram_corr(int n, const double* E, const
 
 void launch_gram_corr(int T, int n, const double* E, const double* F, double* corr, hipStream_t s) {
   hipLaunchKernelGGL(k_gram_corr, dim3((unsigned)T), dim3(256), 0, s, n, E, F, corr);
+}
+
+// pi-pi diagrams from point propagators S_p (the 12 solutions of the point sources at
+// (t0, x0)) and stochastic propagators of two noise sets (Sec. 8), in factorised form, from the
+// timeslice Gram matrices
+//   G[t][i][j] = <eta1_i, eta2_j>_t   Fp[t][i][j] = <X1_i, X2_j>_t   Pn[t][k][l] = <Sp_k, Sp_l>_t
+//   A[k][i] = <Sp_k, X1_i>_t0          B[t][j][k] = <X2_j, Sp_k>_t
+// with, for t = t0 + dt:
+//   Cs(dt) = sum_ij G[t0]_ij conj(Fp[t]_ij) / (n1 n2)       L(dt) = sum_ij G[t]_ij conj(Fp[t]_ij) / (n1 n2)
+//   D2(dt) = sum_ij G[t]_ij sum_k B[t]_jk A_ki / (n1 n2)    Cp(dt) = sum_k Pn[t]_kk
+// The partial kernel sums a chunk of rows i per block (grid: chunks x T); the final kernel sums
+// the chunks in order and forms D0 = Cp Cs, D1 = L Cp(0), D2, D3 = conj(D2).
+__global__ __launch_bounds__(256) void k_pipi_mixed_partial(int T, int t0, int n1, int n2, int rows,
+                                                            const double* G, const double* Fp, const double* A,
+                                                            const double* B, double* partial) {
+  const int c = blockIdx.x, dt = blockIdx.y, t = (t0 + dt) % T;
+  const int i0 = c * rows, i1 = min(n1, i0 + rows);
+  const size_t per = (size_t)n1 * n2;
+  const double* G0 = G + 2 * (size_t)t0 * per;
+  const double* Gt = G + 2 * (size_t)t * per;
+  const double* Ft = Fp + 2 * (size_t)t * per;
+  const double* Bt = B + 2 * (size_t)t * n2 * 12;
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // Cs, L, D2 (re, im)
+  const long cnt = (long)(i1 - i0) * n2;
+  for (long e = threadIdx.x; e < cnt; e += 256) {
+    const int i = i0 + (int)(e / n2), j = (int)(e % n2);
+    const size_t ij = 2 * ((size_t)i * n2 + j);
+    const double fr = Ft[ij], fi = -Ft[ij + 1];  // F_ji = conj(Fp_ij)
+    const double g0r = G0[ij], g0i = G0[ij + 1], gr = Gt[ij], gi = Gt[ij + 1];
+    v[0] += g0r * fr - g0i * fi;
+    v[1] += g0r * fi + g0i * fr;
+    v[2] += gr * fr - gi * fi;
+    v[3] += gr * fi + gi * fr;
+    double br = 0.0, bi = 0.0;  // (B A)_ji
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const double* b = Bt + 2 * ((size_t)j * 12 + k);
+      const double* a = A + 2 * ((size_t)k * n1 + i);
+      br += b[0] * a[0] - b[1] * a[1];
+      bi += b[0] * a[1] + b[1] * a[0];
+    }
+    v[4] += gr * br - gi * bi;
+    v[5] += gr * bi + gi * br;
+  }
+  block_sum_n<6, 256>(v);
+  if (threadIdx.x < 6) {
+    double r = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      if (q == (int)threadIdx.x) r = v[q];
+    partial[((size_t)dt * gridDim.x + c) * 6 + threadIdx.x] = r;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_pipi_mixed_final(int T, int t0, int nchunk, double norm, const double* Pn,
+                                                         const double* partial, double* diag, double* pieces) {
+  const int dt = blockIdx.x, t = (t0 + dt) % T;
+  double v[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    double s = 0.0;
+    for (int c = threadIdx.x; c < nchunk; c += 64) s += partial[((size_t)dt * nchunk + c) * 6 + q];
+    v[q] = wave_sum(s) * norm;
+  }
+  if (threadIdx.x != 0) return;
+  double cpr = 0.0, cpi = 0.0, c0r = 0.0, c0i = 0.0;  // traces of the point Gram matrices at t, t0
+  for (int k = 0; k < 12; ++k) {
+    cpr += Pn[2 * (((size_t)t * 12 + k) * 12 + k)];
+    cpi += Pn[2 * (((size_t)t * 12 + k) * 12 + k) + 1];
+    c0r += Pn[2 * (((size_t)t0 * 12 + k) * 12 + k)];
+    c0i += Pn[2 * (((size_t)t0 * 12 + k) * 12 + k) + 1];
+  }
+  double* d = diag + 2 * dt;
+  d[0] = cpr * v[0] - cpi * v[1];  // D0 = Cp Cs
+  d[1] = cpr * v[1] + cpi * v[0];
+  d[2 * T] = v[2] * c0r - v[3] * c0i;  // D1 = L Cp(0)
+  d[2 * T + 1] = v[2] * c0i + v[3] * c0r;
+  d[4 * T] = v[4];  // D2
+  d[4 * T + 1] = v[5];
+  d[6 * T] = v[4];  // D3 = conj(D2)
+  d[6 * T + 1] = -v[5];
+  if (pieces) {
+    double* p = pieces + 2 * dt;
+    p[0] = cpr;
+    p[1] = cpi;
+    p[2 * T] = v[0];
+    p[2 * T + 1] = v[1];
+    p[4 * T] = v[2];
+    p[4 * T + 1] = v[3];
+  }
+}
+
+int pipi_mixed_chunks(int n1) { return std::max(1, std::min(n1, 64)); }
+
+void launch_pipi_mixed(int T, int t0, int n1, int n2, const double* Pn, const double* G, const double* Fp,
+                       const double* A, const double* B, double* partial, double* diag, double* pieces,
+                       hipStream_t s) {
+  const int nchunk = pipi_mixed_chunks(n1), rows = (n1 + nchunk - 1) / nchunk;
+  hipLaunchKernelGGL(k_pipi_mixed_partial, dim3((unsigned)nchunk, (unsigned)T), dim3(256), 0, s, T, t0, n1, n2, rows,
+                     G, Fp, A, B, partial);
+  hipLaunchKernelGGL(k_pipi_mixed_final, dim3((unsigned)T), dim3(64), 0, s, T, t0, nchunk,
+                     1.0 / ((double)n1 * (double)n2), Pn, partial, diag, pieces);
 }
 
 // Momentum-projected pion from O(t, p) and O(t, -p): corr[dt] = sum_t0 sum_{a, b}

@@ -439,4 +439,19 @@ void launch_dilute(const Geo& g, int nnoise, int scheme, int D, const double* no
                      noise, out);
 }
 
+// Point sources (Sec. 8: propagators from a point at the origin): the 12 unit vectors at one
+// site, source k = 3 spin + colour; one thread per complex output element.
+__global__ __launch_bounds__(BS) void k_point_sources(long per, long site, double* out) {
+  const long e = (long)blockIdx.x * BS + threadIdx.x;
+  if (e >= 12 * per) return;
+  const long k = e / per, r = e % per;  // source k, complex element r = 12 site + spin-colour
+  out[2 * e] = r == 12 * site + k ? 1.0 : 0.0;
+  out[2 * e + 1] = 0.0;
+}
+
+void launch_point_sources(const Geo& g, long site, double* out, hipStream_t s) {
+  const long per = 12L * g.X * g.Y * g.Z * g.T;
+  hipLaunchKernelGGL(k_point_sources, dim3((unsigned)((12 * per + BS - 1) / BS)), dim3(BS), 0, s, per, site, out);
+}
+
 }  // namespace a2a

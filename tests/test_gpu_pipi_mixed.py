@@ -1,0 +1,176 @@
+"""GPU parity of the point sources and of the pi-pi diagrams from point and stochastic
+propagators (Sec. 8) against the oracle:
+
+  point sources   bitwise equal to the oracle's unit vectors;
+  contraction     random complex inputs (several 64-wide tiles of the Gram kernels, ragged
+                  n1 != n2, t0 != 0, and the one-set variant with the same set twice): the
+                  diagrams and pieces agree with the oracle's literal traces to 1e-12 relative
+                  (FP64 sums in another order);
+  full dilution   unit sources over the whole lattice (set 1) and over four spin-colour
+                  components with Z4 phases (set 2), solved on the GPU to 1e-12: the diagrams
+                  agree with the oracle's on the dense inverse (LAPACK) to 1e-9;
+  end to end      tiny workload: the 12 point sources and two sets of 8 noise vectors solved on
+                  the GPU (FP16 inner, tol 1e-10), diagrams against the oracle's on oracle
+                  solutions (tol 1e-12): agreement to 1e-7 (each propagator carries an error
+                  of at most cond(D) x 1e-10, cond(D) ~ 10-100).
+"""
+import numpy as np
+import pytest
+
+from paper_1405_4524_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1405_4524_amd import a2a
+
+    c = a2a.Context(0)
+    yield c
+    c.finalize()
+
+
+def dev(a):
+    import torch
+
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return torch.from_numpy(a.view(np.float64).reshape(a.shape + (2,))).cuda()
+
+
+def host(t):
+    return t.cpu().numpy().view(np.complex128)[..., 0]
+
+
+@pytest.mark.parametrize("dims,t0,x0", [((4, 4, 2, 6), 3, (1, 2, 1)), ((2, 2, 2, 2), 0, (0, 0, 0))])
+def test_point_sources(ctx, orc, dims, t0, x0):
+    import torch
+
+    print(f"[gpu] point sources dims={dims} t0={t0} x0={x0}", flush=True)
+    X, Y, Z, T = dims
+    out = torch.full((12, T, Z, Y, X, 4, 3, 2), 7.0, dtype=torch.float64, device="cuda")
+    ctx.point_sources_dev(dims, t0, x0, out)
+    assert np.array_equal(host(out), orc.point_sources(dims, t0, x0))
+    from paper_1405_4524_amd import a2a
+
+    for bad_t0, bad_x0 in ((T, x0), (-1, x0), (t0, (X, 0, 0)), (t0, (0, 0, Z))):
+        with pytest.raises(a2a.A2AError) as e:
+            ctx.point_sources_dev(dims, bad_t0, bad_x0, out)
+        assert e.value.code == a2a.EINVAL
+
+
+@pytest.mark.parametrize("n1,n2,t0,same", [(70, 65, 5, False), (5, 3, 0, False), (66, 66, 2, True)])
+def test_mixed_contraction_random_inputs(ctx, orc, n1, n2, t0, same):
+    print(f"[gpu] mixed pi-pi contraction n1={n1} n2={n2} t0={t0} same={same}", flush=True)
+    dims = (4, 2, 2, 8)
+    X, Y, Z, T = dims
+    shape = (T, Z, Y, X, 4, 3)
+    rng = np.random.default_rng(n1 + 100 * n2)
+
+    def cplx(*s):
+        return rng.standard_normal(s) + 1j * rng.standard_normal(s)
+
+    Sp = cplx(12, *shape)
+    eta1, X1 = cplx(n1, *shape), cplx(n1, *shape)
+    eta2, X2 = (eta1, X1) if same else (cplx(n2, *shape), cplx(n2, *shape))
+    d, pc = ctx.contract_pipi_mixed_dev(dev(Sp), t0, dev(eta1), dev(X1), n1, dev(eta2), dev(X2), n2, dims)
+    dw, pw = orc.pipi_mixed(Sp, t0, eta1, X1, eta2, X2)
+    for k in range(3):
+        assert rel(pc[k], pw[k]) < 1e-12, k
+    for k in range(4):
+        assert rel(d[k], dw[k]) < 1e-12, k
+
+
+def test_mixed_full_dilution_is_exact(ctx, orc):
+    import torch
+
+    from paper_1405_4524_amd import a2a
+    from tests.test_oracle_pins import dense_operator
+
+    print("[gpu] mixed pi-pi full dilution", flush=True)
+    dims, tbc, kappa, csw, t0, x0 = (2, 2, 2, 4), -1, 0.125, 1.3, 1, (1, 0, 1)
+    X, Y, Z, T = dims
+    NV = 12 * X * Y * Z * T
+    shape = (T, Z, Y, X, 4, 3)
+    U = inputs.gauge_field(dims, 0.4, seed=91)
+    A = orc.clover(U, kappa, csw)
+    Dinv = np.linalg.inv(dense_operator(lambda v: orc.apply_D(U, A, kappa, v, tbc), dims))
+    eta1 = np.eye(NV, dtype=np.complex128).reshape((NV,) + shape)
+    R = [1, 5, 6, 10]
+    rng = np.random.default_rng(9)
+    cols = [s * 12 + k for s in range(NV // 12) for k in R]
+    eta2 = np.zeros((len(cols), NV), np.complex128)
+    eta2[np.arange(len(cols)), cols] = 1j ** rng.integers(0, 4, len(cols))
+    eta2 = eta2.reshape((len(cols),) + shape)
+    n1, n2 = NV, len(cols)
+
+    def oracle_solve(src):
+        return (Dinv @ src.reshape(src.shape[0], -1).T).T.reshape(src.shape)
+
+    g = ctx.load_gauge(U, tbc)
+    c = ctx.load_clover(g, csw)
+    sp_src = torch.empty((12,) + shape + (2,), dtype=torch.float64, device="cuda")
+    ctx.point_sources_dev(dims, t0, x0, sp_src)
+    sols = []
+    for src in (sp_src, dev(eta1), dev(eta2)):
+        sol = torch.zeros_like(src)
+        info, rc = ctx.solve_propagators_dev(c, src, sol, src.shape[0], kappa, csw, tol=1e-12, prec=a2a.F64)
+        assert rc == 0
+        sols.append((src, sol))
+    (_, Sp), (e1, X1), (e2, X2) = sols
+    d, pc = ctx.contract_pipi_mixed_dev(Sp, t0, e1, X1, n1, e2, X2, n2, dims)
+    dw, pw = orc.pipi_mixed(oracle_solve(orc.point_sources(dims, t0, x0)), t0, eta1, oracle_solve(eta1), eta2,
+                            oracle_solve(eta2))
+    for k in range(3):
+        assert rel(pc[k], pw[k]) < 1e-9, k
+    for k in range(4):
+        assert rel(d[k], dw[k]) < 1e-9, k
+    ctx.unload(g)
+
+
+def test_mixed_end_to_end_tiny(ctx, orc):
+    import torch
+
+    from paper_1405_4524_amd import a2a
+
+    print("[gpu] mixed pi-pi end to end, tiny workload", flush=True)
+    w = inputs.WORKLOADS["tiny_4c8"]
+    dims, tbc, kappa, csw = w["dims"], w["tbc"], w["kappa"], w["csw"]
+    X, Y, Z, T = dims
+    t0, x0, n = 0, (0, 0, 0), 8
+    U = inputs.gauge_field(dims, w["eps"], w["gauge_seed"])
+    A = orc.clover(U, kappa, csw)
+    g = ctx.load_gauge(U, tbc)
+    c = ctx.load_clover(g, csw)
+    shape = (T, Z, Y, X, 4, 3, 2)
+    srcs = [torch.empty((12,) + shape, dtype=torch.float64, device="cuda"),
+            torch.empty((n,) + shape, dtype=torch.float64, device="cuda"),
+            torch.empty((n,) + shape, dtype=torch.float64, device="cuda")]
+    ctx.point_sources_dev(dims, t0, x0, srcs[0])
+    ctx.z2_noise_dev(dims, 41, 0, n, srcs[1])
+    ctx.z2_noise_dev(dims, 42, 0, n, srcs[2])
+    sols = []
+    for src in srcs:
+        sol = torch.zeros_like(src)
+        info, rc = ctx.solve_propagators_dev(c, src, sol, src.shape[0], kappa, csw, tol=1e-10, prec=a2a.F16_F32)
+        assert rc == 0
+        sols.append(sol)
+    d, pc = ctx.contract_pipi_mixed_dev(sols[0], t0, srcs[1], sols[1], n, srcs[2], sols[2], n, dims)
+    eta = [host(s) for s in srcs]
+    assert np.array_equal(eta[0], orc.point_sources(dims, t0, x0))
+    assert np.array_equal(eta[1], inputs.z2_noise(dims, n, 41))
+    Xo = []
+    for e in eta:
+        x, io = orc.solve(U, A, kappa, e, tbc, tol=1e-12)
+        assert np.all(io[:, 2] == 1)
+        Xo.append(x)
+    dw, pw = orc.pipi_mixed(Xo[0], t0, eta[1], Xo[1], eta[2], Xo[2])
+    for k in range(3):
+        assert rel(pc[k], pw[k]) < 1e-7, k
+    for k in range(4):
+        assert rel(d[k], dw[k]) < 1e-7, k
+    ctx.unload(g)
