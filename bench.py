@@ -34,9 +34,9 @@ STORAGE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
 # copy (fetch x2.0, write x1.0). Valid only for the kernel sources they were taken on (hash of the
 # stencil's sources) and for the same workload, precision, RHS block and kernel class.
 TRAFFIC = {
-    ("schur2", "l32t64", "f16", "rb2"): {"src": "af099bd1d74b6542", "bytes": 1.3509e10,
+    ("schur2", "l32t64", "f16", "rb2"): {"src": "9435349907081240", "bytes": 1.3538e10,
                                          "profile": "profiles/bench_l32t64_f16_rb2_hbm_counters.txt"},
-    ("schur2", "l32t64", "f16", "il"): {"src": "7d8be83dceca86ae", "bytes": 1.6092e10,
+    ("schur2", "l32t64", "f16", "il"): {"src": "090af55f3cc4af86", "bytes": 1.6077e10,
                                         "profile": "profiles/bench_l32t64_f16_interleaved_hbm_counters.txt"},
 }
 STENCIL_SOURCES = {"per-thread": ("hop.hip", "a2a_device.h", "a2a_reduce.h", "a2a_kernels.h"),
@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--ensemble", type=int, default=0,
                     help="pi-pi diagrams with vacuum subtraction over this many synthetic 8^3x16 configurations")
     ap.add_argument("--fill-sources", default="16,64,256,1024")
+    ap.add_argument("--point-study", action="store_true",
+                    help="pi-pi diagrams from point and stochastic propagators (4^3x8) against the exact "
+                         "diagrams from full dilution, one noise set against two")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
@@ -126,6 +129,9 @@ def main():
         return
     if args.ensemble:
         ensemble_study(args)
+        return
+    if args.point_study:
+        point_study(args)
         return
 
     w = inputs.WORKLOADS[args.workload]
@@ -511,6 +517,78 @@ def noise_study(args):
            "quantity": "sum_{z,x} tr[S(t,z;0,x) S(t,z;0,x)^dag], mean over t of the relative error",
            "exact_solves": M, "exact_s": round(t_exact, 3), "exact_Q": [round(float(v), 6) for v in exact],
            "rows": rows}
+    ctx.unload(g)
+    print(json.dumps(out))
+
+
+def point_study(args):
+    """The pi-pi diagrams of Sec. 8 from point propagators at the origin (12 solves) and
+    stochastic all-to-all propagators, on the synthetic 4^3x8 field (eps 0.2, kappa 0.120,
+    c_sw 1.0): D0 = Cp Cs, D1 = L Cp(0), D2 (D3 = conj D2).  Exact: every unit source of the
+    lattice (12 V = 6144 solves, tol 1e-10), for which the stochastic formulas are exact.
+    Stochastic: N_r complex-Z2 noise vectors per set; one set used for both propagators (E1)
+    against two independent sets (E2).  Reported per N_r and diagram: |D_est - D| / |D| with
+    the norm over dt (Sec. 7's comparison with point propagators, extended to every diagram)."""
+    import numpy as np
+    import torch
+
+    from paper_1405_4524_amd import a2a, inputs
+
+    w = inputs.WORKLOADS["tiny_4c8"]
+    dims, tbc, kappa, csw = w["dims"], w["tbc"], w["kappa"], w["csw"]
+    X, Y, Z, T = dims
+    NV = 12 * X * Y * Z * T
+    ctx = a2a.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+    g = ctx.load_gauge(inputs.gauge_field(dims, w["eps"], w["gauge_seed"]), tbc)
+    c = ctx.load_clover(g, csw)
+    shape = (T, Z, Y, X, 4, 3, 2)
+
+    def solve(src):
+        sol = torch.zeros_like(src)
+        ctx.solve_propagators_dev(c, src, sol, src.shape[0], kappa, csw, tol=1e-10, prec=a2a.F16_F32, allow=())
+        return sol
+
+    t_start = time.perf_counter()
+    psrc = torch.empty((12,) + shape, dtype=torch.float64, device="cuda")
+    ctx.point_sources_dev(dims, 0, (0, 0, 0), psrc)
+    Sp = solve(psrc)
+    unit = torch.zeros((NV,) + shape, dtype=torch.float64, device="cuda")
+    unit.view(NV, NV, 2)[torch.arange(NV), torch.arange(NV), 0] = 1.0
+    Xu = solve(unit)
+    t_solve = time.perf_counter() - t_start
+    d_ex, p_ex = ctx.contract_pipi_mixed_dev(Sp, 0, unit, Xu, NV, unit, Xu, NV, dims)
+    d_ex, p_ex = d_ex * NV * NV, p_ex.copy()
+    p_ex[1:] *= NV * NV
+    t_exact = time.perf_counter() - t_start
+    del unit, Xu
+    torch.cuda.empty_cache()
+    names = ("D0", "D1", "D2")
+
+    def errs(d):
+        return {k: round(float(np.linalg.norm(d[i] - d_ex[i]) / np.linalg.norm(d_ex[i])), 4) for i, k in enumerate(names)}
+
+    rows = []
+    seed = 500
+    for nr in [int(x) for x in args.noise_counts.split(",")]:
+        e1 = torch.empty((nr,) + shape, dtype=torch.float64, device="cuda")
+        e2 = torch.empty_like(e1)
+        ctx.z2_noise_dev(dims, seed, 0, nr, e1)
+        ctx.z2_noise_dev(dims, seed + 1, 0, nr, e2)
+        seed += 2
+        X1, X2 = solve(e1), solve(e2)
+        tc = time.perf_counter()
+        d1, _ = ctx.contract_pipi_mixed_dev(Sp, 0, e1, X1, nr, e1, X1, nr, dims)
+        d2, _ = ctx.contract_pipi_mixed_dev(Sp, 0, e1, X1, nr, e2, X2, nr, dims)
+        tc = (time.perf_counter() - tc) / 2
+        rows.append({"N_r": nr, "one_set": errs(d1), "two_sets": errs(d2), "contract_ms": round(1e3 * tc, 2)})
+        log(f"point study N_r={nr}: one set {rows[-1]['one_set']}, two sets {rows[-1]['two_sets']}")
+        del e1, e2, X1, X2
+    out = {"mode": "point_study", "dims": list(dims), "kappa": kappa, "c_sw": csw, "point": [0, 0, 0, 0],
+           "quantity": "|D_est - D| / |D| over dt for D0 = Cp Cs, D1 = L Cp(0), D2",
+           "exact_solves": NV + 12, "exact_solve_s": round(t_solve, 3), "exact_total_s": round(t_exact, 3),
+           "exact": {k: [[round(float(v.real), 6), round(float(v.imag), 6)] for v in d_ex[i]]
+                     for i, k in enumerate(names)},
+           "point_pion": [round(float(v.real), 6) for v in p_ex[0]], "rows": rows}
     ctx.unload(g)
     print(json.dumps(out))
 

@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <deque>
 
+#include "a2a_contract.h"
 #include "runtime.h"
 
 using namespace a2a;
@@ -192,8 +193,8 @@ static int cgnr_fallback(Ctx* c, Solver& first, std::vector<Slot>& slots, int cl
   return sv.run_until_done(1 << 30);
 }
 
-int solve_core(Ctx* c, int clover_h, const double* src, int nrhs, double kappa, double csw, double tol, int prec,
-               int max_iter, const double* x0, double* sol, a2a_solve_info* info) {
+static int solve_batch(Ctx* c, int clover_h, const double* src, int nrhs, double kappa, double csw, double tol,
+                       int prec, int max_iter, const double* x0, double* sol, a2a_solve_info* info) {
   if (nrhs <= 0) return c->fail(A2A_EINVAL, "nrhs must be positive");
   if (!(tol > 0.0)) return c->fail(A2A_EINVAL, "tol must be positive");
   if (max_iter <= 0) return c->fail(A2A_EINVAL, "max_iter must be positive");
@@ -259,6 +260,31 @@ int solve_core(Ctx* c, int clover_h, const double* src, int nrhs, double kappa, 
   if (worst == A2A_ENOTCONV) c->fail(A2A_ENOTCONV, "some sources did not converge within max_iter");
   if (worst == A2A_EBREAKDOWN) c->fail(A2A_EBREAKDOWN, "the Krylov solver broke down repeatedly");
   if (worst == A2A_ENAN) c->fail(A2A_ENAN, "non-finite source");
+  return worst;
+}
+
+// Requests of more than SOLVE_BATCH sources run as consecutive batches (each batch iterates in
+// lock step; the slot ids a batch holds leave room for a concurrent engine on the context).
+constexpr int SOLVE_BATCH = SID_CAP / 2;
+
+int solve_core(Ctx* c, int clover_h, const double* src, int nrhs, double kappa, double csw, double tol, int prec,
+               int max_iter, const double* x0, double* sol, a2a_solve_info* info) {
+  if (nrhs <= SOLVE_BATCH) return solve_batch(c, clover_h, src, nrhs, kappa, csw, tol, prec, max_iter, x0, sol, info);
+  if (check_prec(prec)) return c->fail(A2A_EINVAL, "unknown precision mode");
+  GaugeField* gf;
+  CloverField* cf;
+  KappaOp* kop;
+  A2A_TRY(resolve_op(c, clover_h, kappa, prec, &gf, &cf, &kop));
+  const size_t per = (size_t)24 * volume_of(gf->g);  // doubles per spinor field
+  int worst = A2A_OK;
+  for (int i0 = 0; i0 < nrhs; i0 += SOLVE_BATCH) {
+    const int n = std::min(SOLVE_BATCH, nrhs - i0);
+    const size_t off = (size_t)i0 * per;
+    const int rc = solve_batch(c, clover_h, src + off, n, kappa, csw, tol, prec, max_iter, x0 ? x0 + off : nullptr,
+                               sol + off, info ? info + i0 : nullptr);
+    if (rc != A2A_OK && rc != A2A_ENOTCONV && rc != A2A_EBREAKDOWN && rc != A2A_ENAN) return rc;
+    if (rc != A2A_OK && (worst == A2A_OK || rc == A2A_ENAN)) worst = rc;
+  }
   return worst;
 }
 

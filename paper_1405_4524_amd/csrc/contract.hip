@@ -8,6 +8,7 @@
 // each (source, timeslice) column is contiguous.  Blocks own a K-chunk of one timeslice and
 // a 64x64 tile of (a, b); operand tiles are staged through LDS and each thread keeps a 4x4
 // register tile of FP64 accumulators.  Chunk partials are summed in fixed order.
+#include "a2a_contract.h"
 #include "a2a_kernels.h"
 
 namespace a2a {

@@ -6,6 +6,7 @@
 // In the chiral basis every sigma_munu = i gamma_mu gamma_nu is block diagonal, so A is two
 // Hermitian 6x6 blocks (spins {0,1} and {2,3}); the kappa-independent part
 // G = i sum sigma (x) F is built once per (gauge field) and A, A^{-1} per kappa.
+#include "a2a_contract.h"
 #include "a2a_kernels.h"
 
 namespace a2a {

@@ -23,6 +23,7 @@
 // mode multiplies two products (S1 from the first operand pair, S2 from the second) tile by
 // tile and accumulates sum C1 conj(C2) without storing either: per-block FP64 partials,
 // summed in block order by a second launch.
+#include "a2a_contract.h"
 #include "a2a_kernels.h"
 
 namespace a2a {
