@@ -6,8 +6,9 @@
 // is, per timeslice, a complex matrix product E_t^dag (gamma_5 X_t) with inner dimension
 // K = 12 L^3 taken straight from the canonical [src][t][z][y][x][spin][colour] arrays, where
 // each (source, timeslice) column is contiguous.  Blocks own a K-chunk of one timeslice and
-// a 64x64 tile of (a, b); operand tiles are staged through LDS and each thread keeps a 4x4
-// register tile of FP64 accumulators.  Chunk partials are summed in fixed order.
+// a 64x64 tile of (a, b); operand tiles are staged through LDS (coalesced along K) and the
+// products run on the FP64 matrix cores, each wave a 16 x 64 strip of the tile.  Chunk partials
+// are summed in fixed order.
 #include "a2a_contract.h"
 #include "a2a_kernels.h"
 
@@ -18,6 +19,10 @@ constexpr int KC = 16;   // complex elements per K step
 
 // rows (optional, [T][na]): row r of timeslice t is source rows[t na + r] (sources supported on
 // that timeslice only, e.g. after time dilution); without it na = n and row r is source r.
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// NC: 16-column tiles per wave (1..4, from n); columns past n are staged as zeros
+template <int NC>
 __global__ __launch_bounds__(256) void k_stoch_partial(int n, int na, long V, int V3, int nchunk, int kchunk,
                                                         int g5, int t_first, const double* __restrict__ eta,
                                                         const double* __restrict__ X,
@@ -32,70 +37,86 @@ __global__ __launch_bounds__(256) void k_stoch_partial(int n, int na, long V, in
   const long K = 12L * V3;
   const long k_begin = (long)chunk * kchunk;
   const long k_end = min(K, k_begin + kchunk);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double accr[4][4], acci[4][4];
+  // wave w owns output rows a0 + 16 w .. + 15 and NC 16-column tiles of the block; a wave whose
+  // rows are all past na issues no products (wave-uniform)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const bool row_on = a0 + 16 * w < na;
+  d4v cr[NC], ci[NC];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) accr[i][j] = acci[i][j] = 0.0;
+  for (int c = 0; c < NC; ++c) cr[c] = ci[c] = d4v{0.0, 0.0, 0.0, 0.0};
   const size_t src_stride = (size_t)12 * V;  // complex per source
   const size_t tbase = (size_t)t * V3 * 12;
-  for (long k0 = k_begin; k0 < k_end; k0 += KC) {
-    // stage: 64 rows x 16 complex for each operand = 1024 complex each, 4 per thread
+  // operand loads of the stage at k0 (64 rows x 16 complex of each operand, 4 per thread):
+  // every load is unconditional, from a clamped in-range element, and out-of-range elements
+  // are zeroed afterwards.  (Loading the next stage during the products cost occupancy and
+  // gained nothing.)
+  double2 pe[4], px[4];
+  auto load = [&](long k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = threadIdx.x + q * 256;
       const int row = e / KC, kk = e % KC;
       const long k = k0 + kk;
-      double2 ev = make_double2(0.0, 0.0), xv = make_double2(0.0, 0.0);
-      if (k < k_end) {
-        if (a0 + row < na) {
-          const int ar = rows ? rows[(size_t)t * na + a0 + row] : a0 + row;
-          const double* p = eta + 2 * ((size_t)ar * src_stride + tbase + k);
-          ev = make_double2(p[0], p[1]);
-          if (phase) {  // eta conj(f) with f = exp(-i p.y): the product below takes conj(eta) f
-            const double fr = phase[2 * (k / 12)], fi = phase[2 * (k / 12) + 1];
-            ev = make_double2(ev.x * fr + ev.y * fi, ev.y * fr - ev.x * fi);
-          }
-        }
-        if (b0 + row < n) {
-          const double* p = X + 2 * ((size_t)(b0 + row) * src_stride + tbase + k);
-          const double sg = (g5 && (k % 12) >= 6) ? -1.0 : 1.0;  // gamma_5 = diag(1,1,-1,-1)
-          xv = make_double2(sg * p[0], sg * p[1]);
-        }
+      const long kc = min(k, k_end - 1);
+      const int ra = min(a0 + row, na - 1), rb = min(b0 + row, n - 1);
+      const int ar = rows ? rows[(size_t)t * na + ra] : ra;
+      double2 ev = *(const double2*)(eta + 2 * ((size_t)ar * src_stride + tbase + kc));
+      double2 xv = *(const double2*)(X + 2 * ((size_t)rb * src_stride + tbase + kc));
+      if (phase) {  // eta conj(f) with f = exp(-i p.y): the product below takes conj(eta) f
+        const double fr = phase[2 * (kc / 12)], fi = phase[2 * (kc / 12) + 1];
+        ev = make_double2(ev.x * fr + ev.y * fi, ev.y * fr - ev.x * fi);
       }
-      Es[row][kk] = ev;
-      Xs[row][kk] = xv;
+      const double sg = (g5 && (kc % 12) >= 6) ? -1.0 : 1.0;  // gamma_5 = diag(1,1,-1,-1)
+      const bool kin = k < k_end;
+      pe[q] = kin && a0 + row < na ? ev : make_double2(0.0, 0.0);
+      px[q] = kin && b0 + row < n ? make_double2(sg * xv.x, sg * xv.y) : make_double2(0.0, 0.0);
+    }
+  };
+  for (long k0 = k_begin; k0 < k_end; k0 += KC) {
+    load(k0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + q * 256;
+      Es[e / KC][e % KC] = pe[q];
+      Xs[e / KC][e % KC] = px[q];
     }
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < KC; ++kk) {
-      double2 e[4], x[4];
+    if (row_on) {
+      // v_mfma_f64_16x16x4: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; four real
+      // products per complex K step: Re += er xr + ei xi, Im += er xi - ei xr, issued tile-
+      // interleaved so that consecutive products accumulate into different registers
 #pragma unroll
-      for (int i = 0; i < 4; ++i) e[i] = Es[ty * 4 + i][kk];
+      for (int ks = 0; ks < KC / 4; ++ks) {
+        const double2 e = Es[16 * w + li][4 * ks + lk];
+        double2 x[NC];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) x[j] = Xs[tx * 4 + j][kk];
+        for (int c = 0; c < NC; ++c) x[c] = Xs[16 * c + li][4 * ks + lk];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int c = 0; c < NC; ++c) cr[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.x, x[c].x, cr[c], 0, 0, 0);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {  // conj(e) * x
-          accr[i][j] += e[i].x * x[j].x + e[i].y * x[j].y;
-          acci[i][j] += e[i].x * x[j].y - e[i].y * x[j].x;
-        }
+        for (int c = 0; c < NC; ++c) ci[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.x, x[c].y, ci[c], 0, 0, 0);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) cr[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.y, x[c].y, cr[c], 0, 0, 0);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ci[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-e.y, x[c].x, ci[c], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
+  // element q of a 16 x 16 accumulator tile is row 4 q + lane / 16, column lane % 16
   double* out = partial + (((size_t)tl * nchunk + chunk) * na) * n * 2;
+  if (row_on)
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int a = a0 + ty * 4 + i, b = b0 + tx * 4 + j;
-      if (a < na && b < n) {
-        out[2 * ((size_t)a * n + b)] = accr[i][j];
-        out[2 * ((size_t)a * n + b) + 1] = acci[i][j];
+      for (int q = 0; q < 4; ++q) {
+        const int a = a0 + 16 * w + 4 * q + lk, b = b0 + 16 * c + li;
+        if (a < na && b < n) {
+          out[2 * ((size_t)a * n + b)] = cr[c][q];
+          out[2 * ((size_t)a * n + b) + 1] = ci[c][q];
+        }
       }
-    }
 }
 
 __global__ void k_stoch_sum(int n, int na, int T, int nchunk, const double* partial, double* O) {
@@ -125,8 +146,12 @@ void launch_stoch_ops(const Geo& g, int n, const double* eta, const double* X, d
   if (na <= 0) na = n;  // rows == null: eta rows 0 .. na - 1
   const int ntb = (n + CT - 1) / CT, nta = (na + CT - 1) / CT;
   dim3 grid(nchunk, nt, nta * ntb);
-  hipLaunchKernelGGL(k_stoch_partial, grid, dim3(256), 0, s, n, na, V, V3, nchunk, (int)kchunk, g5, t_first, eta, X,
-                     phase, rows, partial);
+  // column tiles per wave: enough for n (a single column block), else all four
+  const int nc = ntb > 1 ? 4 : (n + 15) / 16;
+  auto kern = nc == 1 ? k_stoch_partial<1> : nc == 2 ? k_stoch_partial<2> : nc == 3 ? k_stoch_partial<3>
+                                                                                       : k_stoch_partial<4>;
+  hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, n, na, V, V3, nchunk, (int)kchunk, g5, t_first, eta, X, phase, rows,
+                     partial);
   const long tot = (long)nt * na * n;
   hipLaunchKernelGGL(k_stoch_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, na, nt, nchunk, partial,
                      O);
