@@ -30,9 +30,10 @@ __global__ __launch_bounds__(256) void k_stoch_partial(int n, int na, long V, in
                                                         const int* __restrict__ rows, double* partial) {
   __shared__ double2 Es[CT][KC + 1];
   __shared__ double2 Xs[CT][KC + 1];
-  const int chunk = blockIdx.x, tl = blockIdx.y, t = t_first + tl;
+  // grid: x = output tile (row tile x column tile), y = timeslice, z = K chunk (<= 4096)
+  const int chunk = blockIdx.z, tl = blockIdx.y, t = t_first + tl;
   const int ntb = (n + CT - 1) / CT;
-  const int ta = blockIdx.z / ntb, tb = blockIdx.z % ntb;
+  const int ta = blockIdx.x / ntb, tb = blockIdx.x % ntb;
   const int a0 = ta * CT, b0 = tb * CT;
   const long K = 12L * V3;
   const long k_begin = (long)chunk * kchunk;
@@ -145,7 +146,7 @@ void launch_stoch_ops(const Geo& g, int n, const double* eta, const double* X, d
   kchunk = ((kchunk + KC - 1) / KC) * KC;
   if (na <= 0) na = n;  // rows == null: eta rows 0 .. na - 1
   const int ntb = (n + CT - 1) / CT, nta = (na + CT - 1) / CT;
-  dim3 grid(nchunk, nt, nta * ntb);
+  dim3 grid((unsigned)(nta * ntb), nt, nchunk);
   // column tiles per wave: enough for n (a single column block), else all four
   const int nc = ntb > 1 ? 4 : (n + 15) / 16;
   auto kern = nc == 1 ? k_stoch_partial<1> : nc == 2 ? k_stoch_partial<2> : nc == 3 ? k_stoch_partial<3>
