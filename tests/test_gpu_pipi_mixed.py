@@ -63,7 +63,7 @@ def test_point_sources(ctx, orc, dims, t0, x0):
         assert e.value.code == a2a.EINVAL
 
 
-@pytest.mark.parametrize("n1,n2,t0,same", [(70, 65, 5, False), (5, 3, 0, False), (66, 66, 2, True)])
+@pytest.mark.parametrize("n1,n2,t0,same", [(70, 65, 5, False), (5, 3, 0, False), (66, 66, 2, True), (1, 1, 7, False)])
 def test_mixed_contraction_random_inputs(ctx, orc, n1, n2, t0, same):
     print(f"[gpu] mixed pi-pi contraction n1={n1} n2={n2} t0={t0} same={same}", flush=True)
     dims = (4, 2, 2, 8)
@@ -83,6 +83,20 @@ def test_mixed_contraction_random_inputs(ctx, orc, n1, n2, t0, same):
         assert rel(pc[k], pw[k]) < 1e-12, k
     for k in range(4):
         assert rel(d[k], dw[k]) < 1e-12, k
+
+
+def test_mixed_contraction_rejects_bad_arguments(ctx):
+    import torch
+
+    from paper_1405_4524_amd import a2a
+
+    print("[gpu] mixed pi-pi argument checks", flush=True)
+    dims = (2, 2, 2, 4)
+    v = torch.zeros((12, 4, 2, 2, 2, 4, 3, 2), dtype=torch.float64, device="cuda")
+    for t0, n1, n2 in ((4, 2, 2), (-1, 2, 2), (0, 0, 2), (0, 2, 0)):
+        with pytest.raises(a2a.A2AError) as e:
+            ctx.contract_pipi_mixed_dev(v, t0, v, v, n1, v, v, n2, dims)
+        assert e.value.code == a2a.EINVAL
 
 
 def test_mixed_full_dilution_is_exact(ctx, orc):
