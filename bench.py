@@ -85,6 +85,8 @@ def main():
                     help="serving run: Poisson request streams on resident 8^3x16, 16^3x32, 24^3x48 fields")
     ap.add_argument("--serve-rates", default="1,2,5,10,20,50")
     ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-policy", default='{"max_slots": 256, "check_every": 4}', help="engine policy JSON")
+    ap.add_argument("--serve-step", type=int, default=4, help="solver iterations per engine step")
     ap.add_argument("--serve-cap", type=int, default=384,
                     help="RHS submitted to the engine at most at once; later arrivals wait on the client side")
     ap.add_argument("--mixed", action="store_true",
@@ -681,6 +683,8 @@ def serve_or_mixed(args):
         return src, torch.zeros_like(src)
 
     out = {"mode": "mixed" if args.mixed else "serve", "precision": args.prec, "rhs_block": args.rhs_block}
+    if not args.mixed:
+        out.update(policy=json.loads(args.serve_policy), iters_per_step=args.serve_step, cap_rhs=args.serve_cap)
     if args.mixed:
         rng = np.random.default_rng(4)
         jobs = []
@@ -719,7 +723,7 @@ def serve_or_mixed(args):
                     "max_rel_diff_batch_vs_alone": diff})
         log(f"mixed batch {ntot / t_mix:.1f} RHS/s vs lattice by lattice {ntot / t_seq:.1f} RHS/s, diff {diff:.2e}")
     else:
-        eng = ctx.engine_create('{"max_slots": 256, "check_every": 4}')
+        eng = ctx.engine_create(args.serve_policy)
         results = []
         for rate in [float(x) for x in args.serve_rates.split(",")]:
             rng = np.random.default_rng(3 + int(rate))
@@ -749,7 +753,7 @@ def serve_or_mixed(args):
                     live[tk] = (arrivals[j], n, src, sol)
                     outstanding += n
                 if live:
-                    eng.step(4)
+                    eng.step(args.serve_step)
                 else:
                     time.sleep(max(0.0, min(0.01, arrivals[k] - now)))
                 for tk in list(live):

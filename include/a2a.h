@@ -131,7 +131,9 @@ const char *a2a_last_error(const a2a_ctx *ctx);
  * reliable update, so that the fallback runs).
  * Returns A2A_EINVAL for an unknown key. */
 int a2a_set_option(a2a_ctx *ctx, const char *key, double value);
-/* Bytes of device memory currently held by the context. */
+/* Bytes of device memory in the context's live buffers.  Freed buffers are kept for reuse
+ * (same-size requests take them without hipMalloc) and are released whenever an allocation
+ * would otherwise not fit the budget or the device; they are not counted here. */
 size_t a2a_mem_in_use(const a2a_ctx *ctx);
 
 /* ---- resident fields (Sec. 7 "inversions in the background of the gauge field") ------ */

@@ -457,6 +457,7 @@ extern "C" int a2a_finalize(a2a_ctx* h) {
   for (int g : hs) a2a_unload(h, g);
   for (auto& kv : c->sizes) (void)hipFree(kv.first);
   c->sizes.clear();
+  c->release_cache();
   if (c->scal_host) (void)hipHostFree(c->scal_host);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete h;

@@ -222,27 +222,37 @@ HD M3 field_strength(const Geo& g, const double* U, const int c[4], int mu, int 
 HD void sigma_block(int plane, int b, int cf[3]) {
   const int up[6][3] = {{0, 0, -1}, {0, 1, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
   const int dn[6][3] = {{0, 0, -1}, {0, 1, 0}, {-1, 0, 0}, {-1, 0, 0}, {0, -1, 0}, {0, 0, -1}};
+#pragma unroll
   for (int k = 0; k < 3; ++k) cf[k] = b ? dn[plane][k] : up[plane][k];
 }
 
 // packed G = i sum_{mu<nu} sigma_munu^(b) (x) F_munu for chiral block b at site c
 HD void clover_G_block(const Geo& g, const double* U, const int c[4], int b, double out[36]) {
+  // every loop unrolled: plane, sigma coefficients and matrix indices are compile-time
+  // constants (a run-time index into the coefficient tables would place them in scratch memory)
   cx<double> G[36];
+#pragma unroll
   for (int k = 0; k < 36; ++k) G[k] = mk(0.0, 0.0);
-  int plane = 0;
+#pragma unroll
   for (int mu = 0; mu < 4; ++mu)
-    for (int nu = mu + 1; nu < 4; ++nu, ++plane) {
+#pragma unroll
+    for (int nu = mu + 1; nu < 4; ++nu) {
+      const int plane = mu == 0 ? nu - 1 : mu == 1 ? nu + 1 : 5;  // (01, 02, 03, 12, 13, 23)
       M3 F = field_strength(g, U, c, mu, nu);
       int cf[3];
       sigma_block(plane, b, cf);
       // M = c1 s1 + c2 s2 + c3 s3 = [[c3, c1 - i c2], [c1 + i c2, -c3]]
       cx<double> M[4] = {mk((double)cf[2], 0.0), mk((double)cf[0], -(double)cf[1]),
                          mk((double)cf[0], (double)cf[1]), mk(-(double)cf[2], 0.0)};
+#pragma unroll
       for (int s1 = 0; s1 < 2; ++s1)
+#pragma unroll
         for (int s2 = 0; s2 < 2; ++s2) {
           cx<double> im = mul_i(M[s1 * 2 + s2]);  // i M
           if (im.re == 0.0 && im.im == 0.0) continue;
+#pragma unroll
           for (int a = 0; a < 3; ++a)
+#pragma unroll
             for (int bb = 0; bb < 3; ++bb)
               G[(s1 * 3 + a) * 6 + s2 * 3 + bb] = G[(s1 * 3 + a) * 6 + s2 * 3 + bb] + im * F.m[a * 3 + bb];
         }
@@ -298,39 +308,55 @@ HD void pack6(const cx<double> M[36], double* p) {
 
 HD double cabs2(cx<double> a) { return a.re * a.re + a.im * a.im; }
 
+// Gauss-Jordan with partial pivoting.  Every loop is unrolled and the pivot row is swapped in
+// by a comparison with each candidate row, so all indices are compile-time constants and the
+// augmented matrix stays in registers (a run-time row index would place it in scratch memory,
+// which the runtime must allocate at dispatch).
 HD int invert6(const cx<double> M[36], cx<double> R[36]) {
   cx<double> a[6][12];
+#pragma unroll
   for (int i = 0; i < 6; ++i)
+#pragma unroll
     for (int j = 0; j < 6; ++j) {
       a[i][j] = M[i * 6 + j];
       a[i][6 + j] = mk(i == j ? 1.0 : 0.0, 0.0);
     }
+#pragma unroll
   for (int c = 0; c < 6; ++c) {
     int piv = c;
     double best = cabs2(a[c][c]);
+#pragma unroll
     for (int r = c + 1; r < 6; ++r)
       if (cabs2(a[r][c]) > best) {
         best = cabs2(a[r][c]);
         piv = r;
       }
     if (best == 0.0) return 1;
-    if (piv != c)
-      for (int j = 0; j < 12; ++j) {
-        cx<double> t = a[c][j];
-        a[c][j] = a[piv][j];
-        a[piv][j] = t;
-      }
+#pragma unroll
+    for (int r = c + 1; r < 6; ++r)
+      if (r == piv)
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+          cx<double> t = a[c][j];
+          a[c][j] = a[r][j];
+          a[r][j] = t;
+        }
     cx<double> d = a[c][c];
     double dn = cabs2(d);
     cx<double> di = mk(d.re / dn, -d.im / dn);
+#pragma unroll
     for (int j = 0; j < 12; ++j) a[c][j] = di * a[c][j];
+#pragma unroll
     for (int r = 0; r < 6; ++r) {
       if (r == c) continue;
       cx<double> f = a[r][c];
+#pragma unroll
       for (int j = 0; j < 12; ++j) a[r][j] = a[r][j] - f * a[c][j];
     }
   }
+#pragma unroll
   for (int i = 0; i < 6; ++i)
+#pragma unroll
     for (int j = 0; j < 6; ++j) R[i * 6 + j] = a[i][6 + j];
   return 0;
 }

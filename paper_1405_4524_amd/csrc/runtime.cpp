@@ -81,10 +81,27 @@ int Ctx::dalloc(void** p, size_t n) {
   *p = nullptr;
   if (n == 0) return A2A_OK;
   n = (n + 255) & ~(size_t)255;
+  // a cached block of this size, or at most 1/8 larger
+  auto it = cache.lower_bound(n);
+  if (it != cache.end() && it->first <= n + n / 8) {
+    const size_t sz = it->first;
+    *p = it->second;
+    cache.erase(it);
+    cached -= sz;
+    used += sz;
+    sizes[*p] = sz;
+    return A2A_OK;
+  }
   if (used + n > budget)
     return fail(A2A_ENOMEM, "HBM budget exceeded: need " + std::to_string(n) + " B, " +
                                 std::to_string(budget - std::min(budget, used)) + " B left");
+  if (used + cached + n > budget) release_cache();
   hipError_t e = hipMalloc(p, n);
+  if (e != hipSuccess && cached > 0) {
+    (void)hipGetLastError();
+    release_cache();
+    e = hipMalloc(p, n);
+  }
   if (e != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
@@ -98,11 +115,18 @@ int Ctx::dalloc(void** p, size_t n) {
 void Ctx::dfree(void* p) {
   if (!p) return;
   auto it = sizes.find(p);
-  if (it != sizes.end()) {
-    used -= it->second;
-    sizes.erase(it);
-  }
-  (void)hipFree(p);
+  if (it == sizes.end()) return;  // not a block of this context
+  const size_t sz = it->second;
+  used -= sz;
+  sizes.erase(it);
+  cache.emplace(sz, p);
+  cached += sz;
+}
+
+void Ctx::release_cache() {
+  for (auto& kv : cache) (void)hipFree(kv.second);  // hipFree waits for work still using them
+  cache.clear();
+  cached = 0;
 }
 
 int Ctx::alloc_sid(int nblk, int* sid) {

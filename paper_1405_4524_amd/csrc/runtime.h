@@ -178,7 +178,15 @@ struct Ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   size_t budget = 0, used = 0;
-  std::unordered_map<void*, size_t> sizes;
+  std::unordered_map<void*, size_t> sizes;  // live allocations
+  // freed blocks kept for reuse, by size: per-request slot buffers come and go with every
+  // request, and hipMalloc / hipFree of hundreds of MB (hipFree waits for the device) cost
+  // more than the solves of small requests.  All work on library memory is ordered on
+  // `stream`, so a block can be handed out again while kernels that used it are still queued.
+  // The budget limits live bytes; the cache is released when live + cached + new would exceed
+  // it or hipMalloc fails.
+  std::multimap<size_t, void*> cache;
+  size_t cached = 0;
   std::string err;
   int next_handle = 1;
   std::map<int, std::unique_ptr<GaugeField>> gauges;
@@ -227,6 +235,7 @@ struct Ctx {
   }
   int dalloc(void** p, size_t n);
   void dfree(void* p);
+  void release_cache();
   int alloc_sid(int nblk, int* sid);
   void free_sid(int sid);
   int ensure_partials(int nslots, int nblk);

@@ -172,3 +172,42 @@ def test_engine_admission_by_budget_and_cancel(orc, fields):
         eng.destroy()
     finally:
         c2.finalize()
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_repeat_solve_on_recycled_memory_is_bitwise_identical(ctx, orc, fields, prec):
+    """The context hands freed device buffers to later allocations of the same size: solves
+    and engine requests that run on recycled buffers (holding whatever the previous user left,
+    with other-sized work in between) give bitwise the same solutions, iteration counts and
+    residuals as the first solve on fresh memory."""
+    import torch
+
+    print(f"[gpu] repeat solve on recycled memory prec={prec}", flush=True)
+    f = fields[0]
+    eta = inputs.z2_noise(f["dims"], 20, seed=410)
+    X0, info0, rc = ctx.solve_propagators(f["c"], eta, 0.124, 1.5, tol=1e-10, prec=prec)
+    assert rc == 0
+    other = inputs.z2_noise(f["dims"], 7, seed=411)  # different sizes in between
+    ctx.solve_propagators(f["c"], other, 0.126, 1.5, tol=1e-10, prec=1)
+    for _ in range(2):
+        X1, info1, rc = ctx.solve_propagators(f["c"], eta, 0.124, 1.5, tol=1e-10, prec=prec)
+        assert rc == 0
+        assert np.array_equal(X1, X0)
+        assert [x["iters"] for x in info1] == [x["iters"] for x in info0]
+        assert [x["true_rel_residual"] for x in info1] == [x["true_rel_residual"] for x in info0]
+    runs = []
+    for k in range(2):  # the same request twice, a differently sized one in between
+        eng = ctx.engine_create('{"max_slots": 64}')
+        src = torch.from_numpy(eta).cuda()
+        sol = torch.zeros_like(src)
+        t = eng.submit(f["c"], 0.124, src, 20, 1e-10, prec, 20000, sol)
+        for _ in range(3000):
+            eng.step(4)
+            if eng.poll(t, 20)[0] != 0:
+                break
+        done, info, rc = eng.poll(t, 20)
+        assert done == 1 and rc == 0
+        runs.append((sol.cpu().numpy(), [x["iters"] for x in info]))
+        eng.destroy()
+        ctx.solve_propagators(f["c"], other[:3], 0.126, 1.5, tol=1e-10, prec=1)
+    assert np.array_equal(runs[0][0], runs[1][0]) and runs[0][1] == runs[1][1]
