@@ -128,7 +128,9 @@ const char *a2a_last_error(const a2a_ctx *ctx);
  * sources whose BiCGStab broke down repeatedly are solved again by CGNR from their current
  * iterate; iterations count against the same max_iter), "force_breakdown" (0/1, default 0:
  * a test hook that makes every BiCGStab source of a solve call report a breakdown at its first
- * reliable update, so that the fallback runs).
+ * reliable update, so that the fallback runs), "poison_memory" (0/1, default 0: a test hook that
+ * fills every device buffer the context allocates or reuses with 0xFF bytes, NaN in every
+ * floating format, so that a read of memory not written first shows in the results).
  * Returns A2A_EINVAL for an unknown key. */
 int a2a_set_option(a2a_ctx *ctx, const char *key, double value);
 /* Bytes of device memory in the context's live buffers.  Freed buffers are kept for reuse

@@ -510,6 +510,8 @@ extern "C" int a2a_set_option(a2a_ctx* h, const char* key, double v) {
     c->cgnr_fallback = v != 0;
   } else if (k == "force_breakdown") {
     c->force_breakdown = v != 0;
+  } else if (k == "poison_memory") {
+    c->poison = v != 0;
   } else if (k == "hbm_budget") {
     if (!(v > 0)) return c->fail(A2A_EINVAL, "hbm_budget must be positive");
     c->budget = (size_t)v;

@@ -442,12 +442,14 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void
           r2 += o0 * o0 + o1 * o1 + o2 * o2 + o3 * o3;
         }
       }
+      // a select, not a product with 0 or 1: an idle lane's column holds whatever its memory
+      // held, and 0 * NaN would reach the partial sums of the same lane in the other tiles
 #pragma unroll
       for (int t = 0; t < NTMAX; ++t) {
-        const float keep = (live && t == nt && myslot[t] >= 0) ? 1.f : 0.f;
-        red[t][0] += keep * r0;
-        red[t][1] += keep * r1;
-        red[t][2] += keep * r2;
+        const bool keep = live && t == nt && myslot[t] >= 0;
+        red[t][0] += keep ? r0 : 0.f;
+        red[t][1] += keep ? r1 : 0.f;
+        red[t][2] += keep ? r2 : 0.f;
       }
     }
     // to the storage layout through LDS: one 16-byte store per lane (idle lanes write their own

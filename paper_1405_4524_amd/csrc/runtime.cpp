@@ -90,6 +90,7 @@ int Ctx::dalloc(void** p, size_t n) {
     cached -= sz;
     used += sz;
     sizes[*p] = sz;
+    if (poison) (void)hipMemsetAsync(*p, 0xFF, sz, stream);
     return A2A_OK;
   }
   if (used + n > budget)
@@ -109,6 +110,7 @@ int Ctx::dalloc(void** p, size_t n) {
   }
   used += n;
   sizes[*p] = n;
+  if (poison) (void)hipMemsetAsync(*p, 0xFF, n, stream);
   return A2A_OK;
 }
 

@@ -209,6 +209,7 @@ struct Ctx {
   int solver = SOLVER_BICGSTAB;      // inner Krylov method of solves and engine requests
   int cgnr_fallback = 1;             // BiCGStab breakdowns are finished by CGNR (solve calls)
   int force_breakdown = 0;           // test hook: BiCGStab slots break down at their first update
+  bool poison = false;               // test hook: allocations are filled with 0xFF bytes (NaN)
   std::map<std::string, int> tuned;  // tune key -> RHS-block width
   std::string tune_path;             // A2A_TUNE_CACHE: JSON file of tuned widths
   // reduction scratch

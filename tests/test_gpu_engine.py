@@ -211,3 +211,53 @@ def test_repeat_solve_on_recycled_memory_is_bitwise_identical(ctx, orc, fields, 
         eng.destroy()
         ctx.solve_propagators(f["c"], other[:3], 0.126, 1.5, tol=1e-10, prec=1)
     assert np.array_equal(runs[0][0], runs[1][0]) and runs[0][1] == runs[1][1]
+
+
+@pytest.mark.parametrize("prec", [2, 0])
+def test_no_result_depends_on_unwritten_memory(orc, fields, prec):
+    """With every buffer the context allocates or reuses filled with NaN bytes (option
+    poison_memory), solves in interleaved groups with an idle lane (47 = 16 + 16 + 15 sources),
+    a per-slot solve on reused buffers, CGNR, an engine request and the contractions give
+    bitwise the results of a context without the poison: no kernel lets memory it did not
+    write reach a result (an idle lane's 0 * NaN once reached the reductions of its column)."""
+    import torch
+
+    from paper_1405_4524_amd import a2a
+
+    print(f"[gpu] poisoned memory prec={prec}", flush=True)
+    f = fields[0]
+    eta = inputs.z2_noise(f["dims"], 47, seed=420)
+    res = []
+    for poison in (0, 1):
+        c2 = a2a.Context(0)
+        try:
+            c2.set_option("poison_memory", poison)
+            g = c2.load_gauge(f["U"], -1)
+            cl = c2.load_clover(g, 1.5)
+            out = []
+            for n, solver in ((47, a2a.SOLVER_BICGSTAB), (5, a2a.SOLVER_BICGSTAB), (20, a2a.SOLVER_CGNR)):
+                c2.set_option("solver", solver)
+                X, info, rc = c2.solve_propagators(cl, eta[:n], 0.124, 1.5, tol=1e-10, prec=prec, max_iter=20000)
+                assert rc == 0 and all(x["converged"] == 1 for x in info)
+                out += [X, np.array([x["iters"] for x in info])]
+            c2.set_option("solver", a2a.SOLVER_BICGSTAB)
+            eng = c2.engine_create('{"max_slots": 64}')
+            src = torch.from_numpy(eta[:31]).cuda()
+            sol = torch.zeros_like(src)
+            t = eng.submit(cl, 0.123, src, 31, 1e-10, prec, 20000, sol)
+            for _ in range(3000):
+                eng.step(4)
+                if eng.poll(t, 31)[0] != 0:
+                    break
+            assert eng.poll(t, 31)[0] == 1
+            eng.destroy()
+            out.append(sol.cpu().numpy())
+            X = out[0]
+            corr, O = c2.contract_pion_2pt(eta, X)
+            d, v = c2.contract_pipi_2pt(eta[:16], X[:16])
+            out += [corr, O, d, v]
+            res.append(out)
+        finally:
+            c2.finalize()
+    for k, (a, b) in enumerate(zip(*res)):
+        assert np.array_equal(a, b), k
