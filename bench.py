@@ -37,7 +37,7 @@ STORAGE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
 TRAFFIC = {
     ("schur2", "l32t64", "f16", "rb2"): {"src": "9435349907081240", "bytes": 1.3538e10,
                                          "profile": "profiles/bench_l32t64_f16_rb2_hbm_counters.txt"},
-    ("schur2", "l32t64", "f16", "il"): {"src": "090af55f3cc4af86", "bytes": 1.6077e10,
+    ("schur2", "l32t64", "f16", "il"): {"src": "6019d7b89fbc2b12", "bytes": 1.6062e+10,
                                         "profile": "profiles/bench_l32t64_f16_interleaved_hbm_counters.txt"},
 }
 STENCIL_SOURCES = {"per-thread": ("hop.hip", "a2a_device.h", "a2a_reduce.h", "a2a_kernels.h"),
