@@ -188,3 +188,53 @@ def test_mixed_end_to_end_tiny(ctx, orc):
     for k in range(4):
         assert rel(d[k], dw[k]) < 1e-7, k
     ctx.unload(g)
+
+
+def test_contractions_do_not_read_unwritten_memory(orc):
+    """Every contraction entry point (fill and its dagger, the fill and Gram routes of
+    sum tr S1 S2^dag, dilution and momentum projection with time and time-spin-colour
+    dilution, the mixed pi-pi diagrams) gives bitwise the same results in a context whose
+    allocations are filled with NaN bytes (option poison_memory) as in one without."""
+    import torch
+
+    from paper_1405_4524_amd import a2a
+
+    print("[gpu] contractions on poisoned memory", flush=True)
+    dims = (4, 2, 2, 8)
+    X, Y, Z, T = dims
+    shape = (T, Z, Y, X, 4, 3)
+    rng = np.random.default_rng(77)
+
+    def cplx(*s):
+        return rng.standard_normal(s) + 1j * rng.standard_normal(s)
+
+    n = 21
+    eta1, X1, eta2, X2, Sp = cplx(n, *shape), cplx(n, *shape), cplx(n, *shape), cplx(n, *shape), cplx(12, *shape)
+    noise = dev(cplx(3, *shape))
+    dil = ((a2a.DILUTE_T, T), (a2a.DILUTE_TSC, 12 * T))
+    dsol = [cplx(3 * D, *shape) for _, D in dil]
+    M = 12 * X * Y * Z
+    res = []
+    for poison in (0, 1):
+        c = a2a.Context(0)
+        try:
+            c.set_option("poison_memory", poison)
+            out = []
+            for dag in (False, True):
+                S = torch.empty((M, M, 2), dtype=torch.float64, device="cuda")
+                c.fill_propagator_dev(dev(X1), dev(eta1), n, dims, 2, 5, S, dagger=dag)
+                out.append(S.cpu().numpy())
+            for method in ("fill", "gram"):
+                out.append(c.contract_fill_2pt_dev(dev(X1), dev(eta1), dev(X2), dev(eta2), n, dims, 3, method=method))
+            for (scheme, D), xs in zip(dil, dsol):
+                src = torch.empty((3 * D,) + shape + (2,), dtype=torch.float64, device="cuda")
+                c.dilute_dev(noise, 3, dims, scheme, src)
+                sol = dev(xs)
+                out.append(c.contract_pion_mom_dev(src, sol, 3 * D, dims, [(0, 0, 0), (1, 0, 0)], scheme=scheme))
+            d, pc = c.contract_pipi_mixed_dev(dev(Sp), 3, dev(eta1), dev(X1), n, dev(eta2), dev(X2), n - 4, dims)
+            out += [d, pc]
+            res.append(out)
+        finally:
+            c.finalize()
+    for k, (a, b) in enumerate(zip(*res)):
+        assert np.array_equal(a, b), k
