@@ -111,7 +111,7 @@ def main():
                          "diagrams from full dilution, one noise set against two")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
+        print(json.dumps({"error": "this library runs on one GPU; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
