@@ -289,7 +289,11 @@ int a2a_z2_noise_dev(a2a_ctx *ctx, const a2a_geom *geom, unsigned long long seed
  * "check_every".  Requests of any resident lattice, kappa and precision share the device;
  * a request is admitted when its memory fits the context's HBM budget, and its sources
  * join the running batch at the next step.  sources_dev / solutions_dev must stay valid
- * until a2a_engine_poll reports the ticket done. */
+ * until a2a_engine_poll reports the ticket done.  Each request runs with the inner method
+ * (option "solver") set when it was submitted; unlike a2a_solve_propagators, the engine has
+ * no CGNR fallback: a source whose BiCGStab breaks down repeatedly fails its request with
+ * A2A_EBREAKDOWN (its sources share lane groups with sources still iterating), and the caller
+ * may submit it again with "solver" = A2A_SOLVER_CGNR. */
 int a2a_engine_create(a2a_ctx *ctx, const char *policy_json, a2a_engine **eng);
 int a2a_engine_submit(a2a_engine *eng, int clover_h, double kappa, const double *sources_dev, int nsrc, double tol,
                       int prec, int max_iter, double *solutions_dev, long long *ticket);
