@@ -847,11 +847,14 @@ def copy_1gib(reps):
     return ms
 
 
+ORACLE_ITERS = 12  # full-lattice oracle iterations timed for the CPU baseline
+
+
 def cpu_baseline(w, links_np):
-    """The FP64 CPU oracle on a bounded sample of the same workload (about 20 s of CPU work):
-    two BiCGStab iterations of its plain full-lattice solver on one source at the full lattice
-    (time per iteration), times the iteration count its solver needs at the same kappa, c_sw
-    and field recipe on an 8^3x16 lattice (solved to 1e-10); gives RHS/s."""
+    """The FP64 CPU oracle on a bounded sample of the same workload (10-15 s of CPU work):
+    ORACLE_ITERS BiCGStab iterations of its plain full-lattice solver on one source at the full
+    lattice (time per iteration), times the iteration count its solver needs at the same kappa,
+    c_sw and field recipe on an 8^3x16 lattice (solved to 1e-10); gives RHS/s."""
     import numpy as np
 
     import oracle
@@ -863,8 +866,8 @@ def cpu_baseline(w, links_np):
     t_clover = time.time() - t
     eta = inputs.z2_noise(dims, 1, w["noise_seed"])[0]
     t = time.time()
-    _, hist = oracle.bicgstab_fixed(links_np, A, kappa, eta, tbc, 2)
-    t_iter = (time.time() - t) / 2
+    _, hist = oracle.bicgstab_fixed(links_np, A, kappa, eta, tbc, ORACLE_ITERS)
+    t_iter = (time.time() - t) / ORACLE_ITERS
     del A
     log(f"oracle: clover {t_clover:.1f}s, {t_iter:.2f}s per full-lattice BiCGStab iteration")
     small = (8, 8, 8, 16)
@@ -878,7 +881,7 @@ def cpu_baseline(w, links_np):
     rate = 1.0 / (iters * t_iter)
     log(f"oracle: {iters} iterations at 8^3x16 ({t_small:.1f}s); {rate:.5f} RHS/s estimated at full size")
     return {"value": rate, "unit": "RHS/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"2 full-lattice BiCGStab iterations on 1 source ({t_iter:.2f} s/iter) x {iters} "
+            "sample": f"{ORACLE_ITERS} full-lattice BiCGStab iterations on 1 source ({t_iter:.2f} s/iter) x {iters} "
                       f"iterations needed by the same oracle solver at 8^3x16 with the same kappa, c_sw, "
                       f"field recipe and tol; clover build {t_clover:.1f} s not counted",
             "secs_per_iter": t_iter, "iters_8c16": iters}
