@@ -8,11 +8,16 @@ One step is one pass of the whole hot path over one batch of synthetic input res
   true residual, the stochastic-operator contraction, the pion and the pi-pi correlators.
 value = sources solved per second over the timed steps (whole job, one GPU).
 
-Beside it: the same solve in plain FP64 (FP64 storage and arithmetic, one source at a time),
-the stencil alone in GB/s, the roofline of the dominant kernel measured with HIP events over
-the timed region, and the CPU oracle timed on a bounded sample of the same workload.
+Beside it: the same solve in plain FP64 (FP64 storage and arithmetic, one source at a time)
+and FP64 batched (all sources in one call), the stencil alone in GB/s, the roofline of the
+dominant kernel measured with HIP events over the timed region, and the CPU oracle timed on a
+bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--workload l32t64] [--prec f16] [--no-cpu]
+
+Studies (each prints its own JSON line): --serve (continuous batching under Poisson load),
+--mixed (three lattices in one batch), --stencil-only, --fill (outer-product fill against the
+Gram route), --dilution, --noise-study, --point-study, --ensemble N, --solver cgnr.
 """
 import argparse
 import collections
