@@ -137,6 +137,11 @@ int a2a_set_option(a2a_ctx *ctx, const char *key, double value);
  * (same-size requests take them without hipMalloc) and are released whenever an allocation
  * would otherwise not fit the budget or the device; they are not counted here. */
 size_t a2a_mem_in_use(const a2a_ctx *ctx);
+/* Return the freed buffers kept for reuse to the device (hipFree, which waits for the device);
+ * *released (may be NULL) receives their bytes.  a2a_unload and a2a_engine_destroy do this
+ * too; solve calls keep the buffers, so that the next call of the same shape allocates
+ * nothing. */
+int a2a_trim(a2a_ctx *ctx, size_t *released);
 
 /* ---- resident fields (Sec. 7 "inversions in the background of the gauge field") ------ */
 /* Upload a gauge field (canonical layout) and convert it to the even-odd device layout in

@@ -57,6 +57,7 @@ _SIG = {
     "a2a_last_error": (ctypes.c_char_p, [P]),
     "a2a_set_option": (I, [P, ctypes.c_char_p, D]),
     "a2a_mem_in_use": (SZ, [P]),
+    "a2a_trim": (I, [P, ctypes.POINTER(SZ)]),
     "a2a_load_gauge": (I, [P, ctypes.POINTER(Geom), P, ctypes.POINTER(I)]),
     "a2a_load_gauge_dev": (I, [P, ctypes.POINTER(Geom), P, ctypes.POINTER(I)]),
     "a2a_load_clover": (I, [P, I, D, ctypes.POINTER(I)]),
@@ -217,6 +218,12 @@ class Context:
 
     def mem_in_use(self):
         return int(lib().a2a_mem_in_use(self._c))
+
+    def trim(self):
+        """Return cached device buffers to the device; returns their bytes."""
+        n = SZ()
+        self._chk(lib().a2a_trim(self._c, ctypes.byref(n)))
+        return int(n.value)
 
     # ---- fields
     def load_gauge(self, links, t_bc):

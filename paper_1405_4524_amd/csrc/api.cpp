@@ -617,6 +617,7 @@ extern "C" int a2a_unload(a2a_ctx* h, int handle) {
   if (auto* cf = c->clover(handle)) {
     free_clover(c, cf);
     c->clovers.erase(handle);
+    c->release_cache();  // unloading says the memory is wanted back
     return A2A_OK;
   }
   if (auto* gf = c->gauge(handle)) {
@@ -634,6 +635,7 @@ extern "C" int a2a_unload(a2a_ctx* h, int handle) {
         c->dfree(gf->HL[q][p]);
       }
     c->gauges.erase(handle);
+    c->release_cache();
     return A2A_OK;
   }
   return c->fail(A2A_EHANDLE, "unknown handle");
@@ -1545,5 +1547,16 @@ extern "C" int a2a_engine_destroy(a2a_engine* e) {
     if (kv.second->state == 1) engine_release(e, kv.second.get());
   for (auto& s : e->solvers) s.reset();
   delete e;
+  c->release_cache();
+  return A2A_OK;
+}
+
+extern "C" int a2a_trim(a2a_ctx* h, size_t* released) {
+  if (!h) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  const size_t n = c->cached;
+  c->release_cache();
+  if (released) *released = n;
   return A2A_OK;
 }

@@ -261,3 +261,20 @@ def test_no_result_depends_on_unwritten_memory(orc, fields, prec):
             c2.finalize()
     for k, (a, b) in enumerate(zip(*res)):
         assert np.array_equal(a, b), k
+
+
+def test_trim_returns_cached_buffers(ctx, orc, fields):
+    """a2a_trim hands the freed buffers kept for reuse back to the device: after a solve it
+    releases some bytes, right after that none, live memory is untouched, and the next solve
+    (on fresh buffers) gives bitwise the same solutions."""
+    print("[gpu] trim", flush=True)
+    f = fields[0]
+    eta = inputs.z2_noise(f["dims"], 6, seed=430)
+    X0, _, rc = ctx.solve_propagators(f["c"], eta, 0.124, 1.5, tol=1e-10, prec=2)
+    assert rc == 0
+    live = ctx.mem_in_use()
+    assert ctx.trim() > 0
+    assert ctx.trim() == 0
+    assert ctx.mem_in_use() == live
+    X1, _, rc = ctx.solve_propagators(f["c"], eta, 0.124, 1.5, tol=1e-10, prec=2)
+    assert rc == 0 and np.array_equal(X0, X1)
