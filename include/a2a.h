@@ -183,7 +183,10 @@ int a2a_autotune(a2a_ctx *ctx, int clover_h, double kappa, int prec, int nrhs, i
  * ||eta - D X||_2 <= tol ||eta||_2 for every source.  c_sw must equal the clover handle's.
  * x0_or_null: optional initial guess (resume); info: nrhs records (may be NULL).
  * A zero source gives X = 0, converged, residual 0.  Returns A2A_ENOTCONV if some source
- * did not converge within max_iter (solutions hold the best iterates).  Requests of more than
+ * did not converge within max_iter (solutions hold the best iterates).  A non-finite value in
+ * the sources: the host-pointer call rejects the call before any work (A2A_ENAN); the
+ * device-pointer call fails that source only (info converged = 0), solves the others and
+ * returns A2A_ENAN.  Requests of more than
  * 2048 sources run as consecutive batches of 2048 (the return code is the worst batch's). */
 int a2a_solve_propagators(a2a_ctx *ctx, int clover_h, const double *sources_host, int nrhs, double kappa,
                           double c_sw, double tol, int prec, int max_iter, const double *x0_or_null,

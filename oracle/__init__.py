@@ -161,6 +161,8 @@ def apply_D(U, A, kappa, psi, tbc):
     U = _c(U)
     A = _c(A)
     psi = _c(psi)
+    if psi.shape != U.shape[:4] + (4, 3) or A.shape != U.shape[:4] + (12, 12):
+        raise ValueError(f"apply_D: spinor {psi.shape} / clover {A.shape} do not match links {U.shape}")
     out = np.empty_like(psi)
     _check(lib().orc_apply_D(_p(_dims(U)), int(tbc), _p(U), _p(A), float(kappa), _p(psi), _p(out)), "apply_D")
     return out

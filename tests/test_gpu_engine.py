@@ -278,3 +278,58 @@ def test_trim_returns_cached_buffers(ctx, orc, fields):
     assert ctx.mem_in_use() == live
     X1, _, rc = ctx.solve_propagators(f["c"], eta, 0.124, 1.5, tol=1e-10, prec=2)
     assert rc == 0 and np.array_equal(X0, X1)
+
+
+def test_failures_do_not_affect_co_scheduled_work(ctx, orc, fields):
+    """A request with a non-finite source fails with A2A_ENAN and one whose max_iter is too small
+    with A2A_ENOTCONV, while the requests that share the engine with them (the same lattice and
+    another one, two precisions) converge to their solutions alone; in one solve call the good
+    sources of a batch that holds a non-finite source still converge."""
+    import torch
+
+    from paper_1405_4524_amd import a2a
+
+    print("[gpu] failure isolation", flush=True)
+    f0, f1 = fields
+    eta0 = inputs.z2_noise(f0["dims"], 8, seed=440)
+    eta1 = inputs.z2_noise(f1["dims"], 5, seed=441)
+    bad = eta0[:3].copy()
+    bad[1, 0, 0, 0, 0, 0, 0] = np.nan
+    eng = ctx.engine_create('{"max_slots": 64}')
+    jobs = [("good0", f0, eta0, 2, 20000), ("nan", f0, bad, 2, 20000), ("good1", f1, eta1, 1, 20000),
+            ("short", f0, eta0[:2], 2, 3)]
+    subs = {}
+    for name, f, eta, prec, maxit in jobs:
+        src = torch.from_numpy(eta).cuda()
+        sol = torch.zeros_like(src)
+        subs[name] = (eng.submit(f["c"], 0.124, src, len(eta), 1e-10, prec, maxit, sol), len(eta), src, sol)
+    for _ in range(3000):
+        eng.step(4)
+        if all(eng.poll(t, n)[0] != 0 for t, n, _, _ in subs.values()):
+            break
+    res = {k: eng.poll(t, n) for k, (t, n, _, _) in subs.items()}
+    assert res["nan"][0] == -1 and res["nan"][2] == a2a.ENAN
+    assert res["short"][0] == -1 and res["short"][2] == a2a.ENOTCONV
+    for name, f, eta, prec in (("good0", f0, eta0, 2), ("good1", f1, eta1, 1)):
+        done, info, rc = res[name]
+        assert done == 1 and rc == 0 and all(x["converged"] == 1 for x in info), name
+        X = subs[name][3].cpu().numpy()
+        Xa, _, rc = ctx.solve_propagators(f["c"], eta, 0.124, 1.5, tol=1e-10, prec=prec)
+        assert rc == 0 and rel(X, Xa) < 1e-8, name
+    eng.destroy()
+    mixed = np.stack([eta0[0], bad[1], eta0[2]])
+    # the host-pointer call validates its input first and rejects it whole
+    with pytest.raises(a2a.A2AError) as e:
+        ctx.solve_propagators(f0["c"], mixed, 0.124, 1.5, tol=1e-10, prec=2)
+    assert e.value.code == a2a.ENAN
+    # the device-pointer call fails the non-finite source only
+    src = torch.from_numpy(mixed).cuda()
+    sol = torch.zeros_like(src)
+    info, rc = ctx.solve_propagators_dev(f0["c"], src, sol, 3, 0.124, 1.5, tol=1e-10, prec=2, allow=(a2a.ENAN,))
+    assert rc == a2a.ENAN
+    assert info[0]["converged"] == 1 and info[2]["converged"] == 1 and info[1]["converged"] == 0
+    X = sol.cpu().numpy()  # a complex tensor: from_numpy keeps the complex dtype
+    A = orc.clover(f0["U"], 0.124, 1.5)
+    for i in (0, 2):
+        r = mixed[i] - orc.apply_D(f0["U"], A, 0.124, X[i], -1)
+        assert np.linalg.norm(r) / np.linalg.norm(mixed[i]) <= 1e-10
