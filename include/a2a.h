@@ -279,7 +279,8 @@ int a2a_point_sources_dev(a2a_ctx *ctx, const a2a_geom *geom, int t0, const int 
  * Evaluated from timeslice Gram matrices of the inputs (FP64, no propagator is stored; work
  * ~ 8 T 12 X Y Z (n1 n2 + 12 (n1 + n2)) flop).  All arrays are canonical device spinors;
  * diagrams (complex [4][T]) and pieces (complex [3][T], or NULL) are host arrays.  Temporary
- * device memory ~ 16 T n1 n2 x (2 + a chunk factor) bytes. */
+ * device memory ~ 16 T n1 n2 x (2 + a chunk factor) bytes.  A2A_EINVAL for n1 or n2 < 1 or t0
+ * outside [0, T); A2A_ENOMEM when the temporaries do not fit the budget. */
 int a2a_contract_pipi_mixed_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *point_sol_dev, int t0,
                                 const double *src1_dev, const double *sol1_dev, int n1, const double *src2_dev,
                                 const double *sol2_dev, int n2, double *diagrams_host, double *pieces_host);
