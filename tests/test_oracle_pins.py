@@ -300,3 +300,46 @@ def test_site_inverse(orc):
     Ainv = orc.invert_sites(A)
     assert np.max(np.abs(Ainv @ A - np.eye(12))) < 1e-14
     assert np.max(np.abs(Ainv - np.linalg.inv(A))) < 1e-14
+
+
+def test_solvers_match_dense_lu_on_the_small_workload(orc):
+    """The small workload's lattice (4^3x8, N = 6144): BiCGStab and CGNR solutions of the
+    workload's field and sources against a dense LAPACK solve of the assembled operator."""
+    w = inputs.WORKLOADS["tiny_4c8"]
+    dims, tbc, kappa, csw = w["dims"], w["tbc"], w["kappa"], w["csw"]
+    U = inputs.gauge_field(dims, w["eps"], w["gauge_seed"])
+    A = orc.clover(U, kappa, csw)
+    D = dense_operator(lambda v: orc.apply_D(U, A, kappa, v, tbc), dims)
+    eta = inputs.z2_noise(dims, w["nsrc"], w["noise_seed"])
+    n = eta.shape[0]
+    Xlu = np.linalg.solve(D, eta.reshape(n, -1).T).T.reshape(eta.shape)
+    del D
+    Xb, ib = orc.solve(U, A, kappa, eta, tbc, tol=1e-13)
+    Xc, ic = orc.solve_cgnr(U, A, kappa, eta, tbc, tol=1e-13)
+    assert np.all(ib[:, 2] == 1) and np.all(ic[:, 2] == 1)
+    for i in range(n):
+        nrm = np.linalg.norm(Xlu[i])
+        assert np.linalg.norm(Xb[i] - Xlu[i]) / nrm < 1e-12, i
+        assert np.linalg.norm(Xc[i] - Xlu[i]) / nrm < 1e-12, i
+
+
+def test_bicgstab_fixed_matches_library_bicgstab(orc):
+    """The fixed-iteration BiCGStab (the loop the CPU baseline times) after k = 1..6
+    iterations from zero equals scipy's BiCGStab (van der Vorst 1992, shadow vector r0,
+    no restarts) on the dense operator of 2^4 after the same number of iterations, and its
+    residual history is the true residual ||b - D x_k|| / ||b|| of those iterates."""
+    import scipy.sparse.linalg as spla
+
+    dims, tbc = (2, 2, 2, 2), -1
+    U = inputs.gauge_field(dims, 0.5, seed=61)
+    kappa = 0.13
+    A = orc.clover(U, kappa, 1.5)
+    D = dense_operator(lambda v: orc.apply_D(U, A, kappa, v, tbc), dims)
+    b = inputs.z2_noise(dims, 1, seed=62)[0]
+    bf = b.ravel()
+    for k in range(1, 7):
+        xs, info = spla.bicgstab(D, bf, rtol=0.0, atol=0.0, maxiter=k)
+        assert info == k  # ran all k iterations (no early exit)
+        x, hist = orc.bicgstab_fixed(U, A, kappa, b, tbc, k)
+        assert np.linalg.norm(x.ravel() - xs) / np.linalg.norm(xs) < 1e-12, k
+        assert abs(hist[-1] - np.linalg.norm(bf - D @ xs) / np.linalg.norm(bf)) < 1e-12, k
