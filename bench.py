@@ -66,8 +66,8 @@ def log(msg):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="l32t64")
     ap.add_argument("--prec", default="f16", choices=list(PREC))
     ap.add_argument("--rhs-block", type=int, default=2)
@@ -111,6 +111,12 @@ def main():
     ap.add_argument("--ensemble", type=int, default=0,
                     help="pi-pi diagrams with vacuum subtraction over this many synthetic 8^3x16 configurations")
     ap.add_argument("--fill-sources", default="16,64,256,1024")
+    ap.add_argument("--cpu-study", action="store_true",
+                    help="the CPU oracle alone: FP64 hop GB/s at three shapes and full solves, all cores and one")
+    ap.add_argument("--cpu-study-sources", type=int, default=4, help="16^3x32 sources solved on all cores")
+    ap.add_argument("--serve-leg", default="5,20",
+                    help="offered rates of the short serving leg of the default run ('' to skip)")
+    ap.add_argument("--serve-leg-requests", type=int, default=40)
     ap.add_argument("--point-study", action="store_true",
                     help="pi-pi diagrams from point and stochastic propagators (4^3x8) against the exact "
                          "diagrams from full dilution, one noise set against two")
@@ -120,13 +126,17 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
+    if args.cpu_study:
+        cpu_study(args)
+        return
+
     import numpy as np
     import torch
 
     from paper_1405_4524_amd import a2a, inputs
 
     if args.serve or args.mixed:
-        serve_or_mixed(args)
+        print(json.dumps(serve_or_mixed(args)), flush=True)
         return
     if args.fill:
         fill_study(args)
@@ -174,31 +184,45 @@ def main():
         return
 
     infos = []
+    phases = ("load_gauge", "load_clover", "solve", "contract", "unload")
 
     def step():
+        """One pass of the whole path; returns the host wall time of each phase (every call
+        below returns only after its device work is done, so the phases add up to the step)."""
+        ph = {}
+        t = time.perf_counter()
         g = ctx.load_gauge_dev(links, dims, tbc)
+        ph["load_gauge"], t = time.perf_counter() - t, time.perf_counter()
         c = ctx.load_clover(g, csw)
+        ph["load_clover"], t = time.perf_counter() - t, time.perf_counter()
         info, rc = ctx.solve_propagators_dev(c, src, sol, nsrc, kappa, csw, tol=tol, prec=prec, allow=())
+        ph["solve"], t = time.perf_counter() - t, time.perf_counter()
         if nsrc % 4 == 0 and nsrc <= 128:  # one pass over (eta, X): pi-pi pieces and the pion
             diag, vac, corr = ctx.contract_pipi_2pt_dev(src, sol, nsrc, dims, tbc, want_pion=True)
         else:
             corr, _ = ctx.contract_pion_2pt_dev(src, sol, nsrc, dims, tbc)
             diag = None
-        ctx.unload(g)
+        ph["contract"], t = time.perf_counter() - t, time.perf_counter()
+        ctx.unload(g)  # the fields' buffers go to the context's reuse cache
+        ph["unload"] = time.perf_counter() - t
         infos.append(info)
-        return corr, diag
+        return ph
 
+    warm_s = []
     for i in range(args.warmup):
-        t = time.time()
-        step()
-        log(f"warmup step {i} {time.time() - t:.2f}s")
+        ph = step()
+        warm_s.append(sum(ph.values()))
+        log(f"warmup step {i} {warm_s[-1]:.3f}s")
+    # HIP events around every stencil and vector launch of the solves, on the context stream
     ctx.set_option("kernel_timing", 1)
     ctx.kernel_stats("schur2", reset=True)
     torch.cuda.synchronize()
+    step_ph = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        corr, diag = step()
-        log(f"timed step {i} done")
+        ph = step()
+        step_ph.append(ph)
+        log(f"timed step {i}: {sum(ph.values()):.3f}s (" + ", ".join(f"{k} {ph[k]:.3f}" for k in phases) + ")")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.set_option("kernel_timing", 0)
@@ -207,11 +231,15 @@ def main():
         copy_1gib(1)
     value = nsrc * args.steps / elapsed
     kstats = {k: ctx.kernel_stats(k) for k in ("schur1", "schur2", "xr", "p", "s")}
-    last = infos[-1]
+    timed = infos[args.warmup:]
+    last = timed[-1]
     iters = [x["iters"] for x in last]
-    resid = [x["true_rel_residual"] for x in last]
+    resid = [x["true_rel_residual"] for inf in timed for x in inf]
     rus = [x["reliable_updates"] for x in last]
-    log(f"{value:.2f} RHS/s; iters {min(iters)}-{max(iters)}; max residual {max(resid):.2e}")
+    all_conv = all(x["converged"] for inf in timed for x in inf)
+    step_s = [sum(ph.values()) for ph in step_ph]
+    log(f"{value:.2f} RHS/s; step median {1e3 * float(np.median(step_s)):.1f} ms, max {1e3 * max(step_s):.1f} ms; "
+        f"iters {min(iters)}-{max(iters)}; max residual {max(resid):.2e}")
 
     # dominant kernel of the timed region
     dom = max(kstats, key=lambda k: kstats[k][1])
@@ -256,7 +284,12 @@ def main():
                       ("lane-interleaved groups, per-thread stencil" if args.interleave and prec in (2, 3)
                        else "per-slot")},
            "solve": {"iters_min": min(iters), "iters_max": max(iters), "reliable_updates_max": max(rus),
-                     "max_true_rel_residual": max(resid), "all_converged": all(x["converged"] for x in last)},
+                     "max_true_rel_residual": max(resid), "all_converged": all_conv},
+           "step_ms": {"median": round(1e3 * float(np.median(step_s)), 1), "min": round(1e3 * min(step_s), 1),
+                       "max": round(1e3 * max(step_s), 1),
+                       "warmup_median_untimed_kernels": round(1e3 * float(np.median(warm_s)), 1) if warm_s else None,
+                       "phases_median": {k: round(1e3 * float(np.median([ph[k] for ph in step_ph])), 1)
+                                         for k in phases}},
            "roofline": roofline, "kernels": kernels}
 
     if not args.no_extras:
@@ -313,7 +346,21 @@ def main():
     del src, sol
     torch.cuda.empty_cache()
 
+    if args.serve_leg and not args.no_extras:
+        # a short serving leg: Poisson request streams on three resident lattices (engine)
+        import copy
+
+        sa = copy.copy(args)
+        sa.serve, sa.mixed = True, False
+        sa.serve_rates, sa.serve_requests = args.serve_leg, args.serve_leg_requests
+        sv = serve_or_mixed(sa)
+        out["serving"] = {"rates": sv["rates"], "iters_per_step": sv["iters_per_step"], "cap_rhs": sv["cap_rhs"],
+                          "precision": sv["precision"],
+                          "requests": "lattice uniform over 8^3x16 / 16^3x32 / 24^3x48, kappa ~ U[0.120, 0.130], "
+                                      "1-64 sources, tol 1e-10"}
+        torch.cuda.empty_cache()
     if not args.no_cpu:
+        del links
         out["cpu_baseline"] = cpu_baseline(w, links_np)
     print(json.dumps(out), flush=True)
 
@@ -796,7 +843,7 @@ def serve_or_mixed(args):
         eng.destroy()
         out["rates"] = results
     ctx.finalize()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def stencil_only(args, ctx, links, dims, tbc, kappa, csw, V):
@@ -852,44 +899,101 @@ def copy_1gib(reps):
     return ms
 
 
-ORACLE_ITERS = 12  # full-lattice oracle iterations timed for the CPU baseline
+def host_info():
+    """CPU model, the cores this process may run on, and the oracle's OpenMP threads."""
+    import oracle
+
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "affinity_cores": len(os.sched_getaffinity(0)), "omp_threads": oracle.num_threads()}
 
 
 def cpu_baseline(w, links_np):
-    """The FP64 CPU oracle on a bounded sample of the same workload (10-15 s of CPU work):
-    ORACLE_ITERS BiCGStab iterations of its plain full-lattice solver on one source at the full
-    lattice (time per iteration), times the iteration count its solver needs at the same kappa,
-    c_sw and field recipe on an 8^3x16 lattice (solved to 1e-10); gives RHS/s."""
+    """The FP64 CPU oracle on a bounded sample of the same workload: one full solve (source 0 of
+    the workload's noise set, the oracle's BiCGStab on the un-preconditioned system with
+    true-residual restarts) to the workload's tolerance, on all of the host's cores; RHS/s is
+    one over its wall time (the clover build is timed separately and not counted)."""
+    import oracle
+    from paper_1405_4524_amd import inputs
+
+    dims, tbc, kappa, csw = w["dims"], w["tbc"], w["kappa"], w["csw"]
+    hi = host_info()
+    t = time.perf_counter()
+    A = oracle.clover(links_np, kappa, csw)
+    t_clover = time.perf_counter() - t
+    eta = inputs.z2_noise(dims, 1, w["noise_seed"])[0]
+    t = time.perf_counter()
+    _, info = oracle.solve(links_np, A, kappa, eta, tbc, tol=w["tol"])
+    t_solve = time.perf_counter() - t
+    iters, res = int(info[0, 0]), float(info[0, 3])
+    del A
+    log(f"oracle: clover {t_clover:.1f}s; one full solve {t_solve:.1f}s ({iters} iterations, residual {res:.2e}) "
+        f"on {hi['omp_threads']} threads of {hi['cpu_model']}")
+    X, Y, Z, T = dims
+    return {"value": 1.0 / t_solve, "unit": "RHS/s", "cores": hi["omp_threads"], "kind": "oracle",
+            "sample": f"source 0 of the {w['nsrc']} sources of {X}^3x{T} (a 1-of-{w['nsrc']} subset), solved by the "
+                      f"oracle to ||eta - D X|| <= {w['tol']:g} ||eta|| ({iters} BiCGStab iterations on the full "
+                      f"system, true residual {res:.2e}); clover build {t_clover:.1f} s not counted",
+            "solve_s": round(t_solve, 2), "iters": iters, "secs_per_iter": round(t_solve / max(1, iters), 3),
+            **hi}
+
+
+def cpu_study(args):
+    """The oracle on the host cores (no GPU): the FP64 hopping term in GB/s at the 16^3x32,
+    24^3x48 and 32^3x64 shapes, and full solves of the small workloads, on all cores and on one.
+    Hop bytes are the compulsory ones of the full-lattice operator: V x (4 links + spinor in +
+    spinor out) = 960 B per site."""
     import numpy as np
 
     import oracle
     from paper_1405_4524_amd import inputs
 
-    dims, tbc, kappa, csw = w["dims"], w["tbc"], w["kappa"], w["csw"]
-    t = time.time()
-    A = oracle.clover(links_np, kappa, csw)
-    t_clover = time.time() - t
-    eta = inputs.z2_noise(dims, 1, w["noise_seed"])[0]
-    t = time.time()
-    _, hist = oracle.bicgstab_fixed(links_np, A, kappa, eta, tbc, ORACLE_ITERS)
-    t_iter = (time.time() - t) / ORACLE_ITERS
-    del A
-    log(f"oracle: clover {t_clover:.1f}s, {t_iter:.2f}s per full-lattice BiCGStab iteration")
-    small = (8, 8, 8, 16)
-    Us = inputs.gauge_field(small, w["eps"], w["gauge_seed"])
-    As = oracle.clover(Us, kappa, csw)
-    es = inputs.z2_noise(small, 1, w["noise_seed"])
-    t = time.time()
-    _, info = oracle.solve(Us, As, kappa, es, tbc, tol=w["tol"])
-    t_small = time.time() - t
-    iters = int(info[0, 0])
-    rate = 1.0 / (iters * t_iter)
-    log(f"oracle: {iters} iterations at 8^3x16 ({t_small:.1f}s); {rate:.5f} RHS/s estimated at full size")
-    return {"value": rate, "unit": "RHS/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{ORACLE_ITERS} full-lattice BiCGStab iterations on 1 source ({t_iter:.2f} s/iter) x {iters} "
-                      f"iterations needed by the same oracle solver at 8^3x16 with the same kappa, c_sw, "
-                      f"field recipe and tol; clover build {t_clover:.1f} s not counted",
-            "secs_per_iter": t_iter, "iters_8c16": iters}
+    hi = host_info()
+    nthreads = hi["omp_threads"]
+    out = {"mode": "cpu_study", **hi, "hop": [], "solves": []}
+    for name in ("l16t32", "l24t48", "l32t64"):
+        w = inputs.WORKLOADS[name]
+        U = inputs.gauge_field(w["dims"], w["eps"], w["gauge_seed"])
+        psi = inputs.z2_noise(w["dims"], 1, w["noise_seed"])[0]
+        V = inputs.volume(w["dims"])
+        for th in (nthreads, 1):
+            oracle.set_num_threads(th)
+            oracle.hop(U, psi, w["tbc"])
+            reps = 3 if th > 1 else 1
+            t = time.perf_counter()
+            for _ in range(reps):
+                oracle.hop(U, psi, w["tbc"])
+            dt = (time.perf_counter() - t) / reps
+            row = {"workload": name, "threads": th, "s": round(dt, 4), "GBps": round(V * 960 / dt / 1e9, 2)}
+            out["hop"].append(row)
+            log(f"cpu hop {row}")
+        del U, psi
+    oracle.set_num_threads(nthreads)
+    for name, n_all, n_one in (("tiny_4c8", 4, 4), ("l16t32", args.cpu_study_sources, 1)):
+        w = inputs.WORKLOADS[name]
+        U = inputs.gauge_field(w["dims"], w["eps"], w["gauge_seed"])
+        A = oracle.clover(U, w["kappa"], w["csw"])
+        for th, n in ((nthreads, n_all), (1, n_one)):
+            oracle.set_num_threads(th)
+            eta = inputs.z2_noise(w["dims"], n, w["noise_seed"])
+            t = time.perf_counter()
+            _, info = oracle.solve(U, A, w["kappa"], eta, w["tbc"], tol=w["tol"])
+            dt = time.perf_counter() - t
+            row = {"workload": name, "threads": th, "sources": n, "of": w["nsrc"], "s": round(dt, 3),
+                   "rhs_per_s": round(n / dt, 5), "iters": [int(x) for x in info[:, 0]],
+                   "max_residual": float(info[:, 3].max())}
+            out["solves"].append(row)
+            log(f"cpu solve {row}")
+        del U, A
+    oracle.set_num_threads(nthreads)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -130,7 +130,10 @@ const char *a2a_last_error(const a2a_ctx *ctx);
  * a test hook that makes every BiCGStab source of a solve call report a breakdown at its first
  * reliable update, so that the fallback runs), "poison_memory" (0/1, default 0: a test hook that
  * fills every device buffer the context allocates or reuses with 0xFF bytes, NaN in every
- * floating format, so that a read of memory not written first shows in the results).
+ * floating format, so that a read of memory not written first shows in the results),
+ * "fail_setup_enomem" / "fail_setup_device" (n >= 0, default 0: test hooks that make the next
+ * n source preparations of solve calls and engine admissions fail with A2A_ENOMEM /
+ * A2A_EDEVICE, so that the clean-up of a failed admission can be checked).
  * Returns A2A_EINVAL for an unknown key. */
 int a2a_set_option(a2a_ctx *ctx, const char *key, double value);
 /* Bytes of device memory in the context's live buffers.  Freed buffers are kept for reuse
@@ -138,9 +141,9 @@ int a2a_set_option(a2a_ctx *ctx, const char *key, double value);
  * would otherwise not fit the budget or the device; they are not counted here. */
 size_t a2a_mem_in_use(const a2a_ctx *ctx);
 /* Return the freed buffers kept for reuse to the device (hipFree, which waits for the device);
- * *released (may be NULL) receives their bytes.  a2a_unload and a2a_engine_destroy do this
- * too; solve calls keep the buffers, so that the next call of the same shape allocates
- * nothing. */
+ * *released (may be NULL) receives their bytes.  a2a_engine_destroy and a2a_finalize do
+ * this too; solve calls and a2a_unload keep the buffers, so that the next call of the same
+ * shape (a solve, or the fields of the next gauge configuration) allocates nothing. */
 int a2a_trim(a2a_ctx *ctx, size_t *released);
 
 /* ---- resident fields (Sec. 7 "inversions in the background of the gauge field") ------ */
@@ -151,7 +154,9 @@ int a2a_load_gauge_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *links_d
 /* Build the kappa-independent clover field for c_sw (Sec. 8, c_SW) on a gauge handle.
  * A(kappa) and A^{-1}(kappa) are made and cached on first use of each kappa. */
 int a2a_load_clover(a2a_ctx *ctx, int gauge_h, double c_sw, int *clover_h);
-/* Free a gauge or clover handle (a gauge handle also frees its clover handles). */
+/* Free a gauge or clover handle (a gauge handle also frees its clover handles).  The
+ * buffers go to the context's reuse cache (see a2a_trim), not back to the device: a loop over
+ * configurations that loads, solves and unloads allocates nothing after its first pass. */
 int a2a_unload(a2a_ctx *ctx, int handle);
 
 /* ---- operator application (parity tests and the stencil benchmark) -------------------- */

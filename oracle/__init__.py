@@ -74,6 +74,7 @@ def lib():
             "orc_pipi_from_O": [I, I, P, I, P, P],
             "orc_contract_pipi": [P, I, P, P, P, P],
             "orc_num_threads": [],
+            "orc_set_num_threads": [I],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -106,6 +107,11 @@ def _check(rc, what):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of the oracle's OpenMP loops from now on (for single-core timings)."""
+    _check(lib().orc_set_num_threads(int(n)), "set_num_threads")
 
 
 def gamma(mu):

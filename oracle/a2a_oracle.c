@@ -909,3 +909,13 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the OpenMP loops that follow (n >= 1); for timing the oracle on one core. */
+int orc_set_num_threads(int n)
+{
+    if (n < 1) return -1;
+#ifdef _OPENMP
+    omp_set_num_threads(n);
+#endif
+    return 0;
+}

@@ -512,6 +512,12 @@ extern "C" int a2a_set_option(a2a_ctx* h, const char* key, double v) {
     c->force_breakdown = v != 0;
   } else if (k == "poison_memory") {
     c->poison = v != 0;
+  } else if (k == "fail_setup_enomem") {
+    if (v < 0) return c->fail(A2A_EINVAL, "fail_setup_enomem must be >= 0");
+    c->fail_setup_enomem = (int)v;
+  } else if (k == "fail_setup_device") {
+    if (v < 0) return c->fail(A2A_EINVAL, "fail_setup_device must be >= 0");
+    c->fail_setup_device = (int)v;
   } else if (k == "hbm_budget") {
     if (!(v > 0)) return c->fail(A2A_EINVAL, "hbm_budget must be positive");
     c->budget = (size_t)v;
@@ -617,7 +623,6 @@ extern "C" int a2a_unload(a2a_ctx* h, int handle) {
   if (auto* cf = c->clover(handle)) {
     free_clover(c, cf);
     c->clovers.erase(handle);
-    c->release_cache();  // unloading says the memory is wanted back
     return A2A_OK;
   }
   if (auto* gf = c->gauge(handle)) {
@@ -635,7 +640,6 @@ extern "C" int a2a_unload(a2a_ctx* h, int handle) {
         c->dfree(gf->HL[q][p]);
       }
     c->gauges.erase(handle);
-    c->release_cache();
     return A2A_OK;
   }
   return c->fail(A2A_EHANDLE, "unknown handle");
@@ -1446,16 +1450,31 @@ static int engine_admit(a2a_engine* e, Request* r) {
     sv->add_slot(&s);
   }
   rc = sv->setup(idx);
-  if (rc) return rc;
   std::vector<int> early;
-  for (int i : idx)
-    if (sv->live[i]->state == SS_RUN && sv->live[i]->last_r64 <= sv->live[i]->target) early.push_back(i);
-  if (!early.empty()) {
+  if (!rc)
+    for (int i : idx)
+      if (sv->live[i]->state == SS_RUN && sv->live[i]->last_r64 <= sv->live[i]->target) early.push_back(i);
+  if (!rc && !early.empty()) {
     rc = sv->finalize(early);
-    for (int i : early) sv->live[i]->state = sv->live[i]->info.converged ? SS_DONE : SS_RUN;
+    if (!rc)
+      for (int i : early) sv->live[i]->state = sv->live[i]->info.converged ? SS_DONE : SS_RUN;
+  }
+  if (rc) {
+    // undo the admission: the request's slots leave the solver's tables and give back their
+    // arenas and ids, so that a retry (ENOMEM) starts from scratch and a failed request holds
+    // neither slot capacity nor memory
+    (void)c->sync();
+    Slot* first = r->slots.data();
+    Slot* last = first + r->slots.size();
+    auto& lv = sv->live;
+    lv.erase(std::remove_if(lv.begin(), lv.end(), [&](Slot* s) { return s >= first && s < last; }), lv.end());
+    sv->dirty = true;
+    engine_release(e, r);
+    r->slots.clear();
+    return rc;
   }
   r->state = 1;
-  return rc;
+  return A2A_OK;
 }
 
 extern "C" int a2a_engine_step(a2a_engine* e, int iters, int* active) {

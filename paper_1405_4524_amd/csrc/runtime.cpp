@@ -941,6 +941,14 @@ int Solver::true_residual(const std::vector<int>& idx) {
 // r64 = b - M x64, inner state.  Marks zero / non-finite sources.
 int Solver::setup(const std::vector<int>& idx) {
   if (idx.empty()) return A2A_OK;
+  if (ctx->fail_setup_enomem > 0) {
+    ctx->fail_setup_enomem--;
+    return ctx->fail(A2A_ENOMEM, "source preparation: injected out-of-memory (test hook)");
+  }
+  if (ctx->fail_setup_device > 0) {
+    ctx->fail_setup_device--;
+    return ctx->fail(A2A_EDEVICE, "source preparation: injected device error (test hook)");
+  }
   A2A_TRY(rebuild());
   std::vector<int> with_x0;
   for (int i : idx)

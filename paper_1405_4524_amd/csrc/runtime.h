@@ -210,6 +210,8 @@ struct Ctx {
   int cgnr_fallback = 1;             // BiCGStab breakdowns are finished by CGNR (solve calls)
   int force_breakdown = 0;           // test hook: BiCGStab slots break down at their first update
   bool poison = false;               // test hook: allocations are filled with 0xFF bytes (NaN)
+  int fail_setup_enomem = 0;         // test hook: the next n source preparations fail (A2A_ENOMEM)
+  int fail_setup_device = 0;         // test hook: the next n source preparations fail (A2A_EDEVICE)
   std::map<std::string, int> tuned;  // tune key -> RHS-block width
   std::string tune_path;             // A2A_TUNE_CACHE: JSON file of tuned widths
   // reduction scratch

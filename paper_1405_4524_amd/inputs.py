@@ -127,6 +127,30 @@ def z2_noise(dims, nsrc, seed, src_offset=0, out=None):
     return out
 
 
+def z2_noise_timeslices(dims, nsrc, seed, ts, src_offset=0):
+    """The components of :func:`z2_noise` on the timeslices `ts` only (same counter, so equal
+    bit for bit to those timeslices of the whole-lattice draw), shape
+    (nsrc, len(ts), Z, Y, X, 4, 3) complex128: large lattices without the whole field."""
+    X, Y, Z, T = check_dims(dims)
+    V = X * Y * Z * T
+    V3 = X * Y * Z
+    per = 12 * V
+    ts = [int(t) for t in ts]
+    out = np.empty((nsrc, len(ts), Z, Y, X, 4, 3), dtype=np.complex128)
+    base = np.uint64(int(seed) << 48)
+    idx = np.arange(12 * V3, dtype=np.uint64)
+    inv = np.sqrt(0.5)
+    for s in range(nsrc):
+        for j, t in enumerate(ts):
+            with np.errstate(over="ignore"):
+                k = np.uint64((int(src_offset) + s) * per + t * 12 * V3) + idx
+                h = splitmix64(base + k)
+            flat = out[s, j].reshape(-1)
+            flat.real = np.where((h & np.uint64(1)) != 0, -inv, inv)
+            flat.imag = np.where((h & np.uint64(2)) != 0, -inv, inv)
+    return out
+
+
 # ---------------------------------------------------------------------------------------
 # named workloads (lattice, field, operator and source parameters)
 # ---------------------------------------------------------------------------------------

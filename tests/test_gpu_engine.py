@@ -174,6 +174,72 @@ def test_engine_admission_by_budget_and_cancel(orc, fields):
         c2.finalize()
 
 
+def test_engine_failed_admission_is_undone(ctx, orc, fields):
+    """A request whose source preparation fails after its slots were allocated gives the slots,
+    their ids and their memory back.  An out-of-memory failure while another request runs leaves
+    it queued, and a later step admits it afresh; a device error fails that request alone.  The
+    requests converge to their solutions alone, the engine's active count returns to zero and
+    the context's live memory to its value before the engine was created."""
+    import torch
+
+    from paper_1405_4524_amd import a2a
+
+    print("[gpu] engine: failed admissions are undone", flush=True)
+    f = fields[0]
+    kappa = 0.127
+    sizes = (5, 7, 4)
+    etas = [inputs.z2_noise(f["dims"], n, seed=600 + k) for k, n in enumerate(sizes)]
+    alone = []
+    for eta in etas[:2]:
+        Xa, _, rc = ctx.solve_propagators(f["c"], eta, kappa, 1.5, tol=1e-10, prec=a2a.F16_F32)
+        assert rc == 0
+        alone.append(Xa)
+    # every sid the engine will hold at once was in use above: nothing context-wide grows
+    ctx.solve_propagators(f["c"], np.concatenate(etas), kappa, 1.5, tol=1e-10, prec=a2a.F16_F32)
+    mem0 = ctx.mem_in_use()
+    eng = ctx.engine_create('{"max_slots": 64}')
+    dev = []
+    for e in etas:
+        src = torch.from_numpy(e).cuda()
+        dev.append((src, torch.zeros_like(src)))
+    submit = lambda k: eng.submit(f["c"], kappa, dev[k][0], sizes[k], 1e-10, a2a.F16_F32, 20000, dev[k][1])
+    tA = submit(0)
+    assert eng.step(1) == sizes[0]
+    ctx.set_option("fail_setup_enomem", 2)  # fails the first admission and an immediate retry
+    tB = submit(1)
+    admitted = False
+    for _ in range(4):
+        act = eng.step(1)
+        assert eng.poll(tB, sizes[1])[0] != -1
+        assert act in (sizes[0], sizes[0] + sizes[1]), act
+        if act == sizes[0] + sizes[1]:
+            admitted = True
+            break
+    assert admitted
+    ctx.set_option("fail_setup_device", 1)
+    tC = submit(2)
+    act = eng.step(1)
+    done, _, rc = eng.poll(tC, sizes[2])
+    assert done == -1 and rc == a2a.EDEVICE, (done, rc)
+    assert act == sizes[0] + sizes[1]
+    for _ in range(3000):
+        act = eng.step(8)
+        if act == 0:
+            break
+    assert act == 0
+    A = orc.clover(f["U"], kappa, 1.5)
+    for k, t in enumerate((tA, tB)):
+        done, info, rc = eng.poll(t, sizes[k])
+        assert done == 1 and rc == 0, (k, done, rc)
+        X = dev[k][1].cpu().numpy()
+        for i in range(sizes[k]):
+            r = etas[k][i] - orc.apply_D(f["U"], A, kappa, X[i], -1)
+            assert np.linalg.norm(r) / np.linalg.norm(etas[k][i]) <= 1e-10
+        assert rel(X, alone[k]) < 1e-8
+    eng.destroy()
+    assert ctx.mem_in_use() == mem0
+
+
 @pytest.mark.parametrize("prec", [0, 2])
 def test_repeat_solve_on_recycled_memory_is_bitwise_identical(ctx, orc, fields, prec):
     """The context hands freed device buffers to later allocations of the same size: solves

@@ -65,3 +65,10 @@ def test_gauge_near_identity_scale():
     u0 = np.mean(np.trace(U, axis1=-2, axis2=-1).real) / 3
     # second-order estimate: 1 - eps^2 E tr H^2 / 6 = 1 - 0.35^2 * 8 / 6 = 0.837
     assert 0.80 < u0 < 0.87
+
+
+def test_noise_timeslices_equal_whole_draw():
+    dims = (4, 2, 6, 8)
+    whole = inputs.z2_noise(dims, 3, 9, src_offset=2)
+    part = inputs.z2_noise_timeslices(dims, 3, 9, [0, 5, 7], src_offset=2)
+    assert np.array_equal(whole[:, [0, 5, 7]], part)
