@@ -70,7 +70,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="l32t64")
     ap.add_argument("--prec", default="f16", choices=list(PREC))
-    ap.add_argument("--rhs-block", type=int, default=2)
+    ap.add_argument("--rhs-block", type=int, default=2, help="per-thread RHS width when not autotuned")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: tune the launch configuration (group width, brick, FP64 width) before the warmup")
     ap.add_argument("--check-every", type=int, default=4)
     ap.add_argument("--interleave", type=int, default=1,
                     help="1: FP16/BF16 inner vectors in lane-interleaved groups (matrix-core stencil)")
@@ -183,6 +185,17 @@ def main():
         stencil_only(args, ctx, links, dims, tbc, kappa, csw, V)
         return
 
+    tuned = None
+    if args.autotune:  # before the warmup, outside the timed region
+        g = ctx.load_gauge_dev(links, dims, tbc)
+        c = ctx.load_clover(g, csw)
+        t = time.perf_counter()
+        tuned = ctx.autotune(c, kappa, prec, nsrc)
+        tuned["seconds"] = round(time.perf_counter() - t, 2)
+        ctx.unload(g)
+        ctx.set_option("autotune", 1)
+        log(f"autotuned: {tuned}")
+
     infos = []
     phases = ("load_gauge", "load_clover", "solve", "contract", "unload")
 
@@ -279,7 +292,12 @@ def main():
                       "tol": tol, "links": f"exp(i {w['eps']} H), seed {w['gauge_seed']}",
                       "noise": f"complex Z2 splitmix64 seed {w['noise_seed']}",
                       "precision": f"inner {args.prec} storage / f32 arithmetic, f64 reliable updates"
-                      if prec else "f64", "rhs_block": args.rhs_block, "solver": args.solver,
+                      if prec else "f64",
+                      "rhs_block": (tuned["rhs_block"] or args.rhs_block) if tuned else args.rhs_block,
+                      "autotuned": {k: tuned[k] for k in ("il_width", "brick", "rhs_block", "rhs_block64",
+                                                          "ms_schur", "ms_schur64", "candidates", "seconds")}
+                      if tuned else None,
+                      "solver": args.solver,
                       "layout": "lane-interleaved groups, matrix-core stencil" if mfma else
                       ("lane-interleaved groups, per-thread stencil" if args.interleave and prec in (2, 3)
                        else "per-slot")},
@@ -293,6 +311,7 @@ def main():
            "roofline": roofline, "kernels": kernels}
 
     if not args.no_extras:
+        ctx.set_option("autotune", 0)  # the side measurements keep their stated widths
         # ---- plain FP64: FP64 storage and arithmetic, one source at a time
         ctx.set_option("rhs_block", 1)
         g = ctx.load_gauge_dev(links, dims, tbc)

@@ -133,7 +133,10 @@ const char *a2a_last_error(const a2a_ctx *ctx);
  * floating format, so that a read of memory not written first shows in the results),
  * "fail_setup_enomem" / "fail_setup_device" (n >= 0, default 0: test hooks that make the next
  * n source preparations of solve calls and engine admissions fail with A2A_ENOMEM /
- * A2A_EDEVICE, so that the clean-up of a failed admission can be checked).
+ * A2A_EDEVICE, so that the clean-up of a failed admission can be checked), "il_width" (16, 32
+ * or 48, default 48: RHS per lane-interleaved group), "brick" (by * 10000 + bz * 100 + bt:
+ * the stencil brick of later calls on lattices it tiles, 0 = each lattice's default; a brick
+ * orders the stencil's sweep only, results are unchanged).
  * Returns A2A_EINVAL for an unknown key. */
 int a2a_set_option(a2a_ctx *ctx, const char *key, double value);
 /* Bytes of device memory in the context's live buffers.  Freed buffers are kept for reuse
@@ -173,13 +176,34 @@ int a2a_dslash_clover_dev(a2a_ctx *ctx, int clover_h, double kappa, int op, int 
 int a2a_bench_stencil(a2a_ctx *ctx, int clover_h, double kappa, int op, int prec, int nrhs, int reps,
                       double *ms_per_apply);
 
-/* Autotune the stencil's RHS-block width (right-hand sides per thread sharing each link and
- * clover load: 1, 2 or 4) for this lattice, precision and number of sources: times the
- * Schur operator on min(nrhs, 16) fields for each width, stores the fastest in the context
- * (and in the JSON file named by the environment variable A2A_TUNE_CACHE, keyed by arch,
- * lattice, precision and RHS bucket).  ms_per_width (optional, [3]) receives the times for
- * widths 1, 2, 4 (-1 where not tried).  With option "autotune" = 1 solves tune on first use. */
-int a2a_autotune(a2a_ctx *ctx, int clover_h, double kappa, int prec, int nrhs, int *best_R, double *ms_per_width);
+/* Launch configuration chosen by the autotuner for one workload. */
+typedef struct {
+  int il_width;      /* RHS per lane-interleaved group on the matrix cores: 16, 32 or 48 (0: not used) */
+  int brick[3];      /* stencil brick extents in y, z, t (the x extent is the whole checkerboard row) */
+  int rhs_block;     /* RHS per thread of the per-thread stencil: 1, 2 or 4 (0: the context option) */
+  int rhs_block64;   /* RHS per thread of the FP64 stencils of reliable updates: 1 or 2 */
+  double ms_schur;   /* best time of the inner-precision Schur operator (both stencils), ms; -1 if cached */
+  double ms_schur64; /* best time of the FP64 Schur operator, ms; -1 if cached */
+  int candidates;    /* configurations timed (0: taken from the cache) */
+  int reserved;
+} a2a_tune_result;
+
+/* Autotune the launch configuration of the batched stencils (the multi-RHS batching of the
+ * solve) for this lattice, precision and number of sources, by a coordinate search that times
+ * the Schur operator on min(nrhs, 64) sources: first the RHS width (the lane-interleaved group
+ * width 16 / 32 / 48 for FP16 / BF16 storage on the matrix cores, else the per-thread width
+ * 1 / 2 / 4), then the stencil brick (up to six shapes that tile the lattice), then the FP64
+ * stencils' width 1 / 2 (FP64 Schur operator on min(nrhs, 24) sources).  The result is kept in
+ * the context and in the JSON file named by the environment variable A2A_TUNE_CACHE, keyed by
+ * arch, lattice, precision and RHS bucket (the next power of two, at most 64); a cached key
+ * is returned without timing.  With option "autotune" = 1 solve calls tune on first use of a
+ * key and run in the tuned configuration.  result may be NULL.  Temporary device buffers of
+ * up to min(nrhs, 64) sources are allocated (and kept in the context's buffer cache). */
+int a2a_autotune(a2a_ctx *ctx, int clover_h, double kappa, int prec, int nrhs, a2a_tune_result *result);
+/* The stencil bricks (y, z, t extents) the autotuner may choose for a lattice, in order of
+ * preference (the first is the default), as out[3 k + 0..2], at most maxn of them.  Host only;
+ * returns their number, or A2A_EINVAL for a bad geometry. */
+int a2a_brick_choices(const a2a_geom *geom, int *out, int maxn);
 
 /* ---- solves (Sec. 7: X_i = D^{-1} eta_i) --------------------------------------------- */
 /* Solve D X_i = eta_i for nrhs sources with even-odd preconditioning (odd-site Schur

@@ -39,6 +39,17 @@ class Geom(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int * 4), ("t_bc", ctypes.c_int)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("il_width", ctypes.c_int), ("brick", ctypes.c_int * 3), ("rhs_block", ctypes.c_int),
+                ("rhs_block64", ctypes.c_int), ("ms_schur", ctypes.c_double), ("ms_schur64", ctypes.c_double),
+                ("candidates", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d["brick"] = list(self.brick)
+        return d
+
+
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("converged", ctypes.c_int),
                 ("restarts", ctypes.c_int), ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
@@ -65,7 +76,8 @@ _SIG = {
     "a2a_dslash_clover": (I, [P, I, D, I, I, I, P, P, I]),
     "a2a_dslash_clover_dev": (I, [P, I, D, I, I, I, P, P, I]),
     "a2a_bench_stencil": (I, [P, I, D, I, I, I, I, ctypes.POINTER(D)]),
-    "a2a_autotune": (I, [P, I, D, I, I, ctypes.POINTER(I), P]),
+    "a2a_autotune": (I, [P, I, D, I, I, P]),
+    "a2a_brick_choices": (I, [ctypes.POINTER(Geom), P, I]),
     "a2a_solve_propagators": (I, [P, I, P, I, D, D, D, I, I, P, P, P]),
     "a2a_solve_propagators_dev": (I, [P, I, P, I, D, D, D, I, I, P, P, P]),
     "a2a_contract_pion_2pt": (I, [P, ctypes.POINTER(Geom), P, P, I, I, P, P]),
@@ -268,12 +280,21 @@ class Context:
         return ms.value
 
     def autotune(self, clover_h, kappa, prec, nrhs):
-        """(best RHS-block width, {width: ms of one Schur application})."""
-        r = I()
-        ms = (D * 3)()
-        self._chk(lib().a2a_autotune(self._c, int(clover_h), float(kappa), int(prec), int(nrhs), ctypes.byref(r),
-                                     ms))
-        return r.value, {w: ms[k] for k, w in enumerate((1, 2, 4)) if ms[k] >= 0}
+        """Tune (or look up) the launch configuration of this workload; returns it as a dict:
+        il_width, brick [by, bz, bt], rhs_block, rhs_block64, ms_schur, ms_schur64, candidates."""
+        r = TuneResult()
+        self._chk(lib().a2a_autotune(self._c, int(clover_h), float(kappa), int(prec), int(nrhs), ctypes.byref(r)))
+        return r.as_dict()
+
+    @staticmethod
+    def brick_choices(dims, t_bc=-1):
+        """The stencil bricks (by, bz, bt) the tuner may choose for a lattice, default first."""
+        g = geom(dims, t_bc)
+        out = (I * 48)()
+        n = lib().a2a_brick_choices(ctypes.byref(g), out, 16)
+        if n < 0:
+            raise A2AError(n, "bad lattice geometry")
+        return [tuple(out[3 * k:3 * k + 3]) for k in range(n)]
 
     # ---- solves
     def solve_propagators(self, clover_h, sources, kappa, csw, tol=1e-10, prec=F64, max_iter=100000, x0=None,

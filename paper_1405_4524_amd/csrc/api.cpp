@@ -14,7 +14,8 @@ struct a2a_ctx {
   Ctx c;
 };
 
-static int autotune_R(Ctx* c, int clover_h, double kappa, int prec, int nrhs, int* R, double* ms_out);
+static int autotune_cfg(Ctx* c, int clover_h, double kappa, int prec, int nrhs, TuneCfg* out,
+                        a2a_tune_result* res);
 static void tune_load(Ctx* c);
 
 namespace {
@@ -83,9 +84,9 @@ constexpr int IL_MAX = IL_LANES;
 
 bool use_interleave(const Ctx* c, int prec) { return c->interleave && (prec == 2 || prec == 3); }
 
-int il_alloc(Ctx* c, Slot* slots, int n, long hv, int nlo) {
-  for (int g0 = 0; g0 < n; g0 += IL_MAX) {
-    const int m = std::min(IL_MAX, n - g0);
+int il_alloc(Ctx* c, Slot* slots, int n, long hv, int nlo, int width) {
+  for (int g0 = 0; g0 < n; g0 += width) {
+    const int m = std::min(width, n - g0);
     const int nt = (m + 15) / 16;
     const size_t vs = ((size_t)hv * nt * 768 + 255) & ~(size_t)255;
     void* p = nullptr;
@@ -114,8 +115,11 @@ int il_alloc(Ctx* c, Slot* slots, int n, long hv, int nlo) {
 // per-thread stencil is cheaper per RHS below about 12 of 16 lanes).
 constexpr int IL_REM_MIN = 12;
 
-int slots_alloc(Ctx* c, Slot* slots, int n, int prec, long hv, int nblk, int nlo, int nhi) {
+// ilw: RHS per interleaved group (16, 32 or 48; 0 = the context's option)
+int slots_alloc(Ctx* c, Slot* slots, int n, int prec, long hv, int nblk, int nlo, int nhi, int ilw = 0) {
   const bool il = use_interleave(c, prec) && nlo > 0;
+  int width = ilw > 0 ? ilw : c->il_width;
+  if (width != 16 && width != 32) width = IL_MAX;
   int n_il = 0;
   if (il) {
     n_il = n / 16 * 16;
@@ -124,7 +128,7 @@ int slots_alloc(Ctx* c, Slot* slots, int n, int prec, long hv, int nblk, int nlo
   int rc = A2A_OK;
   int k = 0;
   for (; k < n && !rc; ++k) rc = slot_alloc(c, &slots[k], prec, hv, nblk, k < n_il ? 0 : nlo, nhi);
-  if (!rc && n_il > 0) rc = il_alloc(c, slots, n_il, hv, nlo);
+  if (!rc && n_il > 0) rc = il_alloc(c, slots, n_il, hv, nlo, width);
   if (rc)
     for (int j = 0; j < k; ++j) slot_free(c, &slots[j]);
   return rc;
@@ -208,9 +212,16 @@ static int solve_batch(Ctx* c, int clover_h, const double* src, int nrhs, double
     return c->fail(A2A_EINVAL, "c_sw does not match the clover handle");
   const long hv = gf->g.hv;
   const long long V = volume_of(gf->g);
-  int R = effective_R(c, prec);
-  if (c->autotune) A2A_TRY(autotune_R(c, clover_h, kappa, prec, nrhs, &R, nullptr));
+  TuneCfg tc{};
+  if (c->autotune) A2A_TRY(autotune_cfg(c, clover_h, kappa, prec, nrhs, &tc, nullptr));
+  const int R = tc.R ? tc.R : effective_R(c, prec);
   Solver sv(c, prec, R);
+  if (tc.R64) sv.R64 = tc.R64;
+  if (tc.by > 0) {
+    sv.by = tc.by;
+    sv.bz = tc.bz;
+    sv.bt = tc.bt;
+  }
   sv.method = c->solver;
   const int op = sv.op_index(clover_h, kappa, kop, gf);
   std::vector<Slot> slots(nrhs);
@@ -226,7 +237,7 @@ static int solve_batch(Ctx* c, int clover_h, const double* src, int nrhs, double
     s.max_iter = max_iter;
     s.t_submit = t0;
   }
-  rc = slots_alloc(c, slots.data(), nrhs, prec, hv, sv.ops[op].nblk, NVEC_LO, NVEC_HI);
+  rc = slots_alloc(c, slots.data(), nrhs, prec, hv, sv.ops[op].nblk, NVEC_LO, NVEC_HI, tc.il_width);
   if (!rc) {
     std::vector<int> idx;
     for (int i = 0; i < nrhs; ++i) {
@@ -499,6 +510,18 @@ extern "C" int a2a_set_option(a2a_ctx* h, const char* key, double v) {
     c->timing = v != 0;
   } else if (k == "autotune") {
     c->autotune = v != 0;
+  } else if (k == "il_width") {
+    if (v != 16 && v != 32 && v != 48) return c->fail(A2A_EINVAL, "il_width must be 16, 32 or 48");
+    c->il_width = (int)v;
+  } else if (k == "brick") {  // by * 10000 + bz * 100 + bt, 0 = each lattice's default
+    const long b = (long)v;
+    if (b < 0 || (double)b != v) return c->fail(A2A_EINVAL, "brick must be by * 10000 + bz * 100 + bt or 0");
+    const int by = (int)(b / 10000), bz = (int)(b / 100 % 100), bt = (int)(b % 100);
+    if (b != 0 && (by < 1 || bz < 1 || bt < 1 || by * bz * bt > BS))
+      return c->fail(A2A_EINVAL, "brick extents must be >= 1 with by bz bt <= 256");
+    c->brick_by = by;
+    c->brick_bz = bz;
+    c->brick_bt = bt;
   } else if (k == "interleave") {
     c->interleave = v != 0;
   } else if (k == "mfma") {
@@ -680,19 +703,25 @@ extern "C" int a2a_dslash_clover(a2a_ctx* h, int clover_h, double kappa, int op,
 }
 
 // mean milliseconds of one stencil application (HOP_EO, or the two launches of the Schur
-// operator) on nrhs device-layout fields with RHS-block width R, timed with HIP events
-static int stencil_time(Ctx* c, int clover_h, double kappa, int opk, int prec, int nrhs, int reps, int R,
-                        double* ms) {
+// operator) on nrhs device-layout fields in launch configuration tc (per-thread width, brick,
+// interleaved group width), timed with HIP events
+static int stencil_time(Ctx* c, int clover_h, double kappa, int opk, int prec, int nrhs, int reps,
+                        const TuneCfg& tc, double* ms) {
   GaugeField* gf;
   CloverField* cf;
   KappaOp* kop;
   A2A_TRY(resolve_op(c, clover_h, kappa, prec, &gf, &cf, &kop));
-  Solver sv(c, prec, R);
+  Solver sv(c, prec, tc.R ? tc.R : effective_R(c, prec));
+  if (tc.by > 0) {
+    sv.by = tc.by;
+    sv.bz = tc.bz;
+    sv.bt = tc.bt;
+  }
   const int op = sv.op_index(clover_h, kappa, kop, gf);
   std::vector<Slot> slots(nrhs);
   int rc = A2A_OK;
   for (int i = 0; i < nrhs; ++i) slots[i].op = op;
-  rc = slots_alloc(c, slots.data(), nrhs, prec, gf->g.hv, sv.ops[op].nblk, 5, 0);
+  rc = slots_alloc(c, slots.data(), nrhs, prec, gf->g.hv, sv.ops[op].nblk, 5, 0, tc.il_width);
   if (!rc)
     for (auto& s : slots) sv.add_slot(&s);
   if (!rc) rc = sv.rebuild();
@@ -733,10 +762,10 @@ extern "C" int a2a_bench_stencil(a2a_ctx* h, int clover_h, double kappa, int opk
   (void)hipSetDevice(c->device);
   if (check_prec(prec)) return c->fail(A2A_EINVAL, "unknown precision mode");
   if (opk != A2A_OP_HOP_EO && opk != A2A_OP_SCHUR) return c->fail(A2A_EINVAL, "op must be HOP_EO or SCHUR");
-  return stencil_time(c, clover_h, kappa, opk, prec, nrhs, reps, effective_R(c, prec), ms);
+  return stencil_time(c, clover_h, kappa, opk, prec, nrhs, reps, TuneCfg{}, ms);
 }
 
-// ---- autotuner: RHS-block width of the stencil, per (arch, lattice, precision, RHS bucket)
+// ---- autotuner: launch configuration per (arch, lattice, precision, RHS bucket)
 static std::string tune_key(const Geo& g, int prec, int nrhs) {
   int b = 1;
   while (b < nrhs && b < 64) b <<= 1;
@@ -746,16 +775,20 @@ static std::string tune_key(const Geo& g, int prec, int nrhs) {
 
 static void tune_save(Ctx* c) {
   if (c->tune_path.empty()) return;
-  FILE* f = std::fopen(c->tune_path.c_str(), "w");
+  const std::string tmp = c->tune_path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
   if (!f) return;
   std::fprintf(f, "{");
   bool first = true;
   for (auto& kv : c->tuned) {
-    std::fprintf(f, "%s\n  \"%s\": %d", first ? "" : ",", kv.first.c_str(), kv.second);
+    const TuneCfg& t = kv.second;
+    std::fprintf(f, "%s\n  \"%s\": {\"il_width\": %d, \"by\": %d, \"bz\": %d, \"bt\": %d, \"R\": %d, \"R64\": %d}",
+                 first ? "" : ",", kv.first.c_str(), t.il_width, t.by, t.bz, t.bt, t.R, t.R64);
     first = false;
   }
   std::fprintf(f, "\n}\n");
   std::fclose(f);
+  std::rename(tmp.c_str(), c->tune_path.c_str());
 }
 
 static void tune_load(Ctx* c) {
@@ -765,53 +798,148 @@ static void tune_load(Ctx* c) {
   char line[512];
   while (std::fgets(line, sizeof line, f)) {
     char key[400];
-    int r;
-    if (std::sscanf(line, " \"%399[^\"]\": %d", key, &r) == 2 && (r == 1 || r == 2 || r == 4)) c->tuned[key] = r;
+    TuneCfg t;
+    if (std::sscanf(line, " \"%399[^\"]\": {\"il_width\": %d, \"by\": %d, \"bz\": %d, \"bt\": %d, \"R\": %d, \"R64\": %d",
+                    key, &t.il_width, &t.by, &t.bz, &t.bt, &t.R, &t.R64) != 7)
+      continue;
+    const bool ok = (t.il_width == 0 || t.il_width == 16 || t.il_width == 32 || t.il_width == 48) &&
+                    (t.R == 0 || t.R == 1 || t.R == 2 || t.R == 4) && (t.R64 == 0 || t.R64 == 1 || t.R64 == 2) &&
+                    t.by >= 0 && t.bz >= 0 && t.bt >= 0 && t.by <= 64 && t.bz <= 64 && t.bt <= 64;
+    if (ok) c->tuned[key] = t;  // a brick that does not tile the lattice is ignored at use
   }
   std::fclose(f);
 }
 
-// Time the Schur operator for each candidate width on min(nrhs, 16) fields and keep the
-// fastest; results are cached in the context (and in A2A_TUNE_CACHE if set).
-static int autotune_R(Ctx* c, int clover_h, double kappa, int prec, int nrhs, int* R, double* ms_out) {
+// Coordinate search over the knobs of the path the solve runs, each timed on the Schur
+// operator (both stencil launches) with min(nrhs, 64) sources:
+//   1. the interleaved group width 16 / 32 / 48 (FP16 / BF16 storage on the matrix cores), or the
+//      per-thread RHS width 1 / 2 / 4 (FP32, FP64, or FP16 / BF16 without interleaving);
+//   2. the stencil brick (y, z, t extents; up to six shapes that tile the lattice);
+//   3. the RHS width 1 / 2 of the FP64 stencils of setup, reliable updates and reconstruction,
+//      timed as the FP64 Schur operator on min(nrhs, 24) sources with the chosen brick.
+// The result is cached in the context and in the JSON file named by A2A_TUNE_CACHE.
+static int autotune_cfg(Ctx* c, int clover_h, double kappa, int prec, int nrhs, TuneCfg* out,
+                        a2a_tune_result* res) {
   CloverField* cf = c->clover(clover_h);
   if (!cf) return c->fail(A2A_EHANDLE, "unknown clover handle");
   const Geo g = c->gauge(cf->gauge)->g;
   const std::string key = tune_key(g, prec, nrhs);
-  for (int k = 0; k < 3; ++k)
-    if (ms_out) ms_out[k] = -1.0;
   auto it = c->tuned.find(key);
-  if (it != c->tuned.end() && !ms_out) {
-    *R = it->second;
+  if (it != c->tuned.end()) {
+    *out = it->second;
+    if (res) {
+      std::memset(res, 0, sizeof *res);
+      res->il_width = out->il_width;
+      res->brick[0] = out->by;
+      res->brick[1] = out->bz;
+      res->brick[2] = out->bt;
+      res->rhs_block = out->R;
+      res->rhs_block64 = out->R64;
+      res->ms_schur = res->ms_schur64 = -1.0;
+    }
     return A2A_OK;
   }
-  const int n = std::min(nrhs, 16);
-  const int cand[3] = {1, 2, 4};
-  double best = 1e300;
-  int bestR = 1;
-  for (int k = 0; k < 3; ++k) {
-    if (prec == 0 && cand[k] > 2) continue;
-    double ms = 0;
-    A2A_TRY(stencil_time(c, clover_h, kappa, A2A_OP_SCHUR, prec, n, 3, cand[k], &ms));
-    if (ms_out) ms_out[k] = ms;
-    if (ms < best) {
-      best = ms;
-      bestR = cand[k];
+  const int n = std::min(nrhs, 64);
+  const bool il = use_interleave(c, prec) && c->mfma && n >= IL_REM_MIN;
+  int tried = 0;
+  auto timed = [&](int p, int nn, const TuneCfg& t, double* ms) -> int {
+    ++tried;
+    return stencil_time(c, clover_h, kappa, A2A_OP_SCHUR, p, nn, 3, t, ms);
+  };
+  TuneCfg best{};
+  double tbest = 1e300;
+  // 1. RHS width of the inner stencil
+  if (il) {
+    for (int w : {48, 32, 16}) {
+      if (w > 16 && w - 16 >= ((n + 15) / 16) * 16) continue;  // a group would hold no more sources than w - 16
+      TuneCfg t{};
+      t.il_width = w;
+      double ms = 0;
+      A2A_TRY(timed(prec, n, t, &ms));
+      if (ms < tbest) {
+        tbest = ms;
+        best = t;
+      }
+    }
+  } else {
+    for (int r : {1, 2, 4}) {
+      if (prec == 0 && r > 2) continue;
+      TuneCfg t{};
+      t.R = r;
+      double ms = 0;
+      A2A_TRY(timed(prec, n, t, &ms));
+      if (ms < tbest) {
+        tbest = ms;
+        best = t;
+      }
     }
   }
-  c->tuned[key] = bestR;
+  // 2. brick (the default brick was timed above)
+  int br[8][3];
+  const int nb = brick_choices(g, br, 6);
+  best.by = g.by;
+  best.bz = g.bz;
+  best.bt = g.bt;
+  for (int k = 0; k < nb; ++k) {
+    if (br[k][0] == g.by && br[k][1] == g.bz && br[k][2] == g.bt) continue;
+    TuneCfg t = best;
+    t.by = br[k][0];
+    t.bz = br[k][1];
+    t.bt = br[k][2];
+    double ms = 0;
+    A2A_TRY(timed(prec, n, t, &ms));
+    if (ms < tbest) {
+      tbest = ms;
+      best = t;
+    }
+  }
+  // 3. FP64 stencil width
+  double t64 = 1e300;
+  for (int r : {1, 2}) {
+    TuneCfg t = best;
+    t.il_width = 0;
+    t.R = r;
+    double ms = 0;
+    A2A_TRY(timed(0, std::min(nrhs, 24), t, &ms));
+    if (ms < t64) {
+      t64 = ms;
+      best.R64 = r;
+    }
+  }
+  c->tuned[key] = best;
   tune_save(c);
-  *R = bestR;
+  *out = best;
+  if (res) {
+    std::memset(res, 0, sizeof *res);
+    res->il_width = best.il_width;
+    res->brick[0] = best.by;
+    res->brick[1] = best.bz;
+    res->brick[2] = best.bt;
+    res->rhs_block = best.R;
+    res->rhs_block64 = best.R64;
+    res->ms_schur = tbest;
+    res->ms_schur64 = t64;
+    res->candidates = tried;
+  }
   return A2A_OK;
 }
 
-extern "C" int a2a_autotune(a2a_ctx* h, int clover_h, double kappa, int prec, int nrhs, int* best_R,
-                            double* ms_per_width) {
-  if (!h || !best_R || nrhs <= 0) return A2A_EINVAL;
+extern "C" int a2a_brick_choices(const a2a_geom* geom, int* out, int maxn) {
+  Geo g;
+  if (!geom || !out || maxn < 0 || geom_to_geo(geom, &g)) return A2A_EINVAL;
+  std::vector<int> tmp(3 * (size_t)std::max(1, maxn));
+  const int n = brick_choices(g, (int(*)[3])tmp.data(), maxn);
+  std::copy(tmp.begin(), tmp.begin() + 3 * n, out);
+  return n;
+}
+
+extern "C" int a2a_autotune(a2a_ctx* h, int clover_h, double kappa, int prec, int nrhs, a2a_tune_result* result) {
+  if (!h || nrhs <= 0) return A2A_EINVAL;
   Ctx* c = &h->c;
   (void)hipSetDevice(c->device);
   if (check_prec(prec)) return c->fail(A2A_EINVAL, "unknown precision mode");
-  return autotune_R(c, clover_h, kappa, prec, nrhs, best_R, ms_per_width);
+  TuneCfg t{};
+  return autotune_cfg(c, clover_h, kappa, prec, nrhs, &t, result);
 }
 
 // =========================================================================================

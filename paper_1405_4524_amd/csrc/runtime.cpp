@@ -41,19 +41,29 @@ int geom_to_geo(const a2a_geom* geom, Geo* g) {
   int bx = g->Xh;
   while (bx > 16 && bx % 2 == 0) bx /= 2;
   g->bxh = (unsigned char)bx;
-  g->by = g->bz = g->bt = 1;
-  const int target = std::max(1, BS / bx);
-  static const int cand[][3] = {{4, 2, 2}, {2, 2, 4}, {2, 4, 2}, {4, 4, 1}, {2, 2, 2}, {4, 2, 1},
-                                {2, 2, 1}, {4, 1, 1}, {2, 1, 1}, {1, 1, 1}};
-  for (const auto& c : cand) {
-    if (c[0] * c[1] * c[2] > target) continue;
-    if (g->Y % c[0] || g->Z % c[1] || g->T % c[2]) continue;
-    g->by = (unsigned char)c[0];
-    g->bz = (unsigned char)c[1];
-    g->bt = (unsigned char)c[2];
-    break;
-  }
+  int ch[1][3];
+  brick_choices(*g, ch, 1);
+  g->by = (unsigned char)ch[0][0];
+  g->bz = (unsigned char)ch[0][1];
+  g->bt = (unsigned char)ch[0][2];
   return A2A_OK;
+}
+
+int brick_choices(const Geo& g, int (*out)[3], int maxn) {
+  static const int cand[][3] = {{4, 2, 2}, {2, 2, 4}, {2, 4, 2}, {4, 4, 1}, {8, 2, 1}, {8, 1, 2}, {2, 2, 2},
+                                {4, 2, 1}, {2, 2, 1}, {4, 1, 1}, {2, 1, 1}, {1, 1, 1}};
+  const int target = std::max(1, BS / std::max(1, (int)g.bxh));
+  int n = 0;
+  for (const auto& c : cand) {
+    if (n >= maxn) break;
+    if (c[0] * c[1] * c[2] > target) continue;
+    if (g.Y % c[0] || g.Z % c[1] || g.T % c[2]) continue;
+    out[n][0] = c[0];
+    out[n][1] = c[1];
+    out[n][2] = c[2];
+    ++n;
+  }
+  return n;
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (dispatch index i -> XCD i % 8).
@@ -395,7 +405,8 @@ int Ctx::kappa_op(CloverField* cf, double kappa, int prec, KappaOp** out) {
 // ------------------------------------------------------------------------------------------
 // Solver
 // ------------------------------------------------------------------------------------------
-Solver::Solver(Ctx* c, int p, int r) : ctx(c), prec(p), R(r), R64(c->rhs_block64 == 1 ? 1 : 2) {}
+Solver::Solver(Ctx* c, int p, int r)
+    : ctx(c), prec(p), R(r), R64(c->rhs_block64 == 1 ? 1 : 2), by(c->brick_by), bz(c->brick_bz), bt(c->brick_bt) {}
 
 Solver::~Solver() {
   ctx->dfree(d_ops);
@@ -455,6 +466,11 @@ int Solver::op_index(int clover_h, double kappa, KappaOp* kop, const GaugeField*
   e.kop = kop;
   kop->refs++;
   e.dev.g = gf->g;
+  if (by > 0 && bz > 0 && bt > 0 && gf->g.Y % by == 0 && gf->g.Z % bz == 0 && gf->g.T % bt == 0) {
+    e.dev.g.by = (unsigned char)by;  // a tuned brick (any brick tiling the lattice is a valid sweep)
+    e.dev.g.bz = (unsigned char)bz;
+    e.dev.g.bt = (unsigned char)bt;
+  }
   e.dev.kappa = kappa;
   for (int p = 0; p < 2; ++p) {
     e.dev.U[0][p] = gf->U[prec][p];

@@ -101,12 +101,22 @@ struct Slot {
   int req_idx = 0;
 };
 
+// Launch configuration of one workload, chosen by the autotuner per (arch, lattice, inner
+// precision, RHS bucket).  Zero fields mean "the context's default".
+struct TuneCfg {
+  int il_width = 0;           // RHS per interleaved group (16, 32 or 48 lanes; FP16 / BF16 storage)
+  int by = 0, bz = 0, bt = 0;  // stencil brick extents in y, z, t (the x extent is the whole row)
+  int R = 0;                  // RHS per thread of the per-thread stencil (1, 2 or 4)
+  int R64 = 0;                // RHS per thread of the FP64 stencils of reliable updates (1 or 2)
+};
+
 struct Solver {
   Ctx* ctx;
   int prec;
   int R;    // RHS per thread in the stencil
   int R64;  // RHS per thread in the FP64 stencils of setup, reliable updates and reconstruction
   int method = SOLVER_BICGSTAB;  // inner Krylov method of every slot of this solver
+  int by = 0, bz = 0, bt = 0;    // brick of the operators this solver creates (0: the lattice's default)
   std::vector<OpEntry> ops;
   std::vector<Slot*> live;  // slots in the device tables (running)
   // device tables
@@ -212,8 +222,10 @@ struct Ctx {
   bool poison = false;               // test hook: allocations are filled with 0xFF bytes (NaN)
   int fail_setup_enomem = 0;         // test hook: the next n source preparations fail (A2A_ENOMEM)
   int fail_setup_device = 0;         // test hook: the next n source preparations fail (A2A_EDEVICE)
-  std::map<std::string, int> tuned;  // tune key -> RHS-block width
-  std::string tune_path;             // A2A_TUNE_CACHE: JSON file of tuned widths
+  int il_width = IL_LANES;           // RHS per interleaved group (16, 32 or 48)
+  int brick_by = 0, brick_bz = 0, brick_bt = 0;  // option "brick": stencil brick of new solvers (0: default)
+  std::map<std::string, TuneCfg> tuned;  // tune key -> launch configuration
+  std::string tune_path;             // A2A_TUNE_CACHE: JSON file of tuned configurations
   // reduction scratch
   double* scal_pool = nullptr;
   double* scal_host = nullptr;
@@ -280,6 +292,9 @@ struct Ctx {
 
 double now_seconds();
 int geom_to_geo(const a2a_geom* geom, Geo* g);
+// valid stencil bricks (by, bz, bt) of a lattice in order of preference (the first is the
+// default of geom_to_geo); returns how many were written (at most maxn)
+int brick_choices(const Geo& g, int (*out)[3], int maxn);
 void xcd_order(std::vector<int2>& tiles, bool enable);
 
 }  // namespace a2a

@@ -52,23 +52,57 @@ def test_batch_equals_alone(ctx, orc, fields):
         assert np.linalg.norm(r) / np.linalg.norm(eta[i]) <= 1e-10
 
 
-def test_autotune_picks_a_width_and_solves(ctx, orc, fields):
+@pytest.mark.parametrize("prec,nsrc", [(2, 6), (2, 20), (3, 32), (1, 6)])
+def test_autotune_config_solves(ctx, orc, fields, prec, nsrc):
+    """The tuner picks a configuration of the path the solve runs (group width on the matrix
+    cores for FP16 / BF16 with >= 12 sources, else the per-thread width; a brick tiling the
+    lattice; the FP64 width), caches it, and a solve in that configuration meets 1e-10 with
+    the oracle's D for every source."""
     f = fields[1]
-    print("[gpu] autotune", flush=True)
-    best, ms = ctx.autotune(f["c"], 0.125, 2, 6)
-    assert best in (1, 2, 4) and set(ms) == {1, 2, 4} and all(v > 0 for v in ms.values())
-    assert ms[best] == min(ms.values())
+    X_, Y_, Z_, T_ = f["dims"]
+    print(f"[gpu] autotune prec={prec} nsrc={nsrc}", flush=True)
+    r = ctx.autotune(f["c"], 0.125, prec, nsrc)
+    assert r["candidates"] >= 3 and r["ms_schur"] > 0 and r["ms_schur64"] > 0
+    by, bz, bt = r["brick"]
+    assert Y_ % by == 0 and Z_ % bz == 0 and T_ % bt == 0
+    assert r["rhs_block64"] in (1, 2)
+    if prec in (2, 3) and nsrc >= 12:
+        assert r["il_width"] in (16, 32, 48)
+    else:
+        assert r["il_width"] == 0 and r["rhs_block"] in (1, 2, 4)
+    again = ctx.autotune(f["c"], 0.125, prec, nsrc)
+    assert again["candidates"] == 0 and again["brick"] == r["brick"] and again["il_width"] == r["il_width"]
     ctx.set_option("autotune", 1)
     try:
-        eta = inputs.z2_noise(f["dims"], 6, seed=31)
-        X, info, rc = ctx.solve_propagators(f["c"], eta, 0.125, 1.5, tol=1e-10, prec=2)
+        eta = inputs.z2_noise(f["dims"], nsrc, seed=31)
+        X, info, rc = ctx.solve_propagators(f["c"], eta, 0.125, 1.5, tol=1e-10, prec=prec)
     finally:
         ctx.set_option("autotune", 0)
     assert rc == 0
     A = orc.clover(f["U"], 0.125, 1.5)
-    for i in range(6):
-        r = eta[i] - orc.apply_D(f["U"], A, 0.125, X[i], -1)
-        assert np.linalg.norm(r) / np.linalg.norm(eta[i]) <= 1e-10
+    for i in range(nsrc):
+        res = eta[i] - orc.apply_D(f["U"], A, 0.125, X[i], -1)
+        assert np.linalg.norm(res) / np.linalg.norm(eta[i]) <= 1e-10, (i, info[i])
+
+
+def test_tuned_bricks_give_the_same_operator(ctx, orc, fields):
+    """Every brick the tuner may choose is a reordering of the sweep only: the FP64 Schur
+    operator is bitwise the same, and the FP16 one on the matrix cores matches to rounding."""
+    from paper_1405_4524_amd import a2a
+
+    f = fields[1]
+    print("[gpu] bricks", flush=True)
+    rng = np.random.default_rng(9)
+    psi = (rng.standard_normal((3,) + tuple(f["dims"][::-1]) + (4, 3))
+           + 1j * rng.standard_normal((3,) + tuple(f["dims"][::-1]) + (4, 3)))
+    ref = ctx.dslash_clover(f["c"], 0.125, psi, op=a2a.OP_SCHUR, prec=a2a.F64)
+    for b in ctx.brick_choices(f["dims"]):
+        ctx.set_option("brick", b[0] * 10000 + b[1] * 100 + b[2])
+        try:
+            out = ctx.dslash_clover(f["c"], 0.125, psi, op=a2a.OP_SCHUR, prec=a2a.F64)
+        finally:
+            ctx.set_option("brick", 0)
+        assert np.array_equal(out, ref), b
 
 
 @pytest.mark.parametrize("il", [0, 1])
@@ -179,13 +213,26 @@ def test_engine_failed_admission_is_undone(ctx, orc, fields):
     their ids and their memory back.  An out-of-memory failure while another request runs leaves
     it queued, and a later step admits it afresh; a device error fails that request alone.  The
     requests converge to their solutions alone, the engine's active count returns to zero and
-    the context's live memory to its value before the engine was created."""
+    the context's live memory to its value before the engine was created.  The test has a
+    context of its own, so that no clover fields of other kappas are left for an out-of-memory
+    admission to evict (which would lower the live memory legitimately)."""
+    from paper_1405_4524_amd import a2a
+
+    print("[gpu] engine: failed admissions are undone", flush=True)
+    f = dict(fields[0])
+    cx = a2a.Context(0)
+    try:
+        _failed_admission_body(cx, orc, f, cx.load_clover(cx.load_gauge(f["U"], -1), 1.5))
+    finally:
+        cx.finalize()
+
+
+def _failed_admission_body(ctx, orc, f, clover):
     import torch
 
     from paper_1405_4524_amd import a2a
 
-    print("[gpu] engine: failed admissions are undone", flush=True)
-    f = fields[0]
+    f["c"] = clover
     kappa = 0.127
     sizes = (5, 7, 4)
     etas = [inputs.z2_noise(f["dims"], n, seed=600 + k) for k, n in enumerate(sizes)]
