@@ -232,6 +232,22 @@ int a2a_contract_pion_2pt(a2a_ctx *ctx, const a2a_geom *geom, const double *sour
 int a2a_contract_pion_2pt_dev(a2a_ctx *ctx, const a2a_geom *geom, const double *sources_dev,
                               const double *solutions_dev, int nrhs, int mode, double *corr_host,
                               double *O_host_or_null);
+/* The same contraction for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): it calls no hipMalloc,
+ * hipFree or allocating library routine.  Inputs and outputs are device pointers owned by the
+ * caller: sources_dev and solutions_dev as for a2a_contract_pion_2pt_dev, corr_dev complex
+ * [T], O_dev_or_null complex [T][nrhs][nrhs] (if null, O is kept in the scratch only).  The
+ * partial sums of the timeslice products live in a static 32 MiB device array per GPU, held
+ * from the library's first use on that GPU until the process ends; its device address is
+ * looked up once per device in a2a_init.  Limit: 16 T nrhs^2 bytes (twice that without
+ * O_dev) must fit in 32 MiB, i.e. nrhs <= 181 at T = 64 with O_dev, else A2A_EINVAL and
+ * nothing is launched.  Every call on one GPU shares that GPU's array: calls that overlap on
+ * one GPU (two contexts, two host threads) race and give wrong results.  The array keeps the
+ * last call's contents; nothing in it needs to start at zero.  Returns after the stream has
+ * finished the call's kernels. */
+int a2a_contract_pion_2pt_noalloc(a2a_ctx *ctx, const a2a_geom *geom, const double *sources_dev,
+                                  const double *solutions_dev, int nrhs, int mode, double *corr_dev,
+                                  double *O_dev_or_null);
 /* Zero-momentum pi-pi pieces from four disjoint noise groups (nrhs = 4m, 1 <= m <= 32):
  * diagrams complex [4][T] = D0 (direct), D1 (vacuum, unsubtracted), D2, D3 (single quark
  * loop through the four points, both orientations); vac_pieces complex [T] = the

@@ -82,6 +82,7 @@ _SIG = {
     "a2a_solve_propagators_dev": (I, [P, I, P, I, D, D, D, I, I, P, P, P]),
     "a2a_contract_pion_2pt": (I, [P, ctypes.POINTER(Geom), P, P, I, I, P, P]),
     "a2a_contract_pion_2pt_dev": (I, [P, ctypes.POINTER(Geom), P, P, I, I, P, P]),
+    "a2a_contract_pion_2pt_noalloc": (I, [P, ctypes.POINTER(Geom), P, P, I, I, P, P]),
     "a2a_contract_pipi_2pt": (I, [P, ctypes.POINTER(Geom), P, P, I, P, P, P]),
     "a2a_contract_pipi_2pt_dev": (I, [P, ctypes.POINTER(Geom), P, P, I, P, P, P]),
     "a2a_z2_noise_dev": (I, [P, ctypes.POINTER(Geom), ULL, LL, I, P]),
@@ -344,6 +345,14 @@ class Context:
                                                   int(mode), corr.ctypes.data_as(P),
                                                   O.ctypes.data_as(P) if want_O else None))
         return corr, O
+
+    def contract_pion_2pt_noalloc(self, src_t, sol_t, nrhs, dims, corr_t, O_t=None, t_bc=-1, mode=PION_UNBIASED):
+        """The allocation-free contraction: corr_t (complex128 [T]) and O_t (complex128 [T][n][n] or
+        None) are caller-owned device tensors; the library allocates nothing."""
+        g = geom(dims, t_bc)
+        self._chk(lib().a2a_contract_pion_2pt_noalloc(self._c, ctypes.byref(g), _tptr(src_t), _tptr(sol_t),
+                                                      int(nrhs), int(mode), _tptr(corr_t),
+                                                      _tptr(O_t) if O_t is not None else None))
 
     def contract_pipi_2pt(self, sources, solutions, t_bc=-1, want_pion=False):
         """(diagrams[4, T], vac[T]) and, with want_pion, also the unbiased pion correlator."""

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <deque>
+#include <mutex>
 
 #include "a2a_contract.h"
 #include "runtime.h"
@@ -402,6 +403,38 @@ double json_num(const char* js, const char* key, double dflt) {
 }  // namespace
 
 // =========================================================================================
+// scratch of the allocation-free pion contraction
+// =========================================================================================
+// The stochastic-operator partial sums (and O itself when the caller passes no O buffer) of
+// a2a_contract_pion_2pt_noalloc live in this array.  Every GPU the library runs on holds its
+// own copy at its own address, from the first use of the library on that device until the
+// process ends.  Host code never passes the array's name to a kernel or a copy (on the host it
+// is only a stand-in symbol): it uses the device address looked up once per device below.
+namespace {
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(32) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+std::mutex scratch_mu;
+void* scratch_dev[NOALLOC_MAX_DEVICES];
+
+// with `device` current: the device address of that device's copy of the array
+int scratch_lookup(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return A2A_EINVAL;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (scratch_dev[device]) return A2A_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return A2A_EDEVICE;
+  scratch_dev[device] = p;
+  return A2A_OK;
+}
+
+void* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  return (device >= 0 && device < NOALLOC_MAX_DEVICES) ? scratch_dev[device] : nullptr;
+}
+}  // namespace
+
+// =========================================================================================
 // context
 // =========================================================================================
 extern "C" int a2a_init(a2a_ctx** out, int device, size_t budget, void* stream) {
@@ -411,6 +444,7 @@ extern "C" int a2a_init(a2a_ctx** out, int device, size_t budget, void* stream) 
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return A2A_EDEVICE;
   if (device < 0 || device >= ndev) return A2A_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return A2A_EDEVICE;
+  if (scratch_lookup(device) != A2A_OK) return A2A_EDEVICE;
   auto* h = new a2a_ctx();
   Ctx* c = &h->c;
   c->device = device;
@@ -1041,6 +1075,39 @@ extern "C" int a2a_contract_pion_2pt(a2a_ctx* h, const a2a_geom* geom, const dou
 extern "C" int a2a_contract_pion_2pt_dev(a2a_ctx* h, const a2a_geom* geom, const double* src, const double* sol,
                                          int n, int mode, double* corr, double* O) {
   return pion_impl(h, geom, src, sol, n, mode, corr, O, true);
+}
+
+// The pion contraction without any allocation: partial sums (and O when O_dev is null) in the
+// device's static scratch array, inputs and outputs in the caller's device memory.
+extern "C" int a2a_contract_pion_2pt_noalloc(a2a_ctx* h, const a2a_geom* geom, const double* src,
+                                             const double* sol, int n, int mode, double* corr_dev, double* O_dev) {
+  if (!h || !src || !sol || !corr_dev) return A2A_EINVAL;
+  Ctx* c = &h->c;
+  (void)hipSetDevice(c->device);
+  Geo g;
+  if (geom_to_geo(geom, &g)) return c->fail(A2A_EINVAL, "bad lattice geometry");
+  if (n < 1 || (mode == A2A_PION_UNBIASED && n < 2) || (mode != 0 && mode != 1))
+    return c->fail(A2A_EINVAL, "need nrhs >= 2 for the unbiased estimator and mode 0 or 1");
+  char* base = (char*)scratch_of(c->device);
+  if (!base) return c->fail(A2A_EDEVICE, "no scratch address for this device");
+  const size_t per = sizeof(double) * 2 * (size_t)g.T * n * n;  // one [T][n][n] complex array
+  const size_t o_bytes = O_dev ? 0 : (per + 255) & ~(size_t)255;
+  if (o_bytes + per > NOALLOC_SCRATCH_BYTES)
+    return c->fail(A2A_EINVAL, "T nrhs^2 too large for the 32 MiB scratch of the allocation-free contraction (" +
+                                   std::to_string((o_bytes + per) >> 20) + " MiB needed at the least)");
+  // chunks of the K sum as in the allocating call, as many as the scratch holds
+  const long K = 12L * g.X * g.Y * g.Z;
+  const int ntb = (n + 63) / 64;
+  const long want = 4096 / std::max(1, g.T * ntb * ntb);
+  const long fit = (long)((NOALLOC_SCRATCH_BYTES - o_bytes) / per);
+  const int nchunk = (int)std::max(1L, std::min(std::min(want, (K + 255) / 256), fit));
+  double* O = O_dev ? O_dev : (double*)base;
+  double* part = (double*)(base + o_bytes);
+  launch_stoch_ops(g, n, src, sol, part, nchunk, O, c->stream);
+  launch_pion_corr(g.T, n, O, mode, corr_dev, c->stream);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return c->fail(A2A_EDEVICE, std::string("pion contraction: ") + hipGetErrorString(e));
+  return c->sync();
 }
 
 static int pipi_impl(a2a_ctx* h, const a2a_geom* geom, const double* src, const double* sol, int n, double* diag,
