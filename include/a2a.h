@@ -136,7 +136,8 @@ const char *a2a_last_error(const a2a_ctx *ctx);
  * A2A_EDEVICE, so that the clean-up of a failed admission can be checked), "il_width" (16, 32
  * or 48, default 48: RHS per lane-interleaved group), "brick" (by * 10000 + bz * 100 + bt:
  * the stencil brick of later calls on lattices it tiles, 0 = each lattice's default; a brick
- * orders the stencil's sweep only, results are unchanged).
+ * orders the stencil's sweep only, results are unchanged), "mfma_slab" (0/1, default 0: the
+ * matrix-core stencil's blocks in XCD slabs, XCD k taking the k-th eighth of the bricks).
  * Returns A2A_EINVAL for an unknown key. */
 int a2a_set_option(a2a_ctx *ctx, const char *key, double value);
 /* Bytes of device memory in the context's live buffers.  Freed buffers are kept for reuse
@@ -185,14 +186,15 @@ typedef struct {
   double ms_schur;   /* best time of the inner-precision Schur operator (both stencils), ms; -1 if cached */
   double ms_schur64; /* best time of the FP64 Schur operator, ms; -1 if cached */
   int candidates;    /* configurations timed (0: taken from the cache) */
-  int reserved;
+  int xcd_slab;      /* matrix-core blocks: 1 in XCD slabs, 0 in brick order, -1 not used */
 } a2a_tune_result;
 
 /* Autotune the launch configuration of the batched stencils (the multi-RHS batching of the
  * solve) for this lattice, precision and number of sources, by a coordinate search that times
  * the Schur operator on min(nrhs, 64) sources: first the RHS width (the lane-interleaved group
  * width 16 / 32 / 48 for FP16 / BF16 storage on the matrix cores, else the per-thread width
- * 1 / 2 / 4), then the stencil brick (up to six shapes that tile the lattice), then the FP64
+ * 1 / 2 / 4), then the stencil brick (up to six shapes that tile the lattice) together with
+ * the order of the matrix-core blocks over the XCDs (brick order or XCD slabs), then the FP64
  * stencils' width 1 / 2 (FP64 Schur operator on min(nrhs, 24) sources).  The result is kept in
  * the context and in the JSON file named by the environment variable A2A_TUNE_CACHE, keyed by
  * arch, lattice, precision and RHS bucket (the next power of two, at most 64); a cached key

@@ -52,6 +52,7 @@ struct HopMArgs {
   double ca, cb, gsign;
   int gpow;
   int red;
+  int nt3;  // every group of the launch has three lane tiles (48-lane groups)
   RedBuf rb;
 };
 

@@ -218,6 +218,7 @@ static int solve_batch(Ctx* c, int clover_h, const double* src, int nrhs, double
   const int R = tc.R ? tc.R : effective_R(c, prec);
   Solver sv(c, prec, R);
   if (tc.R64) sv.R64 = tc.R64;
+  if (tc.slab >= 0) sv.mfma_slab = tc.slab;
   if (tc.by > 0) {
     sv.by = tc.by;
     sv.bz = tc.bz;
@@ -544,6 +545,8 @@ extern "C" int a2a_set_option(a2a_ctx* h, const char* key, double v) {
     c->timing = v != 0;
   } else if (k == "autotune") {
     c->autotune = v != 0;
+  } else if (k == "mfma_slab") {
+    c->mfma_slab = v != 0;
   } else if (k == "il_width") {
     if (v != 16 && v != 32 && v != 48) return c->fail(A2A_EINVAL, "il_width must be 16, 32 or 48");
     c->il_width = (int)v;
@@ -746,6 +749,7 @@ static int stencil_time(Ctx* c, int clover_h, double kappa, int opk, int prec, i
   KappaOp* kop;
   A2A_TRY(resolve_op(c, clover_h, kappa, prec, &gf, &cf, &kop));
   Solver sv(c, prec, tc.R ? tc.R : effective_R(c, prec));
+  if (tc.slab >= 0) sv.mfma_slab = tc.slab;
   if (tc.by > 0) {
     sv.by = tc.by;
     sv.bz = tc.bz;
@@ -816,8 +820,10 @@ static void tune_save(Ctx* c) {
   bool first = true;
   for (auto& kv : c->tuned) {
     const TuneCfg& t = kv.second;
-    std::fprintf(f, "%s\n  \"%s\": {\"il_width\": %d, \"by\": %d, \"bz\": %d, \"bt\": %d, \"R\": %d, \"R64\": %d}",
-                 first ? "" : ",", kv.first.c_str(), t.il_width, t.by, t.bz, t.bt, t.R, t.R64);
+    std::fprintf(f,
+                 "%s\n  \"%s\": {\"il_width\": %d, \"by\": %d, \"bz\": %d, \"bt\": %d, \"slab\": %d, \"R\": %d, "
+                 "\"R64\": %d}",
+                 first ? "" : ",", kv.first.c_str(), t.il_width, t.by, t.bz, t.bt, t.slab, t.R, t.R64);
     first = false;
   }
   std::fprintf(f, "\n}\n");
@@ -833,12 +839,15 @@ static void tune_load(Ctx* c) {
   while (std::fgets(line, sizeof line, f)) {
     char key[400];
     TuneCfg t;
-    if (std::sscanf(line, " \"%399[^\"]\": {\"il_width\": %d, \"by\": %d, \"bz\": %d, \"bt\": %d, \"R\": %d, \"R64\": %d",
-                    key, &t.il_width, &t.by, &t.bz, &t.bt, &t.R, &t.R64) != 7)
+    if (std::sscanf(line,
+                    " \"%399[^\"]\": {\"il_width\": %d, \"by\": %d, \"bz\": %d, \"bt\": %d, \"slab\": %d, \"R\": %d, "
+                    "\"R64\": %d",
+                    key, &t.il_width, &t.by, &t.bz, &t.bt, &t.slab, &t.R, &t.R64) != 8)
       continue;
     const bool ok = (t.il_width == 0 || t.il_width == 16 || t.il_width == 32 || t.il_width == 48) &&
                     (t.R == 0 || t.R == 1 || t.R == 2 || t.R == 4) && (t.R64 == 0 || t.R64 == 1 || t.R64 == 2) &&
-                    t.by >= 0 && t.bz >= 0 && t.bt >= 0 && t.by <= 64 && t.bz <= 64 && t.bt <= 64;
+                    t.by >= 0 && t.bz >= 0 && t.bt >= 0 && t.by <= 64 && t.bz <= 64 && t.bt <= 64 &&
+                    t.slab >= -1 && t.slab <= 1;
     if (ok) c->tuned[key] = t;  // a brick that does not tile the lattice is ignored at use
   }
   std::fclose(f);
@@ -869,6 +878,7 @@ static int autotune_cfg(Ctx* c, int clover_h, double kappa, int prec, int nrhs, 
       res->brick[2] = out->bt;
       res->rhs_block = out->R;
       res->rhs_block64 = out->R64;
+      res->xcd_slab = out->slab;
       res->ms_schur = res->ms_schur64 = -1.0;
     }
     return A2A_OK;
@@ -908,25 +918,30 @@ static int autotune_cfg(Ctx* c, int clover_h, double kappa, int prec, int nrhs, 
       }
     }
   }
-  // 2. brick (the default brick was timed above)
+  // 2. brick (the default brick in brick order was timed above), and for the matrix-core
+  //    stencil the block order: brick order or XCD slabs
   int br[8][3];
   const int nb = brick_choices(g, br, 6);
   best.by = g.by;
   best.bz = g.bz;
   best.bt = g.bt;
-  for (int k = 0; k < nb; ++k) {
-    if (br[k][0] == g.by && br[k][1] == g.bz && br[k][2] == g.bt) continue;
-    TuneCfg t = best;
-    t.by = br[k][0];
-    t.bz = br[k][1];
-    t.bt = br[k][2];
-    double ms = 0;
-    A2A_TRY(timed(prec, n, t, &ms));
-    if (ms < tbest) {
-      tbest = ms;
-      best = t;
+  best.slab = il ? c->mfma_slab : -1;
+  const TuneCfg first = best;  // timed in step 1
+  for (int k = 0; k < nb; ++k)
+    for (int sl = 0; sl < (il ? 2 : 1); ++sl) {
+      TuneCfg t = first;
+      t.by = br[k][0];
+      t.bz = br[k][1];
+      t.bt = br[k][2];
+      if (il) t.slab = sl;
+      if (t.by == first.by && t.bz == first.bz && t.bt == first.bt && t.slab == first.slab) continue;
+      double ms = 0;
+      A2A_TRY(timed(prec, n, t, &ms));
+      if (ms < tbest) {
+        tbest = ms;
+        best = t;
+      }
     }
-  }
   // 3. FP64 stencil width
   double t64 = 1e300;
   for (int r : {1, 2}) {
@@ -951,6 +966,7 @@ static int autotune_cfg(Ctx* c, int clover_h, double kappa, int prec, int nrhs, 
     res->brick[2] = best.bt;
     res->rhs_block = best.R;
     res->rhs_block64 = best.R64;
+    res->xcd_slab = best.slab;
     res->ms_schur = tbest;
     res->ms_schur64 = t64;
     res->candidates = tried;

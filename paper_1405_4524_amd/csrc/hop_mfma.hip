@@ -25,6 +25,8 @@
 // the hopping blocks (d, spin s', colour b, re/im), 192..215 the clover block, 216..231 zero.
 // Rows are 464 B apart so that the 16-byte fragment reads of 16 consecutive rows fall on
 // distinct banks.
+#include <type_traits>
+
 #include "a2a_kernels.h"
 
 namespace a2a {
@@ -232,7 +234,7 @@ __device__ __forceinline__ void site_neighbours(const Geo& g, int site, int po, 
 // of three register buffers), and the matrix fragments are read from LDS right before their
 // products.
 
-template <class P, int EPI, int RED>
+template <class P, int EPI, int RED, bool NT3>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_hop_mfma(HopMArgs a) {
   using S = typename P::S;
   using M = MM<S>;
@@ -360,13 +362,16 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void
   // Loads and stores in the sweep are unconditional (positions past the wave's range are clamped
   // to its last site, whose values are then recomputed and rewritten unchanged), so the number
   // of memory operations in flight is the same on every path and the waits on them stay exact.
-  auto prefetch = [&](TileIn& dst) {
+  // With three tiles per group the ring buffer of an item is its tile (items are (site, tile)
+  // pairs, tiles inner, three buffers), so only buffer 0 takes the site's links and clover:
+  // one load per site instead of one per item.
+  auto prefetch = [&](TileIn& dst, auto with_sd) {
     const int p = pk < items ? pk : items - 1;
     const int ntp = __builtin_amdgcn_readfirstlane(p % NT);
     const int site = site_at(s0 + p / NT);
     dst.site = site;
     dst.nt = ntp;
-    dst.SD = gld4(sd_base + (size_t)site * 288);
+    if (decltype(with_sd)::value) dst.SD = gld4(sd_base + (size_t)site * 288);
     int nbs_p[6];
     site_neighbours(g, site, po, gq, nbs_p);
     load_tile<EPI, RED>(dst, vin, vaux2, vrh, nbs_p, hoff, site, NT, ntp, n, gq);
@@ -374,12 +379,12 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void
   };
   // compute cursor: site ck
   int ck = 0;
-  auto step = [&](TileIn& cur, TileIn& pf) {
+  auto step = [&](TileIn& cur, TileIn& pf, auto may_build, auto pf_sd) {
     const int site = cur.site;
     const int nt = cur.nt;
     const bool live = ck < items;
-    if (nt == 0) build(cur.SD);  // this site's matrix, once for all its tiles
-    prefetch(pf);
+    if (decltype(may_build)::value && nt == 0) build(cur.SD);  // this site's matrix, once for all its tiles
+    prefetch(pf, pf_sd);
     __builtin_amdgcn_sched_barrier(0);  // keep the requests ahead of this item's work
     wave_lds_sync();
     f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
@@ -465,12 +470,14 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 
   if (items > 0) {
     TileIn R0, R1, R2;
-    prefetch(R0);
-    prefetch(R1);
+    using yes = std::true_type;
+    using tile0 = std::integral_constant<bool, !NT3>;  // buffers 1 and 2 hold tiles 1 and 2
+    prefetch(R0, yes{});
+    prefetch(R1, tile0{});
     for (int i = 0; i < items; i += 3) {
-      step(R0, R2);
-      step(R1, R0);
-      step(R2, R1);
+      step(R0, R2, yes{}, tile0{});
+      step(R1, R0, tile0{}, yes{});
+      step(R2, R1, tile0{}, tile0{});
     }
   }
 
@@ -500,21 +507,29 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void
   }
 }
 
-template <class P>
-static void launch_mfma_p(const HopMArgs& a, int ntiles, int epi, hipStream_t s) {
+template <class P, bool NT3>
+static void launch_mfma_nt(const HopMArgs& a, int ntiles, int epi, hipStream_t s) {
   const dim3 g(ntiles), b(BS);
   if (epi == 2) {
-    hipLaunchKernelGGL((k_hop_mfma<P, 2, RED_NONE>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_hop_mfma<P, 2, RED_NONE, NT3>), g, b, 0, s, a);
   } else if (epi == 1) {
     if (a.red == RED_ALPHA)
-      hipLaunchKernelGGL((k_hop_mfma<P, 1, RED_ALPHA>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_hop_mfma<P, 1, RED_ALPHA, NT3>), g, b, 0, s, a);
     else if (a.red == RED_OMEGA)
-      hipLaunchKernelGGL((k_hop_mfma<P, 1, RED_OMEGA>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_hop_mfma<P, 1, RED_OMEGA, NT3>), g, b, 0, s, a);
     else
-      hipLaunchKernelGGL((k_hop_mfma<P, 1, RED_NONE>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_hop_mfma<P, 1, RED_NONE, NT3>), g, b, 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_hop_mfma<P, 0, RED_NONE>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_hop_mfma<P, 0, RED_NONE, NT3>), g, b, 0, s, a);
   }
+}
+
+template <class P>
+static void launch_mfma_p(const HopMArgs& a, int ntiles, int epi, hipStream_t s) {
+  if (a.nt3)
+    launch_mfma_nt<P, true>(a, ntiles, epi, s);
+  else
+    launch_mfma_nt<P, false>(a, ntiles, epi, s);
 }
 
 bool hop_mfma_supports(int prec, int inv, bool clov, int red, bool aux1) {

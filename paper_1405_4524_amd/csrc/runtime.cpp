@@ -406,7 +406,14 @@ int Ctx::kappa_op(CloverField* cf, double kappa, int prec, KappaOp** out) {
 // Solver
 // ------------------------------------------------------------------------------------------
 Solver::Solver(Ctx* c, int p, int r)
-    : ctx(c), prec(p), R(r), R64(c->rhs_block64 == 1 ? 1 : 2), by(c->brick_by), bz(c->brick_bz), bt(c->brick_bt) {}
+    : ctx(c),
+      prec(p),
+      R(r),
+      R64(c->rhs_block64 == 1 ? 1 : 2),
+      by(c->brick_by),
+      bz(c->brick_bz),
+      bt(c->brick_bt),
+      mfma_slab(c->mfma_slab) {}
 
 Solver::~Solver() {
   ctx->dfree(d_ops);
@@ -623,6 +630,7 @@ int Solver::rebuild() {
   std::vector<int2> ilh, hnon;
   std::vector<int> gnon;
   il_mfma = true;
+  il_nt3 = true;
   for (int o = 0; o < (int)ops.size(); ++o) {
     std::map<char*, int> gidx;
     std::vector<int> rest;
@@ -649,6 +657,7 @@ int Solver::rebuild() {
     }
     const int e1 = (int)ilg.size();
     if (e1 > e0 && !(ops[o].dev.HL[0] && ops[o].dev.AF[0] && ops[o].dev.AIF[0])) il_mfma = false;
+    for (int e = e0; e < e1; ++e) il_nt3 = il_nt3 && ilg[e].nt == 3;
     const int g0 = (int)(gnon.size() / R);
     const int ng = (int)((rest.size() + R - 1) / R);
     for (int gi = 0; gi < ng; ++gi)
@@ -662,7 +671,11 @@ int Solver::rebuild() {
     for (int b = 0; b < ops[o].nblk; ++b)
       for (int gi = 0; gi < ng; ++gi) hnon.push_back(make_int2(g0 + gi, b));
   }
-  xcd_order(hnon, ctx->xcd_order);  // the matrix-core blocks stay in brick order, unslabbed
+  xcd_order(hnon, ctx->xcd_order);
+  // matrix-core blocks: in brick order (XCD k takes every eighth brick), or in XCD slabs (XCD k
+  // takes the k-th eighth of the bricks, so that bricks adjacent in every direction run on the
+  // same XCD at about the same time and share their faces through its L2); a tuned choice
+  xcd_order(ilh, mfma_slab != 0);
   A2A_TRY(grow(ctx, (void**)&d_ilgroups, &cap_ilg, sizeof(ILGroupDev) * std::max<size_t>(1, ilg.size())));
   A2A_TRY(grow(ctx, (void**)&d_il_hop_tiles, &cap_ilh, sizeof(int2) * std::max<size_t>(1, ilh.size())));
   A2A_TRY(grow(ctx, (void**)&d_groups_nonil, &cap_gnonil, sizeof(int) * std::max<size_t>(1, gnon.size())));
@@ -791,6 +804,7 @@ int Solver::hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par,
     m.gsign = gsign;
     m.gpow = gpow;
     m.red = red;
+    m.nt3 = il_nt3 ? 1 : 0;
     m.rb = ctx->redbuf();
     launch_hop_mfma(kprec, m, n_il_hop_tiles, inv, clov, ctx->stream);
     a.groups = d_groups_nonil;

@@ -108,6 +108,7 @@ struct TuneCfg {
   int by = 0, bz = 0, bt = 0;  // stencil brick extents in y, z, t (the x extent is the whole row)
   int R = 0;                  // RHS per thread of the per-thread stencil (1, 2 or 4)
   int R64 = 0;                // RHS per thread of the FP64 stencils of reliable updates (1 or 2)
+  int slab = -1;              // matrix-core blocks in XCD slabs (1) or in brick order (0); -1: the option
 };
 
 struct Solver {
@@ -117,6 +118,8 @@ struct Solver {
   int R64;  // RHS per thread in the FP64 stencils of setup, reliable updates and reconstruction
   int method = SOLVER_BICGSTAB;  // inner Krylov method of every slot of this solver
   int by = 0, bz = 0, bt = 0;    // brick of the operators this solver creates (0: the lattice's default)
+  int mfma_slab = 0;             // matrix-core stencil blocks ordered in XCD slabs
+  bool il_nt3 = false;           // every interleaved group has three lane tiles
   std::vector<OpEntry> ops;
   std::vector<Slot*> live;  // slots in the device tables (running)
   // device tables
@@ -224,6 +227,7 @@ struct Ctx {
   int fail_setup_device = 0;         // test hook: the next n source preparations fail (A2A_EDEVICE)
   int il_width = IL_LANES;           // RHS per interleaved group (16, 32 or 48)
   int brick_by = 0, brick_bz = 0, brick_bt = 0;  // option "brick": stencil brick of new solvers (0: default)
+  int mfma_slab = 0;                 // option "mfma_slab": matrix-core blocks in XCD slabs
   std::map<std::string, TuneCfg> tuned;  // tune key -> launch configuration
   std::string tune_path;             // A2A_TUNE_CACHE: JSON file of tuned configurations
   // reduction scratch

@@ -67,9 +67,9 @@ def test_autotune_config_solves(ctx, orc, fields, prec, nsrc):
     assert Y_ % by == 0 and Z_ % bz == 0 and T_ % bt == 0
     assert r["rhs_block64"] in (1, 2)
     if prec in (2, 3) and nsrc >= 12:
-        assert r["il_width"] in (16, 32, 48)
+        assert r["il_width"] in (16, 32, 48) and r["xcd_slab"] in (0, 1)
     else:
-        assert r["il_width"] == 0 and r["rhs_block"] in (1, 2, 4)
+        assert r["il_width"] == 0 and r["rhs_block"] in (1, 2, 4) and r["xcd_slab"] == -1
     again = ctx.autotune(f["c"], 0.125, prec, nsrc)
     assert again["candidates"] == 0 and again["brick"] == r["brick"] and again["il_width"] == r["il_width"]
     ctx.set_option("autotune", 1)
@@ -86,23 +86,32 @@ def test_autotune_config_solves(ctx, orc, fields, prec, nsrc):
 
 
 def test_tuned_bricks_give_the_same_operator(ctx, orc, fields):
-    """Every brick the tuner may choose is a reordering of the sweep only: the FP64 Schur
-    operator is bitwise the same, and the FP16 one on the matrix cores matches to rounding."""
+    """Every brick and block order the tuner may choose reorders the sweep only: the Schur
+    operator is bitwise the same in FP64 (per-thread stencil) and in FP16 on the matrix cores
+    (20 sources in one lane-interleaved group), and matches the oracle."""
     from paper_1405_4524_amd import a2a
 
     f = fields[1]
     print("[gpu] bricks", flush=True)
     rng = np.random.default_rng(9)
-    psi = (rng.standard_normal((3,) + tuple(f["dims"][::-1]) + (4, 3))
-           + 1j * rng.standard_normal((3,) + tuple(f["dims"][::-1]) + (4, 3)))
-    ref = ctx.dslash_clover(f["c"], 0.125, psi, op=a2a.OP_SCHUR, prec=a2a.F64)
-    for b in ctx.brick_choices(f["dims"]):
-        ctx.set_option("brick", b[0] * 10000 + b[1] * 100 + b[2])
-        try:
-            out = ctx.dslash_clover(f["c"], 0.125, psi, op=a2a.OP_SCHUR, prec=a2a.F64)
-        finally:
-            ctx.set_option("brick", 0)
-        assert np.array_equal(out, ref), b
+    shp = (20,) + tuple(f["dims"][::-1]) + (4, 3)
+    psi = rng.standard_normal(shp) + 1j * rng.standard_normal(shp)
+    A = orc.clover(f["U"], 0.125, 1.5)
+    odd = (orc.parity_mask(f["dims"]) == 1)[..., None, None]
+    want = orc.schur(f["U"], A, orc.invert_sites(A), 0.125, np.where(odd, psi[0], 0), -1)
+    for prec, tol in ((a2a.F64, 1e-13), (a2a.F16_F32, 4e-3)):
+        ref = ctx.dslash_clover(f["c"], 0.125, psi, op=a2a.OP_SCHUR, prec=prec)
+        assert rel(ref[0], want) <= tol, (prec, rel(ref[0], want))
+        for b in ctx.brick_choices(f["dims"]):
+            for slab in (0, 1):
+                ctx.set_option("brick", b[0] * 10000 + b[1] * 100 + b[2])
+                ctx.set_option("mfma_slab", slab)
+                try:
+                    out = ctx.dslash_clover(f["c"], 0.125, psi, op=a2a.OP_SCHUR, prec=prec)
+                finally:
+                    ctx.set_option("brick", 0)
+                    ctx.set_option("mfma_slab", 0)
+                assert np.array_equal(out, ref), (prec, b, slab)
 
 
 @pytest.mark.parametrize("il", [0, 1])
