@@ -295,8 +295,8 @@ def main():
                       if prec else "f64",
                       "rhs_block": (tuned["rhs_block"] or args.rhs_block) if tuned else args.rhs_block,
                       "autotuned": {k: tuned[k] for k in ("il_width", "brick", "xcd_slab", "rhs_block",
-                                                          "rhs_block64", "ms_schur", "ms_schur64", "candidates",
-                                                          "seconds")}
+                                                          "rhs_block64", "brick64", "xcd64", "ms_schur",
+                                                          "ms_schur64", "candidates", "seconds")}
                       if tuned else None,
                       "solver": args.solver,
                       "layout": "lane-interleaved groups, matrix-core stencil" if mfma else

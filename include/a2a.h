@@ -187,6 +187,8 @@ typedef struct {
   double ms_schur64; /* best time of the FP64 Schur operator, ms; -1 if cached */
   int candidates;    /* configurations timed (0: taken from the cache) */
   int xcd_slab;      /* matrix-core blocks: 1 in XCD slabs, 0 in brick order, -1 not used */
+  int brick64[3];    /* brick of the FP64 stencils of reliable updates (y, z, t) */
+  int xcd64;         /* FP64 stencil blocks: 1 in XCD slabs, 0 not */
 } a2a_tune_result;
 
 /* Autotune the launch configuration of the batched stencils (the multi-RHS batching of the
@@ -194,8 +196,9 @@ typedef struct {
  * the Schur operator on min(nrhs, 64) sources: first the RHS width (the lane-interleaved group
  * width 16 / 32 / 48 for FP16 / BF16 storage on the matrix cores, else the per-thread width
  * 1 / 2 / 4), then the stencil brick (up to six shapes that tile the lattice) together with
- * the order of the matrix-core blocks over the XCDs (brick order or XCD slabs), then the FP64
- * stencils' width 1 / 2 (FP64 Schur operator on min(nrhs, 24) sources).  The result is kept in
+ * the order of the matrix-core blocks over the XCDs (brick order or XCD slabs), then for the
+ * FP64 stencils of the reliable updates their width 1 / 2 and their own brick and block order
+ * (FP64 Schur operator on min(nrhs, 24) sources).  The result is kept in
  * the context and in the JSON file named by the environment variable A2A_TUNE_CACHE, keyed by
  * arch, lattice, precision and RHS bucket (the next power of two, at most 64); a cached key
  * is returned without timing.  With option "autotune" = 1 solve calls tune on first use of a

@@ -42,11 +42,13 @@ class Geom(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     _fields_ = [("il_width", ctypes.c_int), ("brick", ctypes.c_int * 3), ("rhs_block", ctypes.c_int),
                 ("rhs_block64", ctypes.c_int), ("ms_schur", ctypes.c_double), ("ms_schur64", ctypes.c_double),
-                ("candidates", ctypes.c_int), ("xcd_slab", ctypes.c_int)]
+                ("candidates", ctypes.c_int), ("xcd_slab", ctypes.c_int), ("brick64", ctypes.c_int * 3),
+                ("xcd64", ctypes.c_int)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["brick"] = list(self.brick)
+        d["brick64"] = list(self.brick64)
         return d
 
 

@@ -28,6 +28,7 @@ struct HopArgs {
   int inv;
   int red;
   int brick;          // site blocks are 4D bricks (several RHS groups per block), else linear
+  int by, bz, bt;     // brick extents of this launch (0: the operator's; ignored unless they tile it)
   RedBuf rb;
 };
 

@@ -224,6 +224,10 @@ static int solve_batch(Ctx* c, int clover_h, const double* src, int nrhs, double
     sv.bz = tc.bz;
     sv.bt = tc.bt;
   }
+  sv.by64 = tc.by64;
+  sv.bz64 = tc.bz64;
+  sv.bt64 = tc.bt64;
+  sv.xcd_sub = tc.xcd64;
   sv.method = c->solver;
   const int op = sv.op_index(clover_h, kappa, kop, gf);
   std::vector<Slot> slots(nrhs);
@@ -750,6 +754,7 @@ static int stencil_time(Ctx* c, int clover_h, double kappa, int opk, int prec, i
   A2A_TRY(resolve_op(c, clover_h, kappa, prec, &gf, &cf, &kop));
   Solver sv(c, prec, tc.R ? tc.R : effective_R(c, prec));
   if (tc.slab >= 0) sv.mfma_slab = tc.slab;
+  sv.xcd_hop = tc.xcd64;
   if (tc.by > 0) {
     sv.by = tc.by;
     sv.bz = tc.bz;
@@ -822,8 +827,9 @@ static void tune_save(Ctx* c) {
     const TuneCfg& t = kv.second;
     std::fprintf(f,
                  "%s\n  \"%s\": {\"il_width\": %d, \"by\": %d, \"bz\": %d, \"bt\": %d, \"slab\": %d, \"R\": %d, "
-                 "\"R64\": %d}",
-                 first ? "" : ",", kv.first.c_str(), t.il_width, t.by, t.bz, t.bt, t.slab, t.R, t.R64);
+                 "\"R64\": %d, \"by64\": %d, \"bz64\": %d, \"bt64\": %d, \"xcd64\": %d}",
+                 first ? "" : ",", kv.first.c_str(), t.il_width, t.by, t.bz, t.bt, t.slab, t.R, t.R64, t.by64, t.bz64,
+                 t.bt64, t.xcd64);
     first = false;
   }
   std::fprintf(f, "\n}\n");
@@ -841,13 +847,15 @@ static void tune_load(Ctx* c) {
     TuneCfg t;
     if (std::sscanf(line,
                     " \"%399[^\"]\": {\"il_width\": %d, \"by\": %d, \"bz\": %d, \"bt\": %d, \"slab\": %d, \"R\": %d, "
-                    "\"R64\": %d",
-                    key, &t.il_width, &t.by, &t.bz, &t.bt, &t.slab, &t.R, &t.R64) != 8)
+                    "\"R64\": %d, \"by64\": %d, \"bz64\": %d, \"bt64\": %d, \"xcd64\": %d",
+                    key, &t.il_width, &t.by, &t.bz, &t.bt, &t.slab, &t.R, &t.R64, &t.by64, &t.bz64, &t.bt64,
+                    &t.xcd64) != 12)
       continue;
     const bool ok = (t.il_width == 0 || t.il_width == 16 || t.il_width == 32 || t.il_width == 48) &&
                     (t.R == 0 || t.R == 1 || t.R == 2 || t.R == 4) && (t.R64 == 0 || t.R64 == 1 || t.R64 == 2) &&
                     t.by >= 0 && t.bz >= 0 && t.bt >= 0 && t.by <= 64 && t.bz <= 64 && t.bt <= 64 &&
-                    t.slab >= -1 && t.slab <= 1;
+                    t.slab >= -1 && t.slab <= 1 && t.xcd64 >= -1 && t.xcd64 <= 1 && t.by64 >= 0 && t.bz64 >= 0 &&
+                    t.bt64 >= 0 && t.by64 <= 64 && t.bz64 <= 64 && t.bt64 <= 64;
     if (ok) c->tuned[key] = t;  // a brick that does not tile the lattice is ignored at use
   }
   std::fclose(f);
@@ -879,6 +887,10 @@ static int autotune_cfg(Ctx* c, int clover_h, double kappa, int prec, int nrhs, 
       res->rhs_block = out->R;
       res->rhs_block64 = out->R64;
       res->xcd_slab = out->slab;
+      res->brick64[0] = out->by64 ? out->by64 : out->by;
+      res->brick64[1] = out->by64 ? out->bz64 : out->bz;
+      res->brick64[2] = out->by64 ? out->bt64 : out->bt;
+      res->xcd64 = out->xcd64;
       res->ms_schur = res->ms_schur64 = -1.0;
     }
     return A2A_OK;
@@ -942,18 +954,45 @@ static int autotune_cfg(Ctx* c, int clover_h, double kappa, int prec, int nrhs, 
         best = t;
       }
     }
-  // 3. FP64 stencil width
+  // 3. FP64 stencils: width, then their own brick and tile order over the XCDs
   double t64 = 1e300;
+  const int n64 = std::min(nrhs, 24);
+  TuneCfg b64 = best;
+  b64.il_width = 0;
+  b64.slab = -1;
+  b64.xcd64 = c->xcd_order ? 1 : 0;
   for (int r : {1, 2}) {
-    TuneCfg t = best;
-    t.il_width = 0;
+    TuneCfg t = b64;
     t.R = r;
     double ms = 0;
-    A2A_TRY(timed(0, std::min(nrhs, 24), t, &ms));
+    A2A_TRY(timed(0, n64, t, &ms));
     if (ms < t64) {
       t64 = ms;
-      best.R64 = r;
+      b64.R = r;
     }
+  }
+  const TuneCfg first64 = b64;
+  for (int k = 0; k < nb; ++k)
+    for (int xo = 0; xo < 2; ++xo) {
+      TuneCfg t = first64;
+      t.by = br[k][0];
+      t.bz = br[k][1];
+      t.bt = br[k][2];
+      t.xcd64 = xo;
+      if (t.by == first64.by && t.bz == first64.bz && t.bt == first64.bt && t.xcd64 == first64.xcd64) continue;
+      double ms = 0;
+      A2A_TRY(timed(0, n64, t, &ms));
+      if (ms < t64) {
+        t64 = ms;
+        b64 = t;
+      }
+    }
+  best.R64 = b64.R;
+  best.xcd64 = b64.xcd64;
+  if (b64.by != best.by || b64.bz != best.bz || b64.bt != best.bt) {
+    best.by64 = b64.by;
+    best.bz64 = b64.bz;
+    best.bt64 = b64.bt;
   }
   c->tuned[key] = best;
   tune_save(c);
@@ -967,6 +1006,10 @@ static int autotune_cfg(Ctx* c, int clover_h, double kappa, int prec, int nrhs, 
     res->rhs_block = best.R;
     res->rhs_block64 = best.R64;
     res->xcd_slab = best.slab;
+    res->brick64[0] = best.by64 ? best.by64 : best.by;
+    res->brick64[1] = best.by64 ? best.bz64 : best.bz;
+    res->brick64[2] = best.by64 ? best.bt64 : best.bt;
+    res->xcd64 = best.xcd64;
     res->ms_schur = tbest;
     res->ms_schur64 = t64;
     res->candidates = tried;

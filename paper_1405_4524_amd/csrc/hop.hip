@@ -25,7 +25,12 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
   const int* grp = a.groups + (size_t)tile.x * R;
   const int slot0 = grp[0];
   const OpDev& op = a.ops[a.slots[slot0].op];
-  const Geo g = op.g;
+  Geo g = op.g;
+  if (a.by > 0 && g.Y % a.by == 0 && g.Z % a.bz == 0 && g.T % a.bt == 0) {  // the launch's own brick
+    g.by = (unsigned char)a.by;
+    g.bz = (unsigned char)a.bz;
+    g.bt = (unsigned char)a.bt;
+  }
   const int hv = g.hv;
   const int pos = tile.y * BS + (int)threadIdx.x;  // position in the brick sweep
   const bool valid = pos < hv;

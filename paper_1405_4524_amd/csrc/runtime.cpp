@@ -623,7 +623,7 @@ int Solver::rebuild() {
     for (int b = 0; b < ops[o].nblk; ++b)
       for (int gi = 0; gi < ng; ++gi) htiles.push_back(make_int2(g0 + gi, b));
   }
-  xcd_order(htiles, ctx->xcd_order);
+  xcd_order(htiles, xcd_hop >= 0 ? xcd_hop != 0 : ctx->xcd_order != 0);
   vec_lists(live, ops, every, ctx->xcd_order, vtiles, nonil, ils, ilt);
   // interleaved groups for the matrix-core stencil, and R-groups of the remaining slots
   std::vector<ILGroupDev> ilg;
@@ -726,7 +726,7 @@ int Solver::upload_subset(const std::vector<int>& idx, int R_sub) {
     for (int b = 0; b < ops[o].nblk; ++b)
       for (int gi = 0; gi < ng; ++gi) htiles.push_back(make_int2(g0 + gi, b));
   }
-  xcd_order(htiles, ctx->xcd_order);
+  xcd_order(htiles, xcd_sub >= 0 ? xcd_sub != 0 : ctx->xcd_order != 0);
   vec_lists(live, ops, idx, ctx->xcd_order, vtiles, nonil, ils, ilt);
   // one buffer holds [hop tiles | vec tiles | non-interleaved vec tiles | interleaved tiles]
   A2A_TRY(grow(ctx, (void**)&d_sub_groups, &cap_subg, sizeof(int) * std::max<size_t>(1, groups.size())));
@@ -780,6 +780,11 @@ int Solver::hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par,
   long blocks = 0;  // site blocks of all operators: more tiles means several groups per block
   for (const OpEntry& e : ops) blocks += e.nblk;
   a.brick = n_tiles > blocks;
+  if (psel == 1 && kprec == 0 && by64 > 0) {  // FP64 stencils of setup, reliable updates, reconstruction
+    a.by = by64;
+    a.bz = bz64;
+    a.bt = bt64;
+  }
   a.rb = ctx->redbuf();
   const int c = (cls && cls[0] == '1') ? 0 : 1;
   hipEvent_t ev = nullptr;
@@ -1048,10 +1053,45 @@ int Solver::finalize(const std::vector<int>& idx) {
   return A2A_OK;
 }
 
+// Slots whose iterated residual estimate is below the target: fold the inner correction into
+// x64 and reconstruct, skipping the FP64 Schur residual that a reliable update would compute
+// (the reconstruction's residual of the full system decides convergence).  A slot the full
+// residual does not accept gets its FP64 Schur residual and continues with a tenfold tighter
+// target, like a slot whose reconstruction failed after a reliable update.
+int Solver::finish(const std::vector<int>& fin) {
+  A2A_TRY(upload_subset(fin, 1));
+  A2A_TRY(vec(true, sub_nv, VK_RU_ACCUM));
+  A2A_TRY(finalize(fin));
+  std::vector<int> again;
+  for (int i : fin) {
+    Slot* s = live[i];
+    s->rus++;
+    if (s->info.converged) {
+      s->state = SS_DONE;
+    } else if (s->iters >= s->max_iter) {
+      s->state = SS_FAIL;
+      s->err = A2A_ENOTCONV;
+    } else {
+      again.push_back(i);
+    }
+  }
+  if (again.empty()) return A2A_OK;
+  A2A_TRY(upload_subset(again, R64));
+  A2A_TRY(true_residual(again));
+  A2A_TRY(ctx->read_scal());
+  for (int i : again) {
+    Slot* s = live[i];
+    s->last_r64 = std::sqrt(ctx->scal_host[(size_t)s->sid * NSCAL + SC_R64N2]);
+    s->target *= 0.1;
+  }
+  A2A_TRY(upload_subset(again, 1));
+  return vec(true, sub_nv, init_kind());
+}
+
 // Residual checks, reliable updates, restarts, convergence and retirement.
 int Solver::check() {
   A2A_TRY(ctx->read_scal());
-  std::vector<int> ru, restart;
+  std::vector<int> ru, restart, fin;
   // CGNR with FP16 storage: its iterate accumulates about three times as many FP16-rounded
   // updates between reliable updates as BiCGStab's, so it is flushed at 0.1 like BF16
   const double delta = prec == 0                                 ? ctx->delta_64
@@ -1065,10 +1105,13 @@ int Solver::check() {
     const double est = std::sqrt(sc[SC_RNORM2]) * sc[SC_SIGMA];
     if (sc[SC_FLAGS] != 0.0 || !std::isfinite(est)) {
       restart.push_back(i);
+    } else if (est <= s->target && s->rus > 0 && !ctx->force_breakdown) {
+      fin.push_back(i);  // converged by the estimate: the reconstruction checks the full residual
     } else if (est <= s->target || est <= delta * s->last_r64 || s->iters >= s->max_iter) {
       ru.push_back(i);
     }
   }
+  if (!fin.empty()) A2A_TRY(finish(fin));
   if (ru.empty() && restart.empty()) return A2A_OK;
   std::vector<int> all(ru);
   all.insert(all.end(), restart.begin(), restart.end());

@@ -109,6 +109,8 @@ struct TuneCfg {
   int R = 0;                  // RHS per thread of the per-thread stencil (1, 2 or 4)
   int R64 = 0;                // RHS per thread of the FP64 stencils of reliable updates (1 or 2)
   int slab = -1;              // matrix-core blocks in XCD slabs (1) or in brick order (0); -1: the option
+  int by64 = 0, bz64 = 0, bt64 = 0;  // brick of the FP64 stencils (0: the operators' brick)
+  int xcd64 = -1;             // FP64 stencil tiles in XCD slabs (1) or not (0); -1: the option
 };
 
 struct Solver {
@@ -120,6 +122,9 @@ struct Solver {
   int by = 0, bz = 0, bt = 0;    // brick of the operators this solver creates (0: the lattice's default)
   int mfma_slab = 0;             // matrix-core stencil blocks ordered in XCD slabs
   bool il_nt3 = false;           // every interleaved group has three lane tiles
+  int by64 = 0, bz64 = 0, bt64 = 0;  // brick of the FP64 stencils (reliable updates; 0: the operators')
+  int xcd_hop = -1;              // per-thread stencil tiles of full launches in XCD slabs (1/0; -1: the option)
+  int xcd_sub = -1;              // the same for subset launches (FP64 setup, reliable updates, reconstruction)
   std::vector<OpEntry> ops;
   std::vector<Slot*> live;  // slots in the device tables (running)
   // device tables
@@ -172,6 +177,7 @@ struct Solver {
   int run_steps(int iters);
   int init_kind() const { return method == SOLVER_CGNR ? VK_CG_INIT : VK_INIT; }
   int setup(const std::vector<int>& idx);
+  int finish(const std::vector<int>& fin);
   int check();
   int true_residual(const std::vector<int>& idx);
   int finalize(const std::vector<int>& idx);
