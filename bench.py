@@ -119,6 +119,9 @@ def main():
     ap.add_argument("--serve-leg", default="5,20",
                     help="offered rates of the short serving leg of the default run ('' to skip)")
     ap.add_argument("--serve-leg-requests", type=int, default=40)
+    ap.add_argument("--source-errors", default="",
+                    help="workload whose every source is solved on the GPU (FP16 and BF16 inner) and by the oracle "
+                         "(FP64, tol 1e-12 on the host): per-source propagator error and residual")
     ap.add_argument("--point-study", action="store_true",
                     help="pi-pi diagrams from point and stochastic propagators (4^3x8) against the exact "
                          "diagrams from full dilution, one noise set against two")
@@ -154,6 +157,9 @@ def main():
         return
     if args.point_study:
         point_study(args)
+        return
+    if args.source_errors:
+        source_errors(args)
         return
 
     w = inputs.WORKLOADS[args.workload]
@@ -197,6 +203,7 @@ def main():
         log(f"autotuned: {tuned}")
 
     infos = []
+    last_corr = {}
     phases = ("load_gauge", "load_clover", "solve", "contract", "unload")
 
     def step():
@@ -219,6 +226,7 @@ def main():
         ctx.unload(g)  # the fields' buffers go to the context's reuse cache
         ph["unload"] = time.perf_counter() - t
         infos.append(info)
+        last_corr["pion"], last_corr["pipi"] = corr, diag
         return ph
 
     warm_s = []
@@ -309,7 +317,8 @@ def main():
                        "warmup_median_untimed_kernels": round(1e3 * float(np.median(warm_s)), 1) if warm_s else None,
                        "phases_median": {k: round(1e3 * float(np.median([ph[k] for ph in step_ph])), 1)
                                          for k in phases}},
-           "roofline": roofline, "kernels": kernels}
+           "roofline": roofline, "kernels": kernels,
+           "correlators": correlator_summary(last_corr, T)}
 
     if not args.no_extras:
         ctx.set_option("autotune", 0)  # the side measurements keep their stated widths
@@ -383,6 +392,16 @@ def main():
         del links
         out["cpu_baseline"] = cpu_baseline(w, links_np)
     print(json.dumps(out), flush=True)
+
+
+def correlator_summary(last, T):
+    """Real parts of the last timed step's pion correlator C(dt) and pi-pi pieces D0..D3 (dt <= T/2)."""
+    out = {}
+    if last.get("pion") is not None:
+        out["pion_C"] = [float(f"{v.real:.6e}") for v in last["pion"][:T // 2 + 1]]
+    if last.get("pipi") is not None:
+        out["pipi_D0_D1_D2_D3"] = [[float(f"{v.real:.6e}") for v in d[:T // 2 + 1]] for d in last["pipi"]]
+    return out
 
 
 SERVE_LATTICES = [((8, 8, 8, 16), 11), ((16, 16, 16, 32), 12), ((24, 24, 24, 48), 13)]
@@ -933,6 +952,72 @@ def host_info():
     except OSError:
         pass
     return {"cpu_model": model, "affinity_cores": len(os.sched_getaffinity(0)), "omp_threads": oracle.num_threads()}
+
+
+def source_errors(args):
+    """Every source of one workload, solved on the GPU in the benchmark's configuration (all
+    sources in one call, FP16 and BF16 storage, FP64 reliable updates, tol 1e-10) and by the
+    oracle (FP64 BiCGStab on the full system to 1e-12, host cores): per source, the propagator's
+    relative error ||X - X_O|| / ||X_O||, the residual ||eta - D X|| / ||eta|| recomputed with
+    the oracle's D, and the residual the library reports.  The oracle's inputs are the host
+    generators' (the device noise equals them bitwise, which is checked per source)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1405_4524_amd import a2a, inputs
+
+    w = inputs.WORKLOADS[args.source_errors]
+    dims, tbc, kappa, csw, n = w["dims"], w["tbc"], w["kappa"], w["csw"], w["nsrc"]
+    X, Y, Z, T = dims
+    U = inputs.gauge_field(dims, w["eps"], w["gauge_seed"])
+    ctx = a2a.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+    ctx.set_option("autotune", 1)
+    links = torch.from_numpy(U.view(np.float64)).cuda()
+    g = ctx.load_gauge_dev(links, dims, tbc)
+    c = ctx.load_clover(g, csw)
+    src = torch.empty((n, T, Z, Y, X, 4, 3, 2), dtype=torch.float64, device="cuda")
+    ctx.z2_noise_dev(dims, w["noise_seed"], 0, n, src)
+    sols, infos = {}, {}
+    for name, p in (("f16", a2a.F16_F32), ("bf16", a2a.BF16_F32)):
+        sol = torch.zeros_like(src)
+        t = time.perf_counter()
+        info, _ = ctx.solve_propagators_dev(c, src, sol, n, kappa, csw, tol=w["tol"], prec=p, allow=())
+        torch.cuda.synchronize()
+        log(f"source errors: GPU {name} solve of {n} sources {time.perf_counter() - t:.2f}s")
+        sols[name] = sol.cpu().numpy().view(np.complex128).reshape(n, T, Z, Y, X, 4, 3)
+        infos[name] = info
+        del sol
+    dev_eta = src.cpu().numpy().view(np.complex128).reshape(n, T, Z, Y, X, 4, 3)
+    ctx.unload(g)
+    ctx.finalize()
+    del src, links
+    torch.cuda.empty_cache()
+    A = oracle.clover(U, kappa, csw)
+    rows = []
+    t0 = time.perf_counter()
+    for i in range(n):
+        eta = inputs.z2_noise(dims, 1, w["noise_seed"], src_offset=i)[0]
+        assert np.array_equal(eta, dev_eta[i]), i
+        Xo, io = oracle.solve(U, A, kappa, eta, tbc, tol=1e-12)
+        row = {"source": i, "oracle_iters": int(io[0, 0]), "oracle_residual": float(f"{io[0, 3]:.3e}")}
+        ne = np.linalg.norm(eta)
+        for name in ("f16", "bf16"):
+            Xg = sols[name][i]
+            row[f"{name}_prop_err"] = float(f"{np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo):.3e}")
+            row[f"{name}_residual"] = float(
+                f"{np.linalg.norm(eta - oracle.apply_D(U, A, kappa, Xg, tbc)) / ne:.3e}")
+            row[f"{name}_reported"] = float(f"{infos[name][i]['true_rel_residual']:.3e}")
+            row[f"{name}_iters"] = infos[name][i]["iters"]
+        rows.append(row)
+        log(f"source errors: {row} ({time.perf_counter() - t0:.0f}s)")
+    summary = {}
+    for name in ("f16", "bf16"):
+        e = [r[f"{name}_prop_err"] for r in rows]
+        res = [r[f"{name}_residual"] for r in rows]
+        summary[name] = {"prop_err_max": max(e), "prop_err_median": float(np.median(e)), "residual_max": max(res)}
+    print(json.dumps({"mode": "source_errors", "workload": args.source_errors, "nsrc": n, "tol": w["tol"],
+                      "oracle_tol": 1e-12, "summary": summary, "rows": rows}), flush=True)
 
 
 def cpu_baseline(w, links_np):
