@@ -78,6 +78,11 @@ def main():
                     help="1: FP16/BF16 inner vectors in lane-interleaved groups (matrix-core stencil)")
     ap.add_argument("--mfma", type=int, default=1, help="0: interleaved groups use the per-thread stencil")
     ap.add_argument("--delta", type=float, default=0.03, help="reliable-update reduction factor")
+    ap.add_argument("--target-frac", type=float, default=0.8,
+                    help="Schur-residual target as a fraction of tol ||eta|| (the full residual decides)")
+    ap.add_argument("--tail-checks", type=int, default=1, help="1: residual checks after every iteration in the tail")
+    ap.add_argument("--ru-correction", type=int, default=1,
+                    help="1: reliable updates as r64 -= M (sigma x_lo); 0: r64 = b - M x64 recomputed")
     ap.add_argument("--solver", default="bicgstab", choices=["bicgstab", "cgnr"],
                     help="inner Krylov method (cgnr: CG on the normal equations)")
     ap.add_argument("--fp64-sources", type=int, default=4)
@@ -185,6 +190,9 @@ def main():
     ctx.set_option("interleave", args.interleave)
     ctx.set_option("mfma", args.mfma)
     ctx.set_option("delta", args.delta)
+    ctx.set_option("ru_correction", args.ru_correction)
+    ctx.set_option("target_frac", args.target_frac)
+    ctx.set_option("tail_checks", args.tail_checks)
     ctx.set_option("solver", a2a.SOLVER_CGNR if args.solver == "cgnr" else a2a.SOLVER_BICGSTAB)
 
     if args.stencil_only:

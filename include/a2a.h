@@ -137,7 +137,15 @@ const char *a2a_last_error(const a2a_ctx *ctx);
  * or 48, default 48: RHS per lane-interleaved group), "brick" (by * 10000 + bz * 100 + bt:
  * the stencil brick of later calls on lattices it tiles, 0 = each lattice's default; a brick
  * orders the stencil's sweep only, results are unchanged), "mfma_slab" (0/1, default 0: the
- * matrix-core stencil's blocks in XCD slabs, XCD k taking the k-th eighth of the bricks).
+ * matrix-core stencil's blocks in XCD slabs, XCD k taking the k-th eighth of the bricks),
+ * "ru_correction" (0/1, default 1: mixed-precision reliable updates compute the FP64 residual
+ * as r64 -= M (sigma x_lo) from the stored low-precision correction, in FP64 arithmetic; 0
+ * recomputes r64 = b - M x64 from the FP64 iterate), "target_frac" (in (0, 1], default 0.8: a
+ * source's iteration stops when its odd-site Schur residual reaches target_frac tol ||eta||;
+ * the reconstruction then computes the full-system FP64 residual, which decides convergence,
+ * and a source it does not accept continues with a tenfold tighter target), "tail_checks" (0/1,
+ * default 1: once at most a quarter of the most sources a solve has run at once are still
+ * iterating, their residuals are checked after every iteration instead of every check_every).
  * Returns A2A_EINVAL for an unknown key. */
 int a2a_set_option(a2a_ctx *ctx, const char *key, double value);
 /* Bytes of device memory in the context's live buffers.  Freed buffers are kept for reuse

@@ -29,6 +29,9 @@ struct HopArgs {
   int red;
   int brick;          // site blocks are 4D bricks (several RHS groups per block), else linear
   int by, bz, bt;     // brick extents of this launch (0: the operator's; ignored unless they tile it)
+  // FP64 stencils only: 1 = vin, 2 = vaux2 is the slot's inner (low-precision) vector, in the
+  // inner storage lo_prec (1 FP32, 2 FP16, 3 BF16), times the slot's scale sigma
+  int lo_mask, lo_prec;
   RedBuf rb;
 };
 
@@ -75,6 +78,7 @@ enum VecKind {
   VK_CG_P,          // p = gamma5 u + beta p  (u = M r')
   VK_CG_INIT,       // r' = gamma5 r64/sigma; p = x_lo = 0 -> RED_CG_INIT
   VK_CG_RESCALE,    // r' = gamma5 r64/sigma'; p *= sigma/sigma' -> RED_CG_RU
+  VK_COPY_HI,       // hi[vout] = hi[vin]
 };
 
 struct VecArgs {
@@ -85,7 +89,7 @@ struct VecArgs {
   int kind;
   int par;        // parity for VK_CLOVER
   int use_inv;    // VK_CLOVER: 1 -> A^{-1}
-  int vin, vout;  // VK_CLOVER / VK_ZERO_HI; vin >= 0: FP64 residual source of the INIT / RESCALE kinds
+  int vin, vout;  // VK_CLOVER / VK_ZERO_HI / VK_COPY_HI; vin >= 0: FP64 residual source of the INIT / RESCALE kinds
   RedBuf rb;
 };
 
@@ -109,6 +113,9 @@ void launch_finalize(int kind, const OpDev* ops, const SlotDev* slots, const int
                      hipStream_t s);
 
 void launch_hop(int prec, int R, const HopArgs& a, int ntiles, hipStream_t s);
+// the FP64 correction-form variants (HopArgs::lo_mask): first stencil EPI_INV with the hopping
+// input from the inner arena, second EPI_CLOV with the clover input from it; R = 1 or 2
+bool hop_lo_supports(int R, int lo_mask, int lo_prec, int inv, bool clov);
 // o = gam H in (+ cb A aux2) (then A^{-1} .) for every lane of the groups, on the matrix
 // cores; reduction kinds NONE, ALPHA and OMEGA (with the clover term); no axpy term
 bool hop_mfma_supports(int prec, int inv, bool clov, int red, bool aux1);

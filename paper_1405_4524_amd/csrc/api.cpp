@@ -551,6 +551,13 @@ extern "C" int a2a_set_option(a2a_ctx* h, const char* key, double v) {
     c->autotune = v != 0;
   } else if (k == "mfma_slab") {
     c->mfma_slab = v != 0;
+  } else if (k == "ru_correction") {
+    c->ru_correction = v != 0;
+  } else if (k == "tail_checks") {
+    c->tail_checks = v != 0;
+  } else if (k == "target_frac") {
+    if (!(v > 0.0 && v <= 1.0)) return c->fail(A2A_EINVAL, "target_frac must be in (0, 1]");
+    c->target_frac = v;
   } else if (k == "il_width") {
     if (v != 16 && v != 32 && v != 48) return c->fail(A2A_EINVAL, "il_width must be 16, 32 or 48");
     c->il_width = (int)v;

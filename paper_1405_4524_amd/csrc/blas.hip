@@ -207,6 +207,10 @@ __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, in
 #pragma unroll
     for (int k = 0; k < 12; ++k) z.v[k] = mk(0.0, 0.0);
     store_spinor<double, double>(HI(a.vout), hv, site, z);
+  } else if (KIND == VK_COPY_HI) {
+    Spinor<double> z;
+    load_spinor<double, double>(HI(a.vin), hv, site, z);
+    store_spinor<double, double>(HI(a.vout), hv, site, z);
   } else if (KIND == VK_ZERO_LO || KIND == VK_FILL_LO) {
     Spinor<A> z;
     uint32_t h = (uint32_t)site * 2654435761u + (uint32_t)sd.sid * 40503u + 12345u;
@@ -338,6 +342,7 @@ static void launch_vec_p(const VecArgs& a, int n, hipStream_t s) {
     case VK_INIT: hipLaunchKernelGGL((k_vec<P, VK_INIT>), g, b, 0, s, a); break;
     case VK_CLOVER: hipLaunchKernelGGL((k_vec<P, VK_CLOVER>), g, b, 0, s, a); break;
     case VK_ZERO_HI: hipLaunchKernelGGL((k_vec<P, VK_ZERO_HI>), g, b, 0, s, a); break;
+    case VK_COPY_HI: hipLaunchKernelGGL((k_vec<P, VK_COPY_HI>), g, b, 0, s, a); break;
     case VK_ZERO_X: hipLaunchKernelGGL((k_vec<P, VK_ZERO_X>), g, b, 0, s, a); break;
     case VK_ZERO_LO: hipLaunchKernelGGL((k_vec<P, VK_ZERO_LO>), g, b, 0, s, a); break;
     case VK_FILL_LO: hipLaunchKernelGGL((k_vec<P, VK_FILL_LO>), g, b, 0, s, a); break;

@@ -17,7 +17,10 @@ namespace a2a {
 
 enum { EPI_PLAIN = 0, EPI_CLOV = 1, EPI_INV = 2 };
 
-template <class P, int R, int EPI>
+// LOM (FP64 stencils of the correction-form reliable update): 1 = the hopping input, 2 = the
+// clover input aux2 is the slot's inner vector in storage SI, scaled by the slot's sigma (the
+// inner vectors hold the true vector / sigma), read through the slot's inner layout.
+template <class P, int R, int EPI, int LOM = 0, typename SI = typename P::S>
 __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
   using S = typename P::S;
   using A = typename P::A;
@@ -38,13 +41,17 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
   const int sel = a.psel;
   const int po = a.out_par, pi = 1 - po;
 
-  VView w[R];
+  VView w[R], wl[R];
+  A sgm[R];  // the slot's sigma for LOM terms
   bool on[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     int sl = grp[r];
     on[r] = sl >= 0;
-    w[r] = view_of(a.slots[on[r] ? sl : slot0], sel, hv);
+    const SlotDev& sd = a.slots[on[r] ? sl : slot0];
+    w[r] = view_of(sd, sel, hv);
+    wl[r] = lo_view(sd);
+    sgm[r] = LOM != 0 ? (A)sd.scal[SC_SIGMA] : (A)1;
   }
 
   Spinor<A> acc[R];
@@ -70,7 +77,10 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
         for (int r = 0; r < R; ++r) {
           if (!on[r]) continue;
           Spinor<A> p;
-          vload<S, A>(w[r], a.vin, nf, p);
+          if (LOM == 1)
+            vload<SI, A>(wl[r], a.vin, nf, p);
+          else
+            vload<S, A>(w[r], a.vin, nf, p);
           cx<A> h[6], uh[6];
           project(mu, 1, p, h);
           su3_mul_half(U, h, uh);
@@ -86,7 +96,10 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
         for (int r = 0; r < R; ++r) {
           if (!on[r]) continue;
           Spinor<A> p;
-          vload<S, A>(w[r], a.vin, nb, p);
+          if (LOM == 1)
+            vload<SI, A>(wl[r], a.vin, nb, p);
+          else
+            vload<S, A>(w[r], a.vin, nb, p);
           cx<A> h[6], uh[6];
           project(mu, 0, p, h);
           su3_dag_mul_half(U, h, uh);
@@ -105,8 +118,9 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (!on[r]) continue;
+      const A gr = LOM == 1 ? gam * sgm[r] : gam;
 #pragma unroll
-      for (int k = 0; k < 12; ++k) acc[r].v[k] = gam * acc[r].v[k];
+      for (int k = 0; k < 12; ++k) acc[r].v[k] = gr * acc[r].v[k];
       if (a.vaux1 >= 0) {
         Spinor<A> x1;
         vload<S, A>(w[r], a.vaux1, site, x1);
@@ -126,12 +140,16 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
           cx<A> i6[6], o6[6];
           if (EPI == EPI_CLOV) {
             Spinor<A> x2;
-            vload<S, A>(w[r], a.vaux2, site, x2);
+            if (LOM == 2)
+              vload<SI, A>(wl[r], a.vaux2, site, x2);
+            else
+              vload<S, A>(w[r], a.vaux2, site, x2);
+            const A cr = LOM == 2 ? cbv * sgm[r] : cbv;
 #pragma unroll
             for (int k = 0; k < 6; ++k) i6[k] = x2.v[b * 6 + k];
             clover_apply_block(blk, i6, o6);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) acc[r].v[b * 6 + k] = acc[r].v[b * 6 + k] + cbv * o6[k];
+            for (int k = 0; k < 6; ++k) acc[r].v[b * 6 + k] = acc[r].v[b * 6 + k] + cr * o6[k];
           } else {
 #pragma unroll
             for (int k = 0; k < 6; ++k) i6[k] = acc[r].v[b * 6 + k];
@@ -213,8 +231,49 @@ static void launch_hop_p(int R, const HopArgs& a, int ntiles, hipStream_t s) {
   }
 }
 
+// FP64 stencils of the correction-form reliable update: inputs from the inner arena
+template <int R, int LOM, typename SI>
+static void launch_hop_lo_r(const HopArgs& a, int ntiles, hipStream_t s) {
+  if (LOM == 1)
+    hipLaunchKernelGGL((k_hop<PrecF64, R, EPI_INV, 1, SI>), dim3(ntiles), dim3(BS), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_hop<PrecF64, R, EPI_CLOV, 2, SI>), dim3(ntiles), dim3(BS), 0, s, a);
+}
+
+template <typename SI>
+static void launch_hop_lo_s(int R, const HopArgs& a, int ntiles, hipStream_t s) {
+  const bool first = a.lo_mask == 1;
+  if (R == 1) {
+    if (first)
+      launch_hop_lo_r<1, 1, SI>(a, ntiles, s);
+    else
+      launch_hop_lo_r<1, 2, SI>(a, ntiles, s);
+  } else {
+    if (first)
+      launch_hop_lo_r<2, 1, SI>(a, ntiles, s);
+    else
+      launch_hop_lo_r<2, 2, SI>(a, ntiles, s);
+  }
+}
+
+bool hop_lo_supports(int R, int lo_mask, int lo_prec, int inv, bool clov) {
+  if (R != 1 && R != 2) return false;
+  if (lo_prec < 1 || lo_prec > 3) return false;
+  return (lo_mask == 1 && inv && !clov) || (lo_mask == 2 && !inv && clov);
+}
+
 void launch_hop(int prec, int R, const HopArgs& a, int ntiles, hipStream_t s) {
   if (ntiles <= 0) return;
+  if (a.lo_mask) {  // FP64 arithmetic, inner-arena inputs (checked by the caller with hop_lo_supports)
+    if (prec != 0) return;
+    switch (a.lo_prec) {
+      case 1: launch_hop_lo_s<float>(R, a, ntiles, s); break;
+      case 2: launch_hop_lo_s<_Float16>(R, a, ntiles, s); break;
+      case 3: launch_hop_lo_s<bf16_t>(R, a, ntiles, s); break;
+      default: break;
+    }
+    return;
+  }
   switch (prec) {
     case 0: launch_hop_p<PrecF64>(R, a, ntiles, s); break;
     case 1: launch_hop_p<PrecF32>(R, a, ntiles, s); break;

@@ -758,7 +758,7 @@ int Solver::finalize_red(bool sub, int kind) {
 
 int Solver::hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par, int vin, int vout, int vaux1,
                 int vaux2, int vrhat, double ca, double cb, double gsign, int gpow, int inv, int red,
-                const char* cls, int fin) {
+                const char* cls, int fin, int lo_mask) {
   HopArgs a{};
   a.ops = d_ops;
   a.slots = d_slots;
@@ -780,6 +780,8 @@ int Solver::hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par,
   long blocks = 0;  // site blocks of all operators: more tiles means several groups per block
   for (const OpEntry& e : ops) blocks += e.nblk;
   a.brick = n_tiles > blocks;
+  a.lo_mask = lo_mask;
+  a.lo_prec = prec;
   if (psel == 1 && kprec == 0 && by64 > 0) {  // FP64 stencils of setup, reliable updates, reconstruction
     a.by = by64;
     a.bz = bz64;
@@ -972,6 +974,20 @@ int Solver::true_residual(const std::vector<int>& idx) {
   return A2A_OK;
 }
 
+// FP64, correction form: r64 -= M (sigma x_lo) for a subset whose inner iterate x_lo holds the
+// correction since the last FP64 residual (x64 not yet updated): te = A_ee^{-1} H_eo (sigma
+// x_lo), r64 = r64 + kappa^2 H_oe te - A_oo (sigma x_lo), |r64|^2.  The stencils read the
+// stored low-precision correction (its values are exact in FP64) and compute in FP64, so r64
+// stays the FP64 residual of x64 + sigma x_lo up to FP64 rounding, at a quarter of the bytes of
+// the hopping input.  The caller folds x_lo into x64 afterwards.
+int Solver::true_residual_corr(const std::vector<int>& idx) {
+  (void)idx;
+  A2A_TRY(hop(true, sub_nh, R64, 1, 0, 0, VL_X, VH_TE, -1, -1, -1, 0, 0, 1.0, 0, 1, RED_NONE, nullptr, -1, 1));
+  A2A_TRY(hop(true, sub_nh, R64, 1, 0, 1, VH_TE, VH_R, VH_R, VL_X, -1, 1.0, -1.0, 1.0, 2, 0, RED_R64, nullptr, -1,
+              2));
+  return A2A_OK;
+}
+
 // Prepare new slots: eta -> even-odd FP64, b = eta_o + kappa H_oe A_ee^{-1} eta_e, x64 = x0 or 0,
 // r64 = b - M x64, inner state.  Marks zero / non-finite sources.
 int Solver::setup(const std::vector<int>& idx) {
@@ -998,6 +1014,7 @@ int Solver::setup(const std::vector<int>& idx) {
   A2A_TRY(hop(true, nh, R64, 1, 0, 1, VH_TE, VH_BHAT, VH_ETA_O, -1, -1, 1.0, 0, 1.0, 1, 0,
               zero_x0 ? RED_R64 : RED_NONE, nullptr));
   A2A_TRY(vec(true, nv, VK_ZERO_HI, 0, 0, -1, VH_X));
+  if (zero_x0) A2A_TRY(vec(true, nv, VK_COPY_HI, 0, 0, VH_BHAT, VH_R));  // r64 = b - M 0, kept current
   if (!zero_x0) {
     A2A_TRY(upload_subset(with_x0, 1));
     A2A_TRY(layout_in(true, sub_nv, 1, 1, 0, VH_TE, VH_X, 0, RED_NONE));
@@ -1016,7 +1033,10 @@ int Solver::setup(const std::vector<int>& idx) {
       continue;
     }
     s->eta_norm = std::sqrt(e2);
-    s->target = 0.5 * s->tol * s->eta_norm;
+    // the Schur residual b - M x_o equals the full-system residual once x_e is reconstructed
+    // (the even part vanishes up to rounding); the fraction leaves room for that rounding and
+    // for the drift of the iterated estimate, and the reconstruction's residual decides
+    s->target = ctx->target_frac * s->tol * s->eta_norm;
     s->last_r64 = std::sqrt(r2);
     s->state = SS_RUN;
   }
@@ -1119,12 +1139,29 @@ int Solver::check() {
     A2A_TRY(upload_subset(restart, 1));
     A2A_TRY(vec(true, sub_nv, VK_ZERO_X));
   }
-  if (!ru.empty()) {
-    A2A_TRY(upload_subset(ru, 1));
-    A2A_TRY(vec(true, sub_nv, VK_RU_ACCUM));
+  // reliable updates in correction form (mixed precision): r64 -= M (sigma x_lo), then x64 +=
+  // sigma x_lo; restarts (and the FP64-only mode) recompute r64 = b - M x64 from x64
+  const bool corr = prec != 0 && ctx->ru_correction && hop_lo_supports(R64, 1, prec, 1, false) &&
+                    hop_lo_supports(R64, 2, prec, 0, true);
+  if (corr) {
+    if (!restart.empty()) {
+      A2A_TRY(upload_subset(restart, R64));
+      A2A_TRY(true_residual(restart));
+    }
+    if (!ru.empty()) {
+      A2A_TRY(upload_subset(ru, R64));
+      A2A_TRY(true_residual_corr(ru));
+      A2A_TRY(upload_subset(ru, 1));
+      A2A_TRY(vec(true, sub_nv, VK_RU_ACCUM));
+    }
+  } else {
+    if (!ru.empty()) {
+      A2A_TRY(upload_subset(ru, 1));
+      A2A_TRY(vec(true, sub_nv, VK_RU_ACCUM));
+    }
+    A2A_TRY(upload_subset(all, R64));
+    A2A_TRY(true_residual(all));
   }
-  A2A_TRY(upload_subset(all, R64));
-  A2A_TRY(true_residual(all));
   A2A_TRY(ctx->read_scal());
   std::vector<int> done, rescale, reinit;
   for (int i : all) {
@@ -1214,13 +1251,18 @@ int Solver::retire() {
 
 // Up to `iters` steps of every live slot, with residual checks every check_every steps and
 // after the last; stops early when no slot is left.
+// Residual checks every check_every iterations; in the tail of a batch (at most a quarter of
+// the most slots this solver has run at once still live) after every iteration, so that the
+// last sources, which keep their whole lane groups busy, stop as soon as they converge.
 int Solver::run_steps(int iters) {
   A2A_TRY(retire());
   for (int k = 1; k <= iters && !live.empty(); ++k) {
     A2A_TRY(rebuild());
+    peak_live = std::max(peak_live, live.size());
     if (method == SOLVER_CGNR) A2A_TRY(cg_direction());
     A2A_TRY(iteration());
-    if (k % ctx->check_every == 0 || k == iters) {
+    const bool tail = ctx->tail_checks && 4 * live.size() <= peak_live;
+    if (k % ctx->check_every == 0 || k == iters || tail) {
       A2A_TRY(check());
       A2A_TRY(retire());
       A2A_TRY(rebuild());

@@ -123,6 +123,7 @@ struct Solver {
   int mfma_slab = 0;             // matrix-core stencil blocks ordered in XCD slabs
   bool il_nt3 = false;           // every interleaved group has three lane tiles
   int by64 = 0, bz64 = 0, bt64 = 0;  // brick of the FP64 stencils (reliable updates; 0: the operators')
+  size_t peak_live = 0;          // most slots live at once (tail checks)
   int xcd_hop = -1;              // per-thread stencil tiles of full launches in XCD slabs (1/0; -1: the option)
   int xcd_sub = -1;              // the same for subset launches (FP64 setup, reliable updates, reconstruction)
   std::vector<OpEntry> ops;
@@ -168,7 +169,8 @@ struct Solver {
   // kernel sequences
   int hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par, int vin, int vout, int vaux1, int vaux2,
           int vrhat, double ca, double cb, double gsign, int gpow, int inv, int red, const char* cls,
-          int fin = -1);  // fin: finalize kind of the reduction (default: red itself)
+          int fin = -1,    // fin: finalize kind of the reduction (default: red itself)
+          int lo_mask = 0);  // FP64 correction-form stencils: inputs from the inner arena
   int vec(bool sub, int n_tiles, int kind, int par = 0, int use_inv = 0, int vin = -1, int vout = -1);
   int layout_in(bool sub, int n_tiles, int which_in, int psel, int kprec, int ve, int vo, int g5, int red);
   int layout_out(bool sub, int n_tiles, int psel, int kprec, int ve, int vo, int g5);
@@ -180,6 +182,7 @@ struct Solver {
   int finish(const std::vector<int>& fin);
   int check();
   int true_residual(const std::vector<int>& idx);
+  int true_residual_corr(const std::vector<int>& idx);
   int finalize(const std::vector<int>& idx);
   int run_until_done(int max_outer_iters);
   int retire();
@@ -234,6 +237,9 @@ struct Ctx {
   int il_width = IL_LANES;           // RHS per interleaved group (16, 32 or 48)
   int brick_by = 0, brick_bz = 0, brick_bt = 0;  // option "brick": stencil brick of new solvers (0: default)
   int mfma_slab = 0;                 // option "mfma_slab": matrix-core blocks in XCD slabs
+  int ru_correction = 1;             // option "ru_correction": reliable updates as r64 -= M (sigma x_lo)
+  double target_frac = 0.8;          // option "target_frac": Schur-residual target / (tol ||eta||)
+  int tail_checks = 1;               // option "tail_checks": check every iteration in a batch's tail
   std::map<std::string, TuneCfg> tuned;  // tune key -> launch configuration
   std::string tune_path;             // A2A_TUNE_CACHE: JSON file of tuned configurations
   // reduction scratch

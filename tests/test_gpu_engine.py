@@ -455,3 +455,33 @@ def test_failures_do_not_affect_co_scheduled_work(ctx, orc, fields):
     for i in (0, 2):
         r = mixed[i] - orc.apply_D(f0["U"], A, 0.124, X[i], -1)
         assert np.linalg.norm(r) / np.linalg.norm(mixed[i]) <= 1e-10
+
+
+@pytest.mark.parametrize("prec,nsrc", [(2, 20), (2, 5), (3, 16), (1, 4)])
+def test_reliable_update_correction_form(ctx, orc, fields, prec, nsrc):
+    """Reliable updates in correction form (r64 -= M (sigma x_lo) from the stored low-precision
+    correction, FP64 arithmetic; the default) and recomputed from the FP64 iterate (r64 = b -
+    M x64) both solve to 1e-10 with the oracle's D, with agreeing solutions (FP16 in a lane-
+    interleaved group and per slot, BF16, FP32)."""
+    from paper_1405_4524_amd import a2a
+
+    f = fields[1]
+    print(f"[gpu] reliable-update forms prec={prec} nsrc={nsrc}", flush=True)
+    eta = inputs.z2_noise(f["dims"], nsrc, seed=71)
+    A = orc.clover(f["U"], 0.126, 1.5)
+    out = {}
+    for form in (1, 0):
+        ctx.set_option("ru_correction", form)
+        try:
+            X, info, rc = ctx.solve_propagators(f["c"], eta, 0.126, 1.5, tol=1e-10, prec=prec)
+        finally:
+            ctx.set_option("ru_correction", 1)
+        assert rc == 0
+        assert all(x["reliable_updates"] >= 1 for x in info)
+        for i in range(nsrc):
+            res = eta[i] - orc.apply_D(f["U"], A, 0.126, X[i], -1)
+            r = np.linalg.norm(res) / np.linalg.norm(eta[i])
+            assert r <= 1e-10, (form, i, r)
+            assert abs(r - info[i]["true_rel_residual"]) < 1e-13, (form, i, r, info[i])
+        out[form] = X
+    assert rel(out[1], out[0]) < 1e-8
