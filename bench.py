@@ -38,12 +38,10 @@ STORAGE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
 # HBM bytes per launch of the dominant stencil from two rocprofv3 counter passes (FETCH_SIZE,
 # WRITE_SIZE; KiB per dispatch), scaled by what the same counters read for a plain 1 GiB device
 # copy (fetch x2.0, write x1.0). Valid only for the kernel sources they were taken on (hash of the
-# stencil's sources) and for the same workload, precision, RHS block and kernel class.
+# stencil's sources) and for the same workload, precision, layout and kernel class.
 TRAFFIC = {
-    ("schur2", "l32t64", "f16", "rb2"): {"src": "9435349907081240", "bytes": 1.3538e10,
-                                         "profile": "profiles/bench_l32t64_f16_rb2_hbm_counters.txt"},
-    ("schur2", "l32t64", "f16", "il"): {"src": "6019d7b89fbc2b12", "bytes": 1.6062e+10,
-                                        "profile": "profiles/bench_l32t64_f16_interleaved_hbm_counters.txt"},
+    ("schur2", "l32t64", "f16", "il"): {"src": "db1a19ecf26a9190", "bytes": 1.7398e10,
+                                        "profile": "profiles/bench_l32t64_f16_hbm_counters.txt"},
 }
 STENCIL_SOURCES = {"per-thread": ("hop.hip", "a2a_device.h", "a2a_reduce.h", "a2a_kernels.h"),
                    "mfma": ("hop_mfma.hip", "a2a_device.h", "a2a_reduce.h", "a2a_kernels.h")}
