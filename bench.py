@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--target-frac", type=float, default=0.8,
                     help="Schur-residual target as a fraction of tol ||eta|| (the full residual decides)")
     ap.add_argument("--tail-checks", type=int, default=1, help="1: residual checks after every iteration in the tail")
+    ap.add_argument("--schur-sym", type=int, default=1, help="1: BiCGStab on the symmetric Schur form")
     ap.add_argument("--ru-correction", type=int, default=1,
                     help="1: reliable updates as r64 -= M (sigma x_lo); 0: r64 = b - M x64 recomputed")
     ap.add_argument("--solver", default="bicgstab", choices=["bicgstab", "cgnr"],
@@ -191,6 +192,7 @@ def main():
     ctx.set_option("ru_correction", args.ru_correction)
     ctx.set_option("target_frac", args.target_frac)
     ctx.set_option("tail_checks", args.tail_checks)
+    ctx.set_option("schur_sym", args.schur_sym)
     ctx.set_option("solver", a2a.SOLVER_CGNR if args.solver == "cgnr" else a2a.SOLVER_BICGSTAB)
 
     if args.stencil_only:

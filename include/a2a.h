@@ -145,7 +145,11 @@ const char *a2a_last_error(const a2a_ctx *ctx);
  * the reconstruction then computes the full-system FP64 residual, which decides convergence,
  * and a source it does not accept continues with a tenfold tighter target), "tail_checks" (0/1,
  * default 1: once at most a quarter of the most sources a solve has run at once are still
- * iterating, their residuals are checked after every iteration instead of every check_every).
+ * iterating, their residuals are checked after every iteration instead of every check_every),
+ * "schur_sym" (0/1, default 1: BiCGStab iterates the symmetric Schur form
+ * 1 - kappa^2 A_oo^{-1} H_oe A_ee^{-1} H_eo on A_oo^{-1} b, which has the same solution; the FP64
+ * residuals, reliable updates and reconstruction stay in the form A_oo - kappa^2 H_oe A_ee^{-1}
+ * H_eo; CGNR always uses that form).
  * Returns A2A_EINVAL for an unknown key. */
 int a2a_set_option(a2a_ctx *ctx, const char *key, double value);
 /* Bytes of device memory in the context's live buffers.  Freed buffers are kept for reuse

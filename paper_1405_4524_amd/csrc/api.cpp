@@ -553,6 +553,8 @@ extern "C" int a2a_set_option(a2a_ctx* h, const char* key, double v) {
     c->mfma_slab = v != 0;
   } else if (k == "ru_correction") {
     c->ru_correction = v != 0;
+  } else if (k == "schur_sym") {
+    c->schur_sym = v != 0;
   } else if (k == "tail_checks") {
     c->tail_checks = v != 0;
   } else if (k == "target_frac") {

@@ -15,7 +15,8 @@
 
 namespace a2a {
 
-enum { EPI_PLAIN = 0, EPI_CLOV = 1, EPI_INV = 2 };
+// EPI_INVA: o = aux2 + A^{-1} (gam H in), the symmetric Schur operator's second stencil
+enum { EPI_PLAIN = 0, EPI_CLOV = 1, EPI_INV = 2, EPI_INVA = 3 };
 
 // LOM (FP64 stencils of the correction-form reliable update): 1 = the hopping input, 2 = the
 // clover input aux2 is the slot's inner vector in storage SI, scaled by the slot's sigma (the
@@ -130,6 +131,12 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
     }
     if (EPI != EPI_PLAIN) {
       const void* cbase = (EPI == EPI_CLOV) ? op.A[sel][po] : op.Ai[sel][po];
+      Spinor<A> x3[R];  // EPI_INVA: the identity term
+      if (EPI == EPI_INVA) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (on[r]) vload<S, A>(w[r], a.vaux2, site, x3[r]);
+      }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         A blk[36];
@@ -155,7 +162,7 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
             for (int k = 0; k < 6; ++k) i6[k] = acc[r].v[b * 6 + k];
             clover_apply_block(blk, i6, o6);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) acc[r].v[b * 6 + k] = o6[k];
+            for (int k = 0; k < 6; ++k) acc[r].v[b * 6 + k] = EPI == EPI_INVA ? x3[r].v[b * 6 + k] + o6[k] : o6[k];
           }
         }
       }
@@ -213,7 +220,9 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
 template <class P, int R>
 static void launch_hop_r(const HopArgs& a, int ntiles, hipStream_t s) {
   const bool clov = (a.vaux2 >= 0 && a.cb != 0.0);
-  if (a.inv)
+  if (a.inv == 2)
+    hipLaunchKernelGGL((k_hop<P, R, EPI_INVA>), dim3(ntiles), dim3(BS), 0, s, a);
+  else if (a.inv)
     hipLaunchKernelGGL((k_hop<P, R, EPI_INV>), dim3(ntiles), dim3(BS), 0, s, a);
   else if (clov)
     hipLaunchKernelGGL((k_hop<P, R, EPI_CLOV>), dim3(ntiles), dim3(BS), 0, s, a);

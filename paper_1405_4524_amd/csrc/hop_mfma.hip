@@ -190,7 +190,7 @@ __device__ __forceinline__ void load_tile(TileIn& d, const char* vin, const char
 #pragma unroll
   for (int kt = 0; kt < 6; ++kt) d.B[kt] = gld4(vin + ((long long)nbs[kt] * NT + nt) * 768 + hoff[kt]);
   const long long own = ((long long)site * NT + nt) * 768 + (gq < 3 ? gq : 0) * 256 + n * 16;
-  if (EPI == 1) d.Bc = gld4(vaux2 + own);
+  if (EPI == 1 || EPI == 3) d.Bc = gld4(vaux2 + own);
   if (RED == RED_ALPHA) d.Bx = gld4(vrh + own);
 }
 
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void
   const float cbv = (float)a.cb;
 
   const char* hl = (const char*)op.HL[po];
-  const char* cf = (const char*)(EPI == 2 ? op.AIF[po] : op.AF[po]);
+  const char* cf = (const char*)(EPI >= 2 ? op.AIF[po] : op.AF[po]);
   const long long vs = grp.vs;
   const char* vin = grp.base + (long long)a.vin * vs;
   char* vout = grp.base + (long long)a.vout * vs;
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void
         v1[r] += cbv * c1[r];
       }
     }
-    if (EPI == 2) {  // o = A^{-1} (.): transpose the rounded result through LDS, second product
+    if (EPI == 2 || EPI == 3) {  // o = A^{-1} (.): transpose the rounded result through LDS, second product
       tr2[gq] = make_uint2(M::pack2(v0[0], v0[1]), M::pack2(v0[2], v0[3]));
       tr2[4 + gq] = gq < 2 ? make_uint2(M::pack2(v1[0], v1[1]), M::pack2(v1[2], v1[3])) : make_uint2(0, 0);
       wave_lds_sync();
@@ -421,6 +421,20 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void
         v0[r] = c0[r];
         v1[r] = c1[r];
       }
+    }
+    if (EPI == 3) {  // o = aux2 + A^{-1} (.): the site's aux2 chunk to output rows through LDS
+      trb[w][n][gq] = cur.Bc;
+      wave_lds_sync();
+      const uint2 a0 = tr2[gq], a1 = tr2[4 + gq];
+      wave_lds_sync();
+      v0[0] += M::lo(a0.x);
+      v0[1] += M::hi(a0.x);
+      v0[2] += M::lo(a0.y);
+      v0[3] += M::hi(a0.y);
+      v1[0] += M::lo(a1.x);
+      v1[1] += M::hi(a1.x);
+      v1[2] += M::lo(a1.y);
+      v1[3] += M::hi(a1.y);
     }
     // rows 16 m + 4 gq .. +3 of row tile m, rounded to the storage format
     const uint2 q0 = make_uint2(M::pack2(v0[0], v0[1]), M::pack2(v0[2], v0[3]));
@@ -510,7 +524,14 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 template <class P, bool NT3>
 static void launch_mfma_nt(const HopMArgs& a, int ntiles, int epi, hipStream_t s) {
   const dim3 g(ntiles), b(BS);
-  if (epi == 2) {
+  if (epi == 3) {
+    if (a.red == RED_ALPHA)
+      hipLaunchKernelGGL((k_hop_mfma<P, 3, RED_ALPHA, NT3>), g, b, 0, s, a);
+    else if (a.red == RED_OMEGA)
+      hipLaunchKernelGGL((k_hop_mfma<P, 3, RED_OMEGA, NT3>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_hop_mfma<P, 3, RED_NONE, NT3>), g, b, 0, s, a);
+  } else if (epi == 2) {
     hipLaunchKernelGGL((k_hop_mfma<P, 2, RED_NONE, NT3>), g, b, 0, s, a);
   } else if (epi == 1) {
     if (a.red == RED_ALPHA)
@@ -534,6 +555,7 @@ static void launch_mfma_p(const HopMArgs& a, int ntiles, int epi, hipStream_t s)
 
 bool hop_mfma_supports(int prec, int inv, bool clov, int red, bool aux1) {
   if ((prec != 2 && prec != 3) || aux1) return false;
+  if (inv == 2) return red == RED_NONE || red == RED_ALPHA || red == RED_OMEGA;
   if (inv) return red == RED_NONE;
   if (clov) return red == RED_NONE || red == RED_ALPHA || red == RED_OMEGA;
   return red == RED_NONE;
@@ -541,7 +563,7 @@ bool hop_mfma_supports(int prec, int inv, bool clov, int red, bool aux1) {
 
 void launch_hop_mfma(int prec, const HopMArgs& a, int ntiles, int inv, bool clov, hipStream_t s) {
   if (ntiles <= 0) return;
-  const int epi = inv ? 2 : clov ? 1 : 0;
+  const int epi = inv == 2 ? 3 : inv ? 2 : clov ? 1 : 0;
   if (prec == 2) launch_mfma_p<PrecF16>(a, ntiles, epi, s);
   if (prec == 3) launch_mfma_p<PrecB16>(a, ntiles, epi, s);
 }

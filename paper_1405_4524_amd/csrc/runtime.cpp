@@ -943,13 +943,15 @@ int Solver::iteration() {
     for (Slot* s : live) s->iters++;
     return A2A_OK;
   }
-  // v = M p
+  // v = M p (asymmetric: A_oo p - kappa^2 H_oe te; symmetric: p - kappa^2 A_oo^{-1} H_oe te), te =
+  // A_ee^{-1} H_eo p
+  const int inv2 = sym() ? 2 : 0;
   A2A_TRY(hop(false, H, R, 0, prec, 0, VL_P, VL_TE, -1, -1, -1, 0, 0, 1.0, 0, 1, RED_NONE, "1"));
-  A2A_TRY(hop(false, H, R, 0, prec, 1, VL_TE, VL_V, -1, VL_P, VL_RHAT, 0, 1.0, -1.0, 2, 0, RED_ALPHA, "2"));
+  A2A_TRY(hop(false, H, R, 0, prec, 1, VL_TE, VL_V, -1, VL_P, VL_RHAT, 0, 1.0, -1.0, 2, inv2, RED_ALPHA, "2"));
   A2A_TRY(vec(false, Vn, VK_BICG_S));
   // t = M s
   A2A_TRY(hop(false, H, R, 0, prec, 0, VL_S, VL_TE, -1, -1, -1, 0, 0, 1.0, 0, 1, RED_NONE, "1"));
-  A2A_TRY(hop(false, H, R, 0, prec, 1, VL_TE, VL_T, -1, VL_S, -1, 0, 1.0, -1.0, 2, 0, RED_OMEGA, "2"));
+  A2A_TRY(hop(false, H, R, 0, prec, 1, VL_TE, VL_T, -1, VL_S, -1, 0, 1.0, -1.0, 2, inv2, RED_OMEGA, "2"));
   A2A_TRY(vec(false, Vn, VK_BICG_XR));
   for (Slot* s : live) s->iters++;
   return A2A_OK;
@@ -971,6 +973,18 @@ int Solver::true_residual(const std::vector<int>& idx) {
   (void)idx;
   A2A_TRY(hop(true, sub_nh, R64, 1, 0, 0, VH_X, VH_TE, -1, -1, -1, 0, 0, 1.0, 0, 1, RED_NONE, nullptr));
   A2A_TRY(hop(true, sub_nh, R64, 1, 0, 1, VH_TE, VH_R, VH_BHAT, VH_X, -1, 1.0, -1.0, 1.0, 2, 0, RED_R64, nullptr));
+  return A2A_OK;
+}
+
+bool Solver::sym() const { return method == SOLVER_BICGSTAB && ctx->schur_sym; }
+
+// The inner solver's right-hand side, from the FP64 residual in vector *v of the current subset
+// (nv vector tiles): r64 itself, or A_oo^{-1} r64 (in VH_TE) for the symmetric Schur form
+// (A_oo^{-1} M x = A_oo^{-1} b has the solution of M x = b).
+int Solver::inner_rhs(int nv, int* v) {
+  if (!sym()) return A2A_OK;
+  A2A_TRY(vec(true, nv, VK_CLOVER, 1, 1, *v, VH_TE));
+  *v = VH_TE;
   return A2A_OK;
 }
 
@@ -1021,7 +1035,9 @@ int Solver::setup(const std::vector<int>& idx) {
     A2A_TRY(upload_subset(idx, R64));
     A2A_TRY(true_residual(idx));
   }
-  A2A_TRY(vec(true, nv, init_kind(), 0, 0, zero_x0 ? VH_BHAT : VH_R));
+  int vr = zero_x0 ? VH_BHAT : VH_R;
+  A2A_TRY(inner_rhs(nv, &vr));
+  A2A_TRY(vec(true, nv, init_kind(), 0, 0, vr));
   A2A_TRY(ctx->read_scal());
   for (int i : idx) {
     Slot* s = live[i];
@@ -1105,7 +1121,9 @@ int Solver::finish(const std::vector<int>& fin) {
     s->target *= 0.1;
   }
   A2A_TRY(upload_subset(again, 1));
-  return vec(true, sub_nv, init_kind());
+  int vr = VH_R;
+  A2A_TRY(inner_rhs(sub_nv, &vr));
+  return vec(true, sub_nv, init_kind(), 0, 0, vr);
 }
 
 // Residual checks, reliable updates, restarts, convergence and retirement.
@@ -1209,11 +1227,15 @@ int Solver::check() {
   }
   if (!rescale.empty()) {
     A2A_TRY(upload_subset(rescale, 1));
-    A2A_TRY(vec(true, sub_nv, method == SOLVER_CGNR ? VK_CG_RESCALE : VK_RU_RESCALE));
+    int vr = VH_R;
+    A2A_TRY(inner_rhs(sub_nv, &vr));
+    A2A_TRY(vec(true, sub_nv, method == SOLVER_CGNR ? VK_CG_RESCALE : VK_RU_RESCALE, 0, 0, vr));
   }
   if (!reinit.empty()) {
     A2A_TRY(upload_subset(reinit, 1));
-    A2A_TRY(vec(true, sub_nv, init_kind()));
+    int vr = VH_R;
+    A2A_TRY(inner_rhs(sub_nv, &vr));
+    A2A_TRY(vec(true, sub_nv, init_kind(), 0, 0, vr));
   }
   if (!done.empty()) {
     A2A_TRY(finalize(done));
@@ -1233,7 +1255,9 @@ int Solver::check() {
     }
     if (!again.empty()) {
       A2A_TRY(upload_subset(again, 1));
-      A2A_TRY(vec(true, sub_nv, init_kind()));
+      int vr = VH_R;
+      A2A_TRY(inner_rhs(sub_nv, &vr));
+      A2A_TRY(vec(true, sub_nv, init_kind(), 0, 0, vr));
     }
   }
   return A2A_OK;

@@ -183,6 +183,9 @@ struct Solver {
   int check();
   int true_residual(const std::vector<int>& idx);
   int true_residual_corr(const std::vector<int>& idx);
+  int inner_rhs(int nv, int* v);
+  // BiCGStab iterates the symmetric Schur form 1 - kappa^2 A_oo^{-1} H_oe A_ee^{-1} H_eo
+  bool sym() const;
   int finalize(const std::vector<int>& idx);
   int run_until_done(int max_outer_iters);
   int retire();
@@ -240,6 +243,7 @@ struct Ctx {
   int ru_correction = 1;             // option "ru_correction": reliable updates as r64 -= M (sigma x_lo)
   double target_frac = 0.8;          // option "target_frac": Schur-residual target / (tol ||eta||)
   int tail_checks = 1;               // option "tail_checks": check every iteration in a batch's tail
+  int schur_sym = 1;                 // option "schur_sym": BiCGStab on the symmetric Schur form
   std::map<std::string, TuneCfg> tuned;  // tune key -> launch configuration
   std::string tune_path;             // A2A_TUNE_CACHE: JSON file of tuned configurations
   // reduction scratch

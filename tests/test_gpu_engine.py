@@ -485,3 +485,29 @@ def test_reliable_update_correction_form(ctx, orc, fields, prec, nsrc):
             assert abs(r - info[i]["true_rel_residual"]) < 1e-13, (form, i, r, info[i])
         out[form] = X
     assert rel(out[1], out[0]) < 1e-8
+
+
+@pytest.mark.parametrize("prec,nsrc", [(2, 20), (2, 5), (3, 16), (1, 4)])
+def test_symmetric_schur_form(ctx, orc, fields, prec, nsrc):
+    """BiCGStab on the symmetric Schur form (the default; FP16 in a lane-interleaved group on the
+    matrix cores and per slot, BF16, FP32) and on the asymmetric form both solve to 1e-10 with
+    the oracle's D, with agreeing solutions."""
+    f = fields[1]
+    print(f"[gpu] Schur forms prec={prec} nsrc={nsrc}", flush=True)
+    eta = inputs.z2_noise(f["dims"], nsrc, seed=81)
+    A = orc.clover(f["U"], 0.127, 1.5)
+    out = {}
+    for form in (1, 0):
+        ctx.set_option("schur_sym", form)
+        try:
+            X, info, rc = ctx.solve_propagators(f["c"], eta, 0.127, 1.5, tol=1e-10, prec=prec)
+        finally:
+            ctx.set_option("schur_sym", 1)
+        assert rc == 0
+        for i in range(nsrc):
+            res = eta[i] - orc.apply_D(f["U"], A, 0.127, X[i], -1)
+            r = np.linalg.norm(res) / np.linalg.norm(eta[i])
+            assert r <= 1e-10, (form, i, r)
+            assert abs(r - info[i]["true_rel_residual"]) < 1e-13, (form, i, r, info[i])
+        out[form] = X
+    assert rel(out[1], out[0]) < 1e-8
