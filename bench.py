@@ -279,10 +279,13 @@ def main():
     tr = TRAFFIC.get((dom, args.workload, args.prec, layout))
     kind = "mfma" if mfma else "per-thread"
     traffic = tr["bytes"] if tr and tr["src"] == stencil_src_hash(kind) else None
+    sym = bool(args.schur_sym) and args.solver == "bicgstab"
     names = ({"schur1": "k_hop_mfma<.., EPI_INV> (H_eo + A_ee^-1, matrix cores)",
-              "schur2": "k_hop_mfma<.., EPI_CLOV> (H_oe + A_oo + axpy + dot, matrix cores)"} if mfma else
+              "schur2": "k_hop_mfma<.., 3> (identity - A_oo^-1 H_oe + dot, matrix cores)" if sym else
+                        "k_hop_mfma<.., EPI_CLOV> (H_oe + A_oo + axpy + dot, matrix cores)"} if mfma else
              {"schur1": "k_hop<.., EPI_INV> (H_eo + A_ee^-1)",
-              "schur2": "k_hop<.., EPI_CLOV> (H_oe + A_oo + axpy + dot)"})
+              "schur2": "k_hop<.., EPI_INVA> (identity - A_oo^-1 H_oe + dot)" if sym else
+                        "k_hop<.., EPI_CLOV> (H_oe + A_oo + axpy + dot)"})
     if args.solver == "cgnr":
         names["xr"] = "k_vec_il<.., VK_CG_XR> (x += alpha p; r' -= alpha g5 q; |r'|^2)"
         names["p"] = "k_vec_il<.., VK_CG_P> (p = g5 u + beta p)"

@@ -150,19 +150,27 @@ struct Field {
 template <typename S>
 struct StridedSpinor {
   static constexpr int NCH = 24 * (int)sizeof(S) / 16;
-  template <typename A>
+  // NT: non-temporal (streaming) loads and stores, for kernels that touch each value once
+  template <typename A, bool NT = false>
   HD static void load(const char* p0, long long ss, long long cs, long site, A* r) {
     S tmp[24];
     const char* p = p0 + site * ss;
 #pragma unroll
     for (int k = 0; k < NCH; ++k) {
-      uint4 c = *(const uint4*)(p + k * cs);
+      uint4 c;
+      if (NT) {
+        typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+        const u4v v = __builtin_nontemporal_load((const u4v*)(p + k * cs));
+        c = make_uint4(v.x, v.y, v.z, v.w);
+      } else {
+        c = *(const uint4*)(p + k * cs);
+      }
       __builtin_memcpy((char*)tmp + k * 16, &c, 16);
     }
 #pragma unroll
     for (int i = 0; i < 24; ++i) r[i] = Conv<S>::template to<A>(tmp[i]);
   }
-  template <typename A>
+  template <typename A, bool NT = false>
   HD static void store(char* p0, long long ss, long long cs, long site, const A* r) {
     S tmp[24];
 #pragma unroll
@@ -172,7 +180,17 @@ struct StridedSpinor {
     for (int k = 0; k < NCH; ++k) {
       uint4 c;
       __builtin_memcpy(&c, (const char*)tmp + k * 16, 16);
-      *(uint4*)(p + k * cs) = c;
+      if (NT) {
+        typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+        u4v v;
+        v.x = c.x;
+        v.y = c.y;
+        v.z = c.z;
+        v.w = c.w;
+        __builtin_nontemporal_store(v, (u4v*)(p + k * cs));
+      } else {
+        *(uint4*)(p + k * cs) = c;
+      }
     }
   }
 };
@@ -474,24 +492,24 @@ HD VView lo_view(const SlotDev& sd) { return VView{sd.arena[0], sd.vstride[0], s
 HD VView hi_view(const SlotDev& sd, long hv) { return VView{sd.arena[1], sd.vstride[1], 16, (long long)hv * 16}; }
 HD VView view_of(const SlotDev& sd, int psel, long hv) { return psel ? hi_view(sd, hv) : lo_view(sd); }
 
-template <typename S, typename A>
+template <typename S, typename A, bool NT = false>
 HD void vload(const VView& w, int v, long site, Spinor<A>& s) {
-  StridedSpinor<S>::template load<A>(w.base + (long long)v * w.vs, w.ss, w.cs, site, (A*)s.v);
+  StridedSpinor<S>::template load<A, NT>(w.base + (long long)v * w.vs, w.ss, w.cs, site, (A*)s.v);
 }
-template <typename S, typename A>
+template <typename S, typename A, bool NT = false>
 HD void vstore(const VView& w, int v, long site, const Spinor<A>& s) {
-  StridedSpinor<S>::template store<A>(w.base + (long long)v * w.vs, w.ss, w.cs, site, (const A*)s.v);
+  StridedSpinor<S>::template store<A, NT>(w.base + (long long)v * w.vs, w.ss, w.cs, site, (const A*)s.v);
 }
 // the inner iterate x (storage SX) of a slot
-template <typename SX, typename A>
+template <typename SX, typename A, bool NT = false>
 HD void xload(const SlotDev& sd, int v, long site, Spinor<A>& s) {
-  StridedSpinor<SX>::template load<A>(sd.arena[0] + (long long)v * sd.vstride[0] + sd.lxoff, sd.lss_x, sd.lcs, site,
-                                      (A*)s.v);
+  StridedSpinor<SX>::template load<A, NT>(sd.arena[0] + (long long)v * sd.vstride[0] + sd.lxoff, sd.lss_x, sd.lcs,
+                                          site, (A*)s.v);
 }
-template <typename SX, typename A>
+template <typename SX, typename A, bool NT = false>
 HD void xstore(const SlotDev& sd, int v, long site, const Spinor<A>& s) {
-  StridedSpinor<SX>::template store<A>(sd.arena[0] + (long long)v * sd.vstride[0] + sd.lxoff, sd.lss_x, sd.lcs, site,
-                                       (const A*)s.v);
+  StridedSpinor<SX>::template store<A, NT>(sd.arena[0] + (long long)v * sd.vstride[0] + sd.lxoff, sd.lss_x, sd.lcs,
+                                           site, (const A*)s.v);
 }
 
 // slot scalar block layout (doubles)

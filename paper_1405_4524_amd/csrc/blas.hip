@@ -44,7 +44,8 @@ struct VecRed {
 };
 
 // One site of one slot.  Reducing kinds add their (rhat, r), |r|^2 contributions to v3.
-template <class P, int KIND>
+// NT: streaming (non-temporal) loads and stores of the inner vectors (lane-interleaved kernels)
+template <class P, int KIND, bool NT = false>
 __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, int hv, int site, double (&v3)[3]) {
   using S = typename P::S;
   using SX = typename P::SX;
@@ -57,62 +58,62 @@ __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, in
   if (KIND == VK_BICG_S) {  // s = r - alpha v
     const cx<A> al = scal_c<A>(sc, SC_ALPHA);
     Spinor<A> r, v;
-    vload<S, A>(lw, VL_R, site, r);
-    vload<S, A>(lw, VL_V, site, v);
+    vload<S, A, NT>(lw, VL_R, site, r);
+    vload<S, A, NT>(lw, VL_V, site, v);
 #pragma unroll
     for (int k = 0; k < 12; ++k) r.v[k] = r.v[k] - al * v.v[k];
-    vstore<S, A>(lw, VL_S, site, r);
+    vstore<S, A, NT>(lw, VL_S, site, r);
   } else if (KIND == VK_BICG_P) {  // p = r + beta (p - omega v)
     const cx<A> be = scal_c<A>(sc, SC_BETA), om = scal_c<A>(sc, SC_OMEGA);
     Spinor<A> r, p, v;
-    vload<S, A>(lw, VL_R, site, r);
-    vload<S, A>(lw, VL_P, site, p);
-    vload<S, A>(lw, VL_V, site, v);
+    vload<S, A, NT>(lw, VL_R, site, r);
+    vload<S, A, NT>(lw, VL_P, site, p);
+    vload<S, A, NT>(lw, VL_V, site, v);
 #pragma unroll
     for (int k = 0; k < 12; ++k) p.v[k] = r.v[k] + be * (p.v[k] - om * v.v[k]);
-    vstore<S, A>(lw, VL_P, site, p);
+    vstore<S, A, NT>(lw, VL_P, site, p);
   } else if (KIND == VK_BICG_XR) {  // x += alpha p + omega s; r = s - omega t; (rhat, r), |r|^2
     const cx<A> al = scal_c<A>(sc, SC_ALPHA), om = scal_c<A>(sc, SC_OMEGA);
     Spinor<A> x, p, s, t;
-    xload<SX, A>(sd, VL_X, site, x);
-    vload<S, A>(lw, VL_P, site, p);
-    vload<S, A>(lw, VL_S, site, s);
-    vload<S, A>(lw, VL_T, site, t);
+    xload<SX, A, NT>(sd, VL_X, site, x);
+    vload<S, A, NT>(lw, VL_P, site, p);
+    vload<S, A, NT>(lw, VL_S, site, s);
+    vload<S, A, NT>(lw, VL_T, site, t);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       x.v[k] = x.v[k] + al * p.v[k] + om * s.v[k];
       s.v[k] = s.v[k] - om * t.v[k];
     }
-    xstore<SX, A>(sd, VL_X, site, x);
-    vstore<S, A>(lw, VL_R, site, s);
+    xstore<SX, A, NT>(sd, VL_X, site, x);
+    vstore<S, A, NT>(lw, VL_R, site, s);
     round_to<S>(s);  // reduce the values as stored
     Spinor<A> rh;
-    vload<S, A>(lw, VL_RHAT, site, rh);
+    vload<S, A, NT>(lw, VL_RHAT, site, rh);
     dot3(rh, s, v3);
   } else if (KIND == VK_CG_XR) {  // x += alpha p; r' -= alpha gamma5 q; |r'|^2
     const A al = (A)sc[SC_ALPHA];
     Spinor<A> x, p, r, q;
-    xload<SX, A>(sd, VL_X, site, x);
-    vload<S, A>(lw, VL_P, site, p);
-    vload<S, A>(lw, VL_R, site, r);
-    vload<S, A>(lw, VL_V, site, q);
+    xload<SX, A, NT>(sd, VL_X, site, x);
+    vload<S, A, NT>(lw, VL_P, site, p);
+    vload<S, A, NT>(lw, VL_R, site, r);
+    vload<S, A, NT>(lw, VL_V, site, q);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       x.v[k] = x.v[k] + al * p.v[k];
       r.v[k] = k < 6 ? r.v[k] - al * q.v[k] : r.v[k] + al * q.v[k];
     }
-    xstore<SX, A>(sd, VL_X, site, x);
-    vstore<S, A>(lw, VL_R, site, r);
+    xstore<SX, A, NT>(sd, VL_X, site, x);
+    vstore<S, A, NT>(lw, VL_R, site, r);
     round_to<S>(r);
     dot3(r, r, v3);
   } else if (KIND == VK_CG_P) {  // p = gamma5 u + beta p
     const A be = (A)sc[SC_BETA];
     Spinor<A> u, p;
-    vload<S, A>(lw, VL_S, site, u);
-    vload<S, A>(lw, VL_P, site, p);
+    vload<S, A, NT>(lw, VL_S, site, u);
+    vload<S, A, NT>(lw, VL_P, site, p);
 #pragma unroll
     for (int k = 0; k < 12; ++k) p.v[k] = (k < 6 ? u.v[k] : mk(-u.v[k].re, -u.v[k].im)) + be * p.v[k];
-    vstore<S, A>(lw, VL_P, site, p);
+    vstore<S, A, NT>(lw, VL_P, site, p);
   } else if (KIND == VK_CG_INIT || KIND == VK_CG_RESCALE) {  // r' = gamma5 r64 / sigma'
     const double snew =
         KIND == VK_CG_INIT ? sqrt(sc[SC_R64N2] / (12.0 * hv)) : ru_scale(sc[SC_R64N2], sc[SC_SIGMA], hv);
@@ -125,26 +126,26 @@ __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, in
       const double f = k < 6 ? inv : -inv;
       r.v[k] = mk((A)(rh64.v[k].re * f), (A)(rh64.v[k].im * f));
     }
-    vstore<S, A>(lw, VL_R, site, r);
+    vstore<S, A, NT>(lw, VL_R, site, r);
     round_to<S>(r);
     Spinor<A> p;
     if (KIND == VK_CG_INIT) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) p.v[k] = mk((A)0, (A)0);
-      xstore<SX, A>(sd, VL_X, site, p);
+      xstore<SX, A, NT>(sd, VL_X, site, p);
     } else {
       const A ratio = (A)(sc[SC_SIGMA] * inv);
-      vload<S, A>(lw, VL_P, site, p);
+      vload<S, A, NT>(lw, VL_P, site, p);
 #pragma unroll
       for (int k = 0; k < 12; ++k) p.v[k] = ratio * p.v[k];
     }
-    vstore<S, A>(lw, VL_P, site, p);
+    vstore<S, A, NT>(lw, VL_P, site, p);
     dot3(r, r, v3);
   } else if (KIND == VK_RU_ACCUM) {  // x64 += sigma x_lo; x_lo = 0
     const double sg = sc[SC_SIGMA];
     Spinor<A> xl;
     Spinor<double> xh;
-    xload<SX, A>(sd, VL_X, site, xl);
+    xload<SX, A, NT>(sd, VL_X, site, xl);
     load_spinor<double, double>(HI(VH_X), hv, site, xh);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -153,7 +154,7 @@ __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, in
       xl.v[k] = mk((A)0, (A)0);
     }
     store_spinor<double, double>(HI(VH_X), hv, site, xh);
-    xstore<SX, A>(sd, VL_X, site, xl);
+    xstore<SX, A, NT>(sd, VL_X, site, xl);
   } else if (KIND == VK_RU_RESCALE || KIND == VK_INIT) {
     const double snew =
         KIND == VK_INIT ? sqrt(sc[SC_R64N2] / (12.0 * hv)) : ru_scale(sc[SC_R64N2], sc[SC_SIGMA], hv);
@@ -163,31 +164,31 @@ __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, in
     Spinor<A> r;
 #pragma unroll
     for (int k = 0; k < 12; ++k) r.v[k] = mk((A)(rh64.v[k].re * inv), (A)(rh64.v[k].im * inv));
-    vstore<S, A>(lw, VL_R, site, r);
+    vstore<S, A, NT>(lw, VL_R, site, r);
     round_to<S>(r);  // the values as stored
     Spinor<A> rh;
     if (KIND == VK_INIT) {
       Spinor<A> z;
 #pragma unroll
       for (int k = 0; k < 12; ++k) z.v[k] = mk((A)0, (A)0);
-      vstore<S, A>(lw, VL_RHAT, site, r);
-      vstore<S, A>(lw, VL_P, site, r);
-      vstore<S, A>(lw, VL_V, site, z);
-      xstore<SX, A>(sd, VL_X, site, z);
+      vstore<S, A, NT>(lw, VL_RHAT, site, r);
+      vstore<S, A, NT>(lw, VL_P, site, r);
+      vstore<S, A, NT>(lw, VL_V, site, z);
+      xstore<SX, A, NT>(sd, VL_X, site, z);
       rh = r;
     } else {
       const A ratio = (A)(sc[SC_SIGMA] * inv);
       Spinor<A> p, v;
-      vload<S, A>(lw, VL_P, site, p);
-      vload<S, A>(lw, VL_V, site, v);
+      vload<S, A, NT>(lw, VL_P, site, p);
+      vload<S, A, NT>(lw, VL_V, site, v);
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
         p.v[k] = ratio * p.v[k];
         v.v[k] = ratio * v.v[k];
       }
-      vstore<S, A>(lw, VL_P, site, p);
-      vstore<S, A>(lw, VL_V, site, v);
-      vload<S, A>(lw, VL_RHAT, site, rh);
+      vstore<S, A, NT>(lw, VL_P, site, p);
+      vstore<S, A, NT>(lw, VL_V, site, v);
+      vload<S, A, NT>(lw, VL_RHAT, site, rh);
     }
     dot3(rh, r, v3);
   } else if (KIND == VK_CLOVER) {  // FP64: hi[vout] = C hi[vin], C = A or A^{-1} of parity par
@@ -201,7 +202,7 @@ __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, in
     Spinor<A> z;
 #pragma unroll
     for (int k = 0; k < 12; ++k) z.v[k] = mk((A)0, (A)0);
-    xstore<SX, A>(sd, VL_X, site, z);
+    xstore<SX, A, NT>(sd, VL_X, site, z);
   } else if (KIND == VK_ZERO_HI) {
     Spinor<double> z;
 #pragma unroll
@@ -226,7 +227,7 @@ __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, in
         z.v[k] = mk(re, im);
       }
     }
-    vstore<S, A>(lw, a.vout, site, z);
+    vstore<S, A, NT>(lw, a.vout, site, z);
   }
 #undef HI
 }
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(BSI) void k_vec_il(VecArgs a) {
 #pragma unroll
     for (int i = 0; i < BS / (BSI / 16); ++i) {
       const int site = tile.y * BS + (BSI / 16) * i + q;
-      if (site < hv) vec_site<P, KIND>(a, sd, hv, site, v3);
+      if (site < hv) vec_site<P, KIND, true>(a, sd, hv, site, v3);
     }
   }
   if (VecRed<KIND>::on) {
