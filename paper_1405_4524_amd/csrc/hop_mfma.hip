@@ -95,6 +95,19 @@ __device__ __forceinline__ uint4 gld4(const void* p) {
   const v4u v = *(gptr4)p;
   return make_uint4(v.x, v.y, v.z, v.w);
 }
+// single-use operands (the site's own aux / shadow chunks, the output): streaming access
+__device__ __forceinline__ uint4 gld4nt(const void* p) {
+  const v4u v = __builtin_nontemporal_load((gptr4)p);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gst4nt(void* p, const uint4& v) {
+  v4u w;
+  w.x = v.x;
+  w.y = v.y;
+  w.z = v.z;
+  w.w = v.w;
+  __builtin_nontemporal_store(w, (__attribute__((address_space(1))) v4u*)p);
+}
 __device__ __forceinline__ void gst4(void* p, const uint4& v) {
   v4u w;
   w.x = v.x;
@@ -190,8 +203,8 @@ __device__ __forceinline__ void load_tile(TileIn& d, const char* vin, const char
 #pragma unroll
   for (int kt = 0; kt < 6; ++kt) d.B[kt] = gld4(vin + ((long long)nbs[kt] * NT + nt) * 768 + hoff[kt]);
   const long long own = ((long long)site * NT + nt) * 768 + (gq < 3 ? gq : 0) * 256 + n * 16;
-  if (EPI == 1 || EPI == 3) d.Bc = gld4(vaux2 + own);
-  if (RED == RED_ALPHA) d.Bx = gld4(vrh + own);
+  if (EPI == 1 || EPI == 3) d.Bc = gld4nt(vaux2 + own);
+  if (RED == RED_ALPHA) d.Bx = gld4nt(vrh + own);
 }
 
 // cb indices of the neighbour site each lane's chunk of K step kt comes from: chunk 4 kt + gq
@@ -478,7 +491,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3, 3))) void
     wave_lds_sync();
     const uint4 ob = trb[w][n][ochunk];
     wave_lds_sync();
-    gst4(vout + ((long long)site * NT + nt) * 768 + ochunk * 256 + n * 16, ob);
+    gst4nt(vout + ((long long)site * NT + nt) * 768 + ochunk * 256 + n * 16, ob);
     ++ck;
   };
 
