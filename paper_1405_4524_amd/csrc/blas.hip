@@ -161,6 +161,11 @@ __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, in
     const double inv = (snew > 0.0) ? 1.0 / snew : 0.0;
     Spinor<double> rh64;
     load_spinor<double, double>(HI(a.vin >= 0 ? a.vin : VH_R), hv, site, rh64);
+    if (a.use_inv) {  // symmetric Schur form: the inner right-hand side is A_oo^{-1} r64
+      Spinor<double> t;
+      clover_apply_mem<double, double>(a.ops[sd.op].Ai[1][1], hv, site, rh64, t);
+      rh64 = t;
+    }
     Spinor<A> r;
 #pragma unroll
     for (int k = 0; k < 12; ++k) r.v[k] = mk((A)(rh64.v[k].re * inv), (A)(rh64.v[k].im * inv));

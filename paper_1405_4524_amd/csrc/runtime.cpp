@@ -978,16 +978,6 @@ int Solver::true_residual(const std::vector<int>& idx) {
 
 bool Solver::sym() const { return method == SOLVER_BICGSTAB && ctx->schur_sym; }
 
-// The inner solver's right-hand side, from the FP64 residual in vector *v of the current subset
-// (nv vector tiles): r64 itself, or A_oo^{-1} r64 (in VH_TE) for the symmetric Schur form
-// (A_oo^{-1} M x = A_oo^{-1} b has the solution of M x = b).
-int Solver::inner_rhs(int nv, int* v) {
-  if (!sym()) return A2A_OK;
-  A2A_TRY(vec(true, nv, VK_CLOVER, 1, 1, *v, VH_TE));
-  *v = VH_TE;
-  return A2A_OK;
-}
-
 // FP64, correction form: r64 -= M (sigma x_lo) for a subset whose inner iterate x_lo holds the
 // correction since the last FP64 residual (x64 not yet updated): te = A_ee^{-1} H_eo (sigma
 // x_lo), r64 = r64 + kappa^2 H_oe te - A_oo (sigma x_lo), |r64|^2.  The stencils read the
@@ -1035,9 +1025,8 @@ int Solver::setup(const std::vector<int>& idx) {
     A2A_TRY(upload_subset(idx, R64));
     A2A_TRY(true_residual(idx));
   }
-  int vr = zero_x0 ? VH_BHAT : VH_R;
-  A2A_TRY(inner_rhs(nv, &vr));
-  A2A_TRY(vec(true, nv, init_kind(), 0, 0, vr));
+  // the symmetric Schur form iterates on A_oo^-1 r64 (applied by the kernel)
+  A2A_TRY(vec(true, nv, init_kind(), 0, sym() ? 1 : 0, zero_x0 ? VH_BHAT : VH_R));
   A2A_TRY(ctx->read_scal());
   for (int i : idx) {
     Slot* s = live[i];
@@ -1121,9 +1110,8 @@ int Solver::finish(const std::vector<int>& fin) {
     s->target *= 0.1;
   }
   A2A_TRY(upload_subset(again, 1));
-  int vr = VH_R;
-  A2A_TRY(inner_rhs(sub_nv, &vr));
-  return vec(true, sub_nv, init_kind(), 0, 0, vr);
+  // the symmetric Schur form iterates on A_oo^-1 r64 (applied by the kernel)
+  return vec(true, sub_nv, init_kind(), 0, sym() ? 1 : 0, VH_R);
 }
 
 // Residual checks, reliable updates, restarts, convergence and retirement.
@@ -1227,15 +1215,13 @@ int Solver::check() {
   }
   if (!rescale.empty()) {
     A2A_TRY(upload_subset(rescale, 1));
-    int vr = VH_R;
-    A2A_TRY(inner_rhs(sub_nv, &vr));
-    A2A_TRY(vec(true, sub_nv, method == SOLVER_CGNR ? VK_CG_RESCALE : VK_RU_RESCALE, 0, 0, vr));
+    // the symmetric Schur form iterates on A_oo^-1 r64 (applied by the kernel)
+    A2A_TRY(vec(true, sub_nv, method == SOLVER_CGNR ? VK_CG_RESCALE : VK_RU_RESCALE, 0, sym() ? 1 : 0, VH_R));
   }
   if (!reinit.empty()) {
     A2A_TRY(upload_subset(reinit, 1));
-    int vr = VH_R;
-    A2A_TRY(inner_rhs(sub_nv, &vr));
-    A2A_TRY(vec(true, sub_nv, init_kind(), 0, 0, vr));
+    // the symmetric Schur form iterates on A_oo^-1 r64 (applied by the kernel)
+    A2A_TRY(vec(true, sub_nv, init_kind(), 0, sym() ? 1 : 0, VH_R));
   }
   if (!done.empty()) {
     A2A_TRY(finalize(done));
@@ -1255,9 +1241,8 @@ int Solver::check() {
     }
     if (!again.empty()) {
       A2A_TRY(upload_subset(again, 1));
-      int vr = VH_R;
-      A2A_TRY(inner_rhs(sub_nv, &vr));
-      A2A_TRY(vec(true, sub_nv, init_kind(), 0, 0, vr));
+      // the symmetric Schur form iterates on A_oo^-1 r64 (applied by the kernel)
+      A2A_TRY(vec(true, sub_nv, init_kind(), 0, sym() ? 1 : 0, VH_R));
     }
   }
   return A2A_OK;

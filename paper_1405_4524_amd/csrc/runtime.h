@@ -183,7 +183,6 @@ struct Solver {
   int check();
   int true_residual(const std::vector<int>& idx);
   int true_residual_corr(const std::vector<int>& idx);
-  int inner_rhs(int nv, int* v);
   // BiCGStab iterates the symmetric Schur form 1 - kappa^2 A_oo^{-1} H_oe A_ee^{-1} H_eo
   bool sym() const;
   int finalize(const std::vector<int>& idx);
