@@ -11,6 +11,8 @@
 // time (FP64 stencils over 24 two-RHS groups: 7% faster); a single group keeps whole (x, y)
 // planes per block, whose z and t neighbours are read by blocks in flight at the same time
 // (bricks made that case 5-8% slower).
+#include <type_traits>
+
 #include "a2a_kernels.h"
 
 namespace a2a {
@@ -56,10 +58,11 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
   }
 
   Spinor<A> acc[R];
+  Spinor<A> resid[R];  // the reconstruction's r_e (EPI_INV with RED_RES_E)
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[r].v[k] = mk((A)0, (A)0);
+    for (int k = 0; k < 12; ++k) acc[r].v[k] = resid[r].v[k] = mk((A)0, (A)0);
 
   if (valid) {
     int c[4];
@@ -129,6 +132,9 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
         for (int k = 0; k < 12; ++k) acc[r].v[k] = acc[r].v[k] + ca * x1.v[k];
       }
     }
+    // EPI_INV with RED_RES_E (the reconstruction): also r_e = y - A x_e, y the input of A^{-1}
+    // (eta_e + kappa H_eo x_o) and x_e the output as stored, and its |r_e|^2
+    const bool res_e = EPI == EPI_INV && std::is_same<S, double>::value && a.red == RED_RES_E;
     if (EPI != EPI_PLAIN) {
       const void* cbase = (EPI == EPI_CLOV) ? op.A[sel][po] : op.Ai[sel][po];
       Spinor<A> x3[R];  // EPI_INVA: the identity term
@@ -162,7 +168,30 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
             for (int k = 0; k < 6; ++k) i6[k] = acc[r].v[b * 6 + k];
             clover_apply_block(blk, i6, o6);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) acc[r].v[b * 6 + k] = EPI == EPI_INVA ? x3[r].v[b * 6 + k] + o6[k] : o6[k];
+            for (int k = 0; k < 6; ++k) {
+              if (res_e) resid[r].v[b * 6 + k] = i6[k];  // y, kept for r_e
+              acc[r].v[b * 6 + k] = EPI == EPI_INVA ? x3[r].v[b * 6 + k] + o6[k] : o6[k];
+            }
+          }
+        }
+      }
+      if (res_e) {  // r_e = y - A x_e with x_e rounded as stored
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          A blk[36];
+          CloverBlkF<S>::template load<A>((const char*)op.A[sel][po] + b * CloverBlkF<S>::bytes(hv), hv, site, blk);
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (!on[r]) continue;
+            cx<A> i6[6], o6[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+              const cx<A> xs = acc[r].v[b * 6 + k];
+              i6[k] = mk((A)Conv<S>::template to<A>(Conv<S>::from(xs.re)), (A)Conv<S>::template to<A>(Conv<S>::from(xs.im)));
+            }
+            clover_apply_block(blk, i6, o6);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) resid[r].v[b * 6 + k] = resid[r].v[b * 6 + k] - o6[k];
           }
         }
       }
@@ -199,6 +228,10 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
         v[r * 3 + 1] += (double)o.v[k].re * x2.v[k].im - (double)o.v[k].im * x2.v[k].re;
         v[r * 3 + 2] += (double)o.v[k].re * o.v[k].re + (double)o.v[k].im * o.v[k].im;
       }
+    } else if (EPI == EPI_INV && std::is_same<S, double>::value && a.red == RED_RES_E) {  // |r_e|^2
+#pragma unroll
+      for (int k = 0; k < 12; ++k)
+        v[r * 3] += (double)resid[r].v[k].re * resid[r].v[k].re + (double)resid[r].v[k].im * resid[r].v[k].im;
     } else {  // |o|^2
 #pragma unroll
       for (int k = 0; k < 12; ++k) v[r * 3] += (double)o.v[k].re * o.v[k].re + (double)o.v[k].im * o.v[k].im;

@@ -1054,10 +1054,9 @@ int Solver::finalize(const std::vector<int>& idx) {
   if (idx.empty()) return A2A_OK;
   A2A_TRY(upload_subset(idx, R64));
   const int nh = sub_nh, nv = sub_nv;
-  // x_e = A_ee^{-1} (eta_e + kappa H_eo x_o)  -> VH_TE
-  A2A_TRY(hop(true, nh, R64, 1, 0, 0, VH_X, VH_TE, VH_ETA_E, -1, -1, 1.0, 0, 1.0, 1, 1, RED_NONE, nullptr));
-  // r_e = eta_e - A_ee x_e + kappa H_eo x_o
-  A2A_TRY(hop(true, nh, R64, 1, 0, 0, VH_X, VH_R, VH_ETA_E, VH_TE, -1, 1.0, -1.0, 1.0, 1, 0, RED_RES_E, nullptr));
+  // x_e = A_ee^{-1} y with y = eta_e + kappa H_eo x_o -> VH_TE, and in the same launch the even
+  // residual r_e = eta_e - A_ee x_e + kappa H_eo x_o = y - A_ee x_e (x_e as stored), |r_e|^2
+  A2A_TRY(hop(true, nh, R64, 1, 0, 0, VH_X, VH_TE, VH_ETA_E, -1, -1, 1.0, 0, 1.0, 1, 1, RED_RES_E, nullptr));
   // r_o = eta_o - A_oo x_o + kappa H_oe x_e
   A2A_TRY(hop(true, nh, R64, 1, 0, 1, VH_TE, VH_R, VH_ETA_O, VH_X, -1, 1.0, -1.0, 1.0, 1, 0, RED_RES_O, nullptr));
   A2A_TRY(layout_out(true, nv, 1, 0, VH_TE, VH_X, 0));
