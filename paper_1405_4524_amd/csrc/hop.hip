@@ -27,6 +27,9 @@ template <class P, int R, int EPI, int LOM = 0, typename SI = typename P::S>
 __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
   using S = typename P::S;
   using A = typename P::A;
+  // FP64 stencils: the site's own operands and the output are touched once (streaming access),
+  // and the output's reductions come from the registers (the stored values are the same)
+  constexpr bool NTX = std::is_same<S, double>::value;
   const int2 tile = a.tiles[blockIdx.x];
   const int* grp = a.groups + (size_t)tile.x * R;
   const int slot0 = grp[0];
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
       for (int k = 0; k < 12; ++k) acc[r].v[k] = gr * acc[r].v[k];
       if (a.vaux1 >= 0) {
         Spinor<A> x1;
-        vload<S, A>(w[r], a.vaux1, site, x1);
+        vload<S, A, NTX>(w[r], a.vaux1, site, x1);
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[r].v[k] = acc[r].v[k] + ca * x1.v[k];
       }
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
       if (EPI == EPI_INVA) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
-          if (on[r]) vload<S, A>(w[r], a.vaux2, site, x3[r]);
+          if (on[r]) vload<S, A, NTX>(w[r], a.vaux2, site, x3[r]);
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
@@ -154,9 +157,9 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
           if (EPI == EPI_CLOV) {
             Spinor<A> x2;
             if (LOM == 2)
-              vload<SI, A>(wl[r], a.vaux2, site, x2);
+              vload<SI, A, NTX>(wl[r], a.vaux2, site, x2);
             else
-              vload<S, A>(w[r], a.vaux2, site, x2);
+              vload<S, A, NTX>(w[r], a.vaux2, site, x2);
             const A cr = LOM == 2 ? cbv * sgm[r] : cbv;
 #pragma unroll
             for (int k = 0; k < 6; ++k) i6[k] = x2.v[b * 6 + k];
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
     }
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (on[r]) vstore<S, A>(w[r], a.vout, site, acc[r]);
+      if (on[r]) vstore<S, A, NTX>(w[r], a.vout, site, acc[r]);
   }
 
   // ---- reductions over the values as stored: one block partial per slot of the group
@@ -210,7 +213,10 @@ __global__ __launch_bounds__(BS) void k_hop(HopArgs a) {
   for (int r = 0; r < R; ++r) {
     if (!valid || !on[r]) continue;
     Spinor<A> o;
-    vload<S, A>(w[r], a.vout, site, o);
+    if (NTX)
+      o = acc[r];
+    else
+      vload<S, A>(w[r], a.vout, site, o);
     if (a.red == RED_ALPHA) {  // (rhat, o)
       Spinor<A> rh;
       vload<S, A>(w[r], a.vrhat, site, rh);
