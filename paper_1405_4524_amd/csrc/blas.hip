@@ -254,16 +254,29 @@ __global__ __launch_bounds__(BS) void k_vec(VecArgs a) {
 }
 
 // interleaved mapping: tiles {16-lane group tile, block of BS sites}; BSI threads as (lane n,
-// row q) visit sites block*BS + 64 i + q, so a wave touches 4 sites x 16 lanes = 4 contiguous
-// 256-byte runs per chunk and a block keeps 16 waves of loads in flight.  Reductions are per
-// lane (slot) and land in the same partial slots as the per-slot mapping (block index = site
-// block of BS sites).
+// row q) visit sites block*BS + 64 i + q, and a block keeps 16 waves of loads in flight.
+// Kinds on inner vectors only give a wave 4 sites x 16 lanes (4 contiguous 256-byte runs per
+// chunk).  Kinds that also touch the slots' FP64 vectors, whose chunk planes are per slot
+// ([chunk][site]), give a wave 8 sites x 8 lanes instead: 8 full 128-byte lines of the
+// interleaved arena per chunk, and for each of its 8 slots 8 consecutive FP64 chunks = one full
+// line (4 sites x 16 lanes used half lines there).  Reductions are per lane (slot) and land in
+// the same partial slots as the per-slot mapping (block index = site block of BS sites).
 constexpr int BSI = 1024;
+
+template <int KIND>
+struct VecWide {
+  static constexpr bool on = KIND == VK_RU_ACCUM || KIND == VK_RU_RESCALE || KIND == VK_INIT || KIND == VK_CG_INIT ||
+                             KIND == VK_CG_RESCALE;
+};
 
 template <class P, int KIND>
 __global__ __launch_bounds__(BSI) void k_vec_il(VecArgs a) {
+  constexpr bool wide = VecWide<KIND>::on;
   const int2 tile = a.tiles[blockIdx.x];
-  const int n = threadIdx.x & 15, q = threadIdx.x >> 4;
+  const int t = threadIdx.x;
+  // wide: thread bits [0..2] lane, [3..8] row, [9] lane bit 3; else [0..3] lane, [4..9] row
+  const int n = wide ? (t & 7) | ((t >> 9) << 3) : t & 15;
+  const int q = wide ? (t >> 3) & 63 : t >> 4;
   const int slot = a.ilslots[tile.x * 16 + n];
   double v3[3] = {0.0, 0.0, 0.0};
   if (slot >= 0) {
@@ -276,14 +289,16 @@ __global__ __launch_bounds__(BSI) void k_vec_il(VecArgs a) {
     }
   }
   if (VecRed<KIND>::on) {
+    // per wave: sum the lanes of equal n (wide: 8 lanes, each on 8 sites; else 16 lanes on 4)
     __shared__ double red[BSI / 64][16][3];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
+      if (wide) v3[k] += __shfl_xor(v3[k], 8, 64);
       v3[k] += __shfl_xor(v3[k], 16, 64);
       v3[k] += __shfl_xor(v3[k], 32, 64);
     }
-    if (lane < 16)
+    if (lane < (wide ? 8 : 16))
 #pragma unroll
       for (int k = 0; k < 3; ++k) red[w][lane][k] = v3[k];
     __syncthreads();
@@ -291,10 +306,15 @@ __global__ __launch_bounds__(BSI) void k_vec_il(VecArgs a) {
       const int m = threadIdx.x & 15, k = threadIdx.x >> 4;
       const int sl = a.ilslots[tile.x * 16 + m];
       if (sl >= 0) {
-        double t = 0.0;
+        double s = 0.0;
+        if (wide) {  // lane m lives in waves 8 (m >> 3) .. 8 (m >> 3) + 7 at wave lane m & 7
 #pragma unroll
-        for (int j = 0; j < BSI / 64; ++j) t += red[j][m][k];
-        store_partial(a.rb, a.slots[sl].sid, tile.y, k, t);
+          for (int j = 0; j < BSI / 128; ++j) s += red[8 * (m >> 3) + j][m & 7][k];
+        } else {
+#pragma unroll
+          for (int j = 0; j < BSI / 64; ++j) s += red[j][m][k];
+        }
+        store_partial(a.rb, a.slots[sl].sid, tile.y, k, s);
       }
     }
   }
