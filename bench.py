@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--workload", default="l32t64")
     ap.add_argument("--prec", default="f16", choices=list(PREC))
     ap.add_argument("--rhs-block", type=int, default=2, help="per-thread RHS width when not autotuned")
+    ap.add_argument("--rhs-block64", type=int, default=2,
+                    help="FP64-stencil RHS width when not autotuned (1 or 2)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: tune the launch configuration (group width, brick, FP64 width) before the warmup")
     ap.add_argument("--check-every", type=int, default=4)
@@ -185,6 +187,7 @@ def main():
     ctx = a2a.Context(0, stream=torch.cuda.current_stream().cuda_stream)
     ctx.z2_noise_dev(dims, w["noise_seed"], 0, nsrc, src)
     ctx.set_option("rhs_block", args.rhs_block)
+    ctx.set_option("rhs_block64", args.rhs_block64)
     ctx.set_option("check_every", args.check_every)
     ctx.set_option("interleave", args.interleave)
     ctx.set_option("mfma", args.mfma)

@@ -965,7 +965,7 @@ static int autotune_cfg(Ctx* c, int clover_h, double kappa, int prec, int nrhs, 
     }
   // 3. FP64 stencils: width, then their own brick and tile order over the XCDs
   double t64 = 1e300;
-  const int n64 = std::min(nrhs, 24);
+  const int n64 = std::min(nrhs, 48);  // the slot counts of reliable updates: bricks rank differently at 24
   TuneCfg b64 = best;
   b64.il_width = 0;
   b64.slab = -1;
