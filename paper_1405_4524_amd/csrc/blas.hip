@@ -44,13 +44,15 @@ struct VecRed {
 };
 
 // One site of one slot.  Reducing kinds add their (rhat, r), |r|^2 contributions to v3.
-// NT: streaming (non-temporal) loads and stores of the inner vectors (lane-interleaved kernels)
+// NT: streaming (non-temporal) loads and stores of the inner vectors and of the FP64 vectors of the
+// reliable-update kinds (lane-interleaved kernels: each value is touched once)
 template <class P, int KIND, bool NT = false>
 __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, int hv, int site, double (&v3)[3]) {
   using S = typename P::S;
   using SX = typename P::SX;
   using A = typename P::A;
   const VView lw = lo_view(sd);
+  const VView hw = hi_view(sd, hv);  // the slot's FP64 vectors (chunk planes)
   char* hi = sd.arena[1];
   const long long vh = sd.vstride[1];
   const double* sc = sd.scal;
@@ -119,7 +121,7 @@ __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, in
         KIND == VK_CG_INIT ? sqrt(sc[SC_R64N2] / (12.0 * hv)) : ru_scale(sc[SC_R64N2], sc[SC_SIGMA], hv);
     const double inv = (snew > 0.0) ? 1.0 / snew : 0.0;
     Spinor<double> rh64;
-    load_spinor<double, double>(HI(a.vin >= 0 ? a.vin : VH_R), hv, site, rh64);
+    vload<double, double, NT>(hw, a.vin >= 0 ? a.vin : VH_R, site, rh64);
     Spinor<A> r;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -146,21 +148,21 @@ __device__ __forceinline__ void vec_site(const VecArgs& a, const SlotDev& sd, in
     Spinor<A> xl;
     Spinor<double> xh;
     xload<SX, A, NT>(sd, VL_X, site, xl);
-    load_spinor<double, double>(HI(VH_X), hv, site, xh);
+    vload<double, double, NT>(hw, VH_X, site, xh);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       xh.v[k].re += sg * (double)xl.v[k].re;
       xh.v[k].im += sg * (double)xl.v[k].im;
       xl.v[k] = mk((A)0, (A)0);
     }
-    store_spinor<double, double>(HI(VH_X), hv, site, xh);
+    vstore<double, double, NT>(hw, VH_X, site, xh);
     xstore<SX, A, NT>(sd, VL_X, site, xl);
   } else if (KIND == VK_RU_RESCALE || KIND == VK_INIT) {
     const double snew =
         KIND == VK_INIT ? sqrt(sc[SC_R64N2] / (12.0 * hv)) : ru_scale(sc[SC_R64N2], sc[SC_SIGMA], hv);
     const double inv = (snew > 0.0) ? 1.0 / snew : 0.0;
     Spinor<double> rh64;
-    load_spinor<double, double>(HI(a.vin >= 0 ? a.vin : VH_R), hv, site, rh64);
+    vload<double, double, NT>(hw, a.vin >= 0 ? a.vin : VH_R, site, rh64);
     if (a.use_inv) {  // symmetric Schur form: the inner right-hand side is A_oo^{-1} r64
       Spinor<double> t;
       clover_apply_mem<double, double>(a.ops[sd.op].Ai[1][1], hv, site, rh64, t);
