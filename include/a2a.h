@@ -196,7 +196,9 @@ typedef struct {
   int rhs_block;     /* RHS per thread of the per-thread stencil: 1, 2 or 4 (0: the context option) */
   int rhs_block64;   /* RHS per thread of the FP64 stencils of reliable updates: 1 or 2 */
   double ms_schur;   /* best time of the inner-precision Schur operator (both stencils), ms; -1 if cached */
-  double ms_schur64; /* best time of the FP64 Schur operator, ms; -1 if cached */
+  double ms_schur64; /* best time of the FP64 stencils the solves run, ms: the correction-form
+                        reliable-update pair for FP16 / BF16 / FP32 storage, else the FP64 Schur
+                        operator; -1 if cached */
   int candidates;    /* configurations timed (0: taken from the cache) */
   int xcd_slab;      /* matrix-core blocks: 1 in XCD slabs, 0 in brick order, -1 not used */
   int brick64[3];    /* brick of the FP64 stencils of reliable updates (y, z, t) */
