@@ -845,7 +845,7 @@ static int ru_time(Ctx* c, int clover_h, double kappa, int prec, int nrhs, int r
     rc = sv.vec(false, Vn, VK_FILL_LO, 0, 0, -1, VL_X);
     if (!rc) rc = sv.vec(false, Vn, VK_ZERO_HI, 0, 0, -1, VH_R);
     if (!rc) rc = sv.upload_subset(all, sv.R64);
-    for (int w = 0; w < 2 && !rc; ++w) rc = sv.true_residual_corr(all);
+    if (!rc) rc = sv.true_residual_corr(all);  // warmup
     if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
       rc = c->fail(A2A_EDEVICE, "hipEventCreate failed");
     if (!rc && hipEventRecord(e0, c->stream) != hipSuccess) rc = c->fail(A2A_EDEVICE, "hipEventRecord failed");
@@ -1034,27 +1034,29 @@ static int autotune_cfg(Ctx* c, int clover_h, double kappa, int prec, int nrhs, 
   auto timed64 = [&](const TuneCfg& t, double* ms) -> int {
     if (!corr) return timed(0, n64, t, ms);
     ++tried;
-    return ru_time(c, clover_h, kappa, prec, n64, 3, best, t, ms);
+    return ru_time(c, clover_h, kappa, prec, n64, 2, best, t, ms);
   };
-  for (int r : {1, 2}) {
-    TuneCfg t = b64;
-    t.R = r;
-    double ms = 0;
-    A2A_TRY(timed64(t, &ms));
-    if (ms < t64) {
-      t64 = ms;
-      b64.R = r;
-    }
-  }
-  const TuneCfg first64 = b64;
-  for (int k = 0; k < nb; ++k)
-    for (int xo = 0; xo < 2; ++xo) {
-      TuneCfg t = first64;
-      t.by = br[k][0];
-      t.bz = br[k][1];
-      t.bt = br[k][2];
-      t.xcd64 = xo;
-      if (t.by == first64.by && t.bz == first64.bz && t.bt == first64.bt && t.xcd64 == first64.xcd64) continue;
+  // width x brick x order jointly: which width wins depends on the brick (and on the box: the
+  // correction-form pair's time varies up to 2x between boxes, with the ranking of the widths)
+  {
+    std::vector<TuneCfg> cand;
+    for (int r : {1, 2})
+      for (int k = -1; k < nb; ++k)
+        for (int xo = 0; xo < 2; ++xo) {
+          TuneCfg t = b64;
+          t.R = r;
+          if (k >= 0) {
+            t.by = br[k][0];
+            t.bz = br[k][1];
+            t.bt = br[k][2];
+          }
+          t.xcd64 = xo;
+          bool dup = false;
+          for (const TuneCfg& u : cand)
+            dup = dup || (u.R == t.R && u.by == t.by && u.bz == t.bz && u.bt == t.bt && u.xcd64 == t.xcd64);
+          if (!dup) cand.push_back(t);
+        }
+    for (const TuneCfg& t : cand) {
       double ms = 0;
       A2A_TRY(timed64(t, &ms));
       if (ms < t64) {
@@ -1062,6 +1064,7 @@ static int autotune_cfg(Ctx* c, int clover_h, double kappa, int prec, int nrhs, 
         b64 = t;
       }
     }
+  }
   best.R64 = b64.R;
   best.xcd64 = b64.xcd64;
   if (b64.by != best.by || b64.bz != best.bz || b64.bt != best.bt) {
