@@ -40,7 +40,7 @@ STORAGE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
 # copy (fetch x2.0, write x1.0). Valid only for the kernel sources they were taken on (hash of the
 # stencil's sources) and for the same workload, precision, layout and kernel class.
 TRAFFIC = {
-    ("schur2", "l32t64", "f16", "il"): {"src": "8b0e066ee05a6155", "bytes": 1.5680e10,
+    ("schur2", "l32t64", "f16", "il"): {"src": "8b0e066ee05a6155", "bytes": 1.5795e10,
                                         "profile": "profiles/bench_l32t64_f16_hbm_counters.txt"},
 }
 STENCIL_SOURCES = {"per-thread": ("hop.hip", "a2a_device.h", "a2a_reduce.h", "a2a_kernels.h"),
