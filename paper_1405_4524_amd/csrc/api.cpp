@@ -508,7 +508,9 @@ extern "C" int a2a_finalize(a2a_ctx* h) {
   for (auto& kv : c->sizes) (void)hipFree(kv.first);
   c->sizes.clear();
   c->release_cache();
+  (void)hipStreamSynchronize(c->stream);  // no copy out of the staging buffer is pending
   if (c->scal_host) (void)hipHostFree(c->scal_host);
+  if (c->stage) (void)hipHostFree(c->stage);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete h;
   return A2A_OK;

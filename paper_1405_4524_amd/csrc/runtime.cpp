@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
+#include <cstring>
 
 namespace a2a {
 
@@ -500,8 +501,32 @@ int Solver::add_slot(Slot* s) {
   return A2A_OK;
 }
 
+// Host table -> device, in stream order.  Small uploads go through the context's pinned staging
+// buffer and return at once (the caller's host vector may go away; the device copy happens
+// before any later kernel of the stream reads dst); a synchronising copy from the caller's
+// memory otherwise.  (Synchronising every upload had left the GPU idle ~14 ms per 32^3x64 step,
+// four round trips per subset upload at each residual check.)
 static int upload(Ctx* c, void* dst, const void* src, size_t n) {
   if (!n) return A2A_OK;
+  constexpr size_t STAGE = (size_t)64 << 20;
+  if (!c->stage && !c->stage_failed) {
+    if (hipHostMalloc((void**)&c->stage, STAGE, hipHostMallocDefault) == hipSuccess) {
+      c->stage_cap = STAGE;
+      c->stage_off = 0;
+    } else {
+      (void)hipGetLastError();
+      c->stage = nullptr;
+      c->stage_failed = true;
+    }
+  }
+  if (c->stage && n <= c->stage_cap / 4) {
+    if (c->stage_off + n > c->stage_cap) A2A_TRY(c->sync());  // frees the whole buffer
+    char* p = c->stage + c->stage_off;
+    std::memcpy(p, src, n);
+    A2A_HIP(c, hipMemcpyAsync(dst, p, n, hipMemcpyHostToDevice, c->stream));
+    c->stage_off += (n + 255) & ~(size_t)255;
+    return A2A_OK;
+  }
   A2A_HIP(c, hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, c->stream));
   return c->sync();
 }
@@ -572,6 +597,7 @@ static void vec_lists(const std::vector<Slot*>& live, const std::vector<OpEntry>
 
 int Solver::rebuild() {
   if (!dirty) return A2A_OK;
+  ++gen;  // slot indices and tables change: earlier subset uploads are stale
   gc_ops();
   // ops and slots
   A2A_TRY(grow(ctx, (void**)&d_ops, &cap_ops, sizeof(OpDev) * std::max<size_t>(1, ops.size())));
@@ -708,6 +734,7 @@ int Solver::rebuild() {
 
 // groups of one slot each (R_sub = 1) or R for a subset of live slots
 int Solver::upload_subset(const std::vector<int>& idx, int R_sub) {
+  if (!dirty && sub_gen == gen && sub_R == R_sub && sub_idx == idx) return A2A_OK;  // already on the device
   std::vector<int> groups;
   std::vector<int2> htiles, vtiles, nonil, ilt;
   std::vector<int> ils;
@@ -746,7 +773,15 @@ int Solver::upload_subset(const std::vector<int>& idx, int R_sub) {
   sub_nn = (int)nonil.size();
   sub_ni = (int)ilt.size();
   sub_n = (int)idx.size();
+  sub_idx = idx;
+  sub_R = R_sub;
+  sub_gen = gen;
   return A2A_OK;
+}
+
+int Solver::upload_subset_vec(const std::vector<int>& idx) {
+  if (!dirty && sub_gen == gen && sub_R > 0 && sub_idx == idx) return A2A_OK;
+  return upload_subset(idx, 1);
 }
 
 int Solver::finalize_red(bool sub, int kind) {
@@ -1083,7 +1118,7 @@ int Solver::finalize(const std::vector<int>& idx) {
 // residual does not accept gets its FP64 Schur residual and continues with a tenfold tighter
 // target, like a slot whose reconstruction failed after a reliable update.
 int Solver::finish(const std::vector<int>& fin) {
-  A2A_TRY(upload_subset(fin, 1));
+  A2A_TRY(upload_subset_vec(fin));
   A2A_TRY(vec(true, sub_nv, VK_RU_ACCUM));
   A2A_TRY(finalize(fin));
   std::vector<int> again;
@@ -1108,7 +1143,7 @@ int Solver::finish(const std::vector<int>& fin) {
     s->last_r64 = std::sqrt(ctx->scal_host[(size_t)s->sid * NSCAL + SC_R64N2]);
     s->target *= 0.1;
   }
-  A2A_TRY(upload_subset(again, 1));
+  A2A_TRY(upload_subset_vec(again));
   // the symmetric Schur form iterates on A_oo^-1 r64 (applied by the kernel)
   return vec(true, sub_nv, init_kind(), 0, sym() ? 1 : 0, VH_R);
 }
@@ -1141,7 +1176,7 @@ int Solver::check() {
   std::vector<int> all(ru);
   all.insert(all.end(), restart.begin(), restart.end());
   if (!restart.empty()) {  // a broken-down inner iterate may hold inf/NaN: drop it, keep x64
-    A2A_TRY(upload_subset(restart, 1));
+    A2A_TRY(upload_subset_vec(restart));
     A2A_TRY(vec(true, sub_nv, VK_ZERO_X));
   }
   // reliable updates in correction form (mixed precision): r64 -= M (sigma x_lo), then x64 +=
@@ -1156,12 +1191,12 @@ int Solver::check() {
     if (!ru.empty()) {
       A2A_TRY(upload_subset(ru, R64));
       A2A_TRY(true_residual_corr(ru));
-      A2A_TRY(upload_subset(ru, 1));
+      A2A_TRY(upload_subset_vec(ru));
       A2A_TRY(vec(true, sub_nv, VK_RU_ACCUM));
     }
   } else {
     if (!ru.empty()) {
-      A2A_TRY(upload_subset(ru, 1));
+      A2A_TRY(upload_subset_vec(ru));
       A2A_TRY(vec(true, sub_nv, VK_RU_ACCUM));
     }
     A2A_TRY(upload_subset(all, R64));
@@ -1213,12 +1248,12 @@ int Solver::check() {
     s->last_r64 = r;
   }
   if (!rescale.empty()) {
-    A2A_TRY(upload_subset(rescale, 1));
+    A2A_TRY(upload_subset_vec(rescale));
     // the symmetric Schur form iterates on A_oo^-1 r64 (applied by the kernel)
     A2A_TRY(vec(true, sub_nv, method == SOLVER_CGNR ? VK_CG_RESCALE : VK_RU_RESCALE, 0, sym() ? 1 : 0, VH_R));
   }
   if (!reinit.empty()) {
-    A2A_TRY(upload_subset(reinit, 1));
+    A2A_TRY(upload_subset_vec(reinit));
     // the symmetric Schur form iterates on A_oo^-1 r64 (applied by the kernel)
     A2A_TRY(vec(true, sub_nv, init_kind(), 0, sym() ? 1 : 0, VH_R));
   }
@@ -1239,7 +1274,7 @@ int Solver::check() {
       }
     }
     if (!again.empty()) {
-      A2A_TRY(upload_subset(again, 1));
+      A2A_TRY(upload_subset_vec(again));
       // the symmetric Schur form iterates on A_oo^-1 r64 (applied by the kernel)
       A2A_TRY(vec(true, sub_nv, init_kind(), 0, sym() ? 1 : 0, VH_R));
     }

@@ -165,6 +165,13 @@ struct Solver {
   int rebuild();
   // subset helpers (indices into live)
   int upload_subset(const std::vector<int>& idx, int R_sub);
+  // the subset's per-slot vector tiles only (they do not depend on the group width): a no-op when
+  // the last subset upload was this subset
+  int upload_subset_vec(const std::vector<int>& idx);
+  // the last subset upload (slot indices, group width, table generation); gen counts rebuilds
+  std::vector<int> sub_idx;
+  int sub_R = 0;
+  unsigned sub_gen = 0, gen = 0;
   int finalize_red(bool sub, int kind);
   // kernel sequences
   int hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par, int vin, int vout, int vaux1, int vaux2,
@@ -248,6 +255,12 @@ struct Ctx {
   // reduction scratch
   double* scal_pool = nullptr;
   double* scal_host = nullptr;
+  // pinned staging of host-to-device table uploads (device tile lists, slot and operator
+  // tables): uploads are copied here and queued without waiting; space is reused only after the
+  // next stream synchronisation (sync() resets stage_off), when every queued copy has completed
+  char* stage = nullptr;
+  size_t stage_cap = 0, stage_off = 0;
+  bool stage_failed = false;
   double* partials = nullptr;
   int partial_slots = 0, partial_blk = 0;
   std::vector<int> sid_free;
@@ -282,6 +295,7 @@ struct Ctx {
   int sync() {
     hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail(A2A_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    stage_off = 0;  // every copy out of the staging buffer has completed
     return A2A_OK;
   }
   int read_scal() {  // whole used range of the scalar pool into host memory
