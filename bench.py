@@ -78,6 +78,7 @@ def main():
                     help="1: FP16/BF16 inner vectors in lane-interleaved groups (matrix-core stencil)")
     ap.add_argument("--mfma", type=int, default=1, help="0: interleaved groups use the per-thread stencil")
     ap.add_argument("--delta", type=float, default=0.03, help="reliable-update reduction factor")
+    ap.add_argument("--delta-bf16", type=float, default=0.05, help="the same for BF16 storage")
     ap.add_argument("--target-frac", type=float, default=0.8,
                     help="Schur-residual target as a fraction of tol ||eta|| (the full residual decides)")
     ap.add_argument("--tail-checks", type=int, default=1, help="1: residual checks after every iteration in the tail")
@@ -192,6 +193,7 @@ def main():
     ctx.set_option("interleave", args.interleave)
     ctx.set_option("mfma", args.mfma)
     ctx.set_option("delta", args.delta)
+    ctx.set_option("delta_bf16", args.delta_bf16)
     ctx.set_option("ru_correction", args.ru_correction)
     ctx.set_option("target_frac", args.target_frac)
     ctx.set_option("tail_checks", args.tail_checks)

@@ -116,7 +116,7 @@ const char *a2a_last_error(const a2a_ctx *ctx);
 /* Tuning knobs: "rhs_block" (1, 2, 4: RHS per thread in the stencil), "rhs_block64" (1, 2:
  * RHS per thread in the FP64 stencils of set-up, reliable updates and reconstruction; default
  * 2), "check_every" (iterations between residual checks), "delta" (reliable-update reduction
- * factor for FP16 / FP32 storage, default 0.03), "delta_bf16" (the same for BF16, default 0.1),
+ * factor for FP16 / FP32 storage, default 0.03), "delta_bf16" (the same for BF16, default 0.05),
  * "delta_cgnr" (the same for CGNR with FP16 storage, default 0.1),
  * "delta64" (the same for the FP64-only mode, default 1e-3),
  * "xcd_order" (0/1), "kernel_timing" (0/1), "autotune" (0/1), "hbm_budget" (bytes; resets

@@ -1153,7 +1153,7 @@ int Solver::check() {
   A2A_TRY(ctx->read_scal());
   std::vector<int> ru, restart, fin;
   // CGNR with FP16 storage: its iterate accumulates about three times as many FP16-rounded
-  // updates between reliable updates as BiCGStab's, so it is flushed at 0.1 like BF16
+  // updates between reliable updates as BiCGStab's, so it is flushed at 0.1
   const double delta = prec == 0                                 ? ctx->delta_64
                        : prec == 3                                 ? ctx->delta_bf16
                        : (prec == 2 && method == SOLVER_CGNR)      ? ctx->delta_cgnr

@@ -229,7 +229,7 @@ struct Ctx {
   int check_every = 4;
   // reliable-update trigger: the iterated residual has dropped by this factor since the last
   // FP64 residual (FP16 and FP32 storage; BF16's 8-bit mantissa holds about two digits)
-  double delta_lo = 0.03, delta_bf16 = 0.1, delta_64 = 1e-3;
+  double delta_lo = 0.03, delta_bf16 = 0.05, delta_64 = 1e-3;
   double delta_cgnr = 0.1;  // CGNR with FP16 storage
   int xcd_order = 1;
   int timing = 0;
