@@ -73,7 +73,8 @@ int brick_choices(const Geo& g, int (*out)[3], int maxn) {
 void xcd_order(std::vector<int2>& tiles, bool enable) {
   const int n = (int)tiles.size();
   if (!enable || n < 16) return;
-  std::vector<int2> out(n);
+  static thread_local std::vector<int2> out;  // reused: the lists are rebuilt at every residual check
+  out.resize(n);
   int start[8], cnt[8];
   int acc = 0;
   for (int k = 0; k < 8; ++k) {
@@ -582,6 +583,8 @@ static void vec_lists(const std::vector<Slot*>& live, const std::vector<OpEntry>
       ils[(size_t)e * 16 + s->il_lane % 16] = i;
     }
     const int e1 = (int)(ils.size() / 16);
+    all.reserve(all.size() + (size_t)ops[o].nblk * mine.size());
+    ilt.reserve(ilt.size() + (size_t)ops[o].nblk * (e1 - e0));
     for (int b = 0; b < ops[o].nblk; ++b) {
       for (int i : mine) {
         all.push_back(make_int2(i, b));
@@ -735,9 +738,19 @@ int Solver::rebuild() {
 // groups of one slot each (R_sub = 1) or R for a subset of live slots
 int Solver::upload_subset(const std::vector<int>& idx, int R_sub) {
   if (!dirty && sub_gen == gen && sub_R == R_sub && sub_idx == idx) return A2A_OK;  // already on the device
-  std::vector<int> groups;
-  std::vector<int2> htiles, vtiles, nonil, ilt;
-  std::vector<int> ils;
+  // the lists are rebuilt at every residual check: the solver keeps their buffers
+  std::vector<int>& groups = sc_groups;
+  std::vector<int2>& htiles = sc_h;
+  std::vector<int2>& vtiles = sc_v;
+  std::vector<int2>& nonil = sc_n;
+  std::vector<int2>& ilt = sc_i;
+  std::vector<int>& ils = sc_ils;
+  groups.clear();
+  htiles.clear();
+  vtiles.clear();
+  nonil.clear();
+  ilt.clear();
+  ils.clear();
   for (int o = 0; o < (int)ops.size(); ++o) {
     std::vector<int> mine;
     for (int i : idx)
@@ -750,6 +763,7 @@ int Solver::upload_subset(const std::vector<int>& idx, int R_sub) {
         size_t k = (size_t)gi * R_sub + r;
         groups.push_back(k < mine.size() ? mine[k] : -1);
       }
+    htiles.reserve(htiles.size() + (size_t)ops[o].nblk * ng);
     for (int b = 0; b < ops[o].nblk; ++b)
       for (int gi = 0; gi < ng; ++gi) htiles.push_back(make_int2(g0 + gi, b));
   }
@@ -757,7 +771,10 @@ int Solver::upload_subset(const std::vector<int>& idx, int R_sub) {
   vec_lists(live, ops, idx, ctx->xcd_order, vtiles, nonil, ils, ilt);
   // one buffer holds [hop tiles | vec tiles | non-interleaved vec tiles | interleaved tiles]
   A2A_TRY(grow(ctx, (void**)&d_sub_groups, &cap_subg, sizeof(int) * std::max<size_t>(1, groups.size())));
-  std::vector<int2> all(htiles);
+  std::vector<int2>& all = sc_all;
+  all.clear();
+  all.reserve(htiles.size() + vtiles.size() + nonil.size() + ilt.size());
+  all.insert(all.end(), htiles.begin(), htiles.end());
   all.insert(all.end(), vtiles.begin(), vtiles.end());
   all.insert(all.end(), nonil.begin(), nonil.end());
   all.insert(all.end(), ilt.begin(), ilt.end());

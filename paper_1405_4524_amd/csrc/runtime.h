@@ -172,6 +172,9 @@ struct Solver {
   std::vector<int> sub_idx;
   int sub_R = 0;
   unsigned sub_gen = 0, gen = 0;
+  // host buffers of upload_subset's lists, kept between calls
+  std::vector<int> sc_groups, sc_ils;
+  std::vector<int2> sc_h, sc_v, sc_n, sc_i, sc_all;
   int finalize_red(bool sub, int kind);
   // kernel sequences
   int hop(bool sub, int n_tiles, int Rk, int psel, int kprec, int out_par, int vin, int vout, int vaux1, int vaux2,
