@@ -149,7 +149,9 @@ const char *a2a_last_error(const a2a_ctx *ctx);
  * "schur_sym" (0/1, default 1: BiCGStab iterates the symmetric Schur form
  * 1 - kappa^2 A_oo^{-1} H_oe A_ee^{-1} H_eo on A_oo^{-1} b, which has the same solution; the FP64
  * residuals, reliable updates and reconstruction stay in the form A_oo - kappa^2 H_oe A_ee^{-1}
- * H_eo; CGNR always uses that form).
+ * H_eo; CGNR always uses that form), "upload_stage_bytes" (size of the pinned host buffer through
+ * which the context uploads its device tables without waiting; 0 = 64 MiB; uploads larger than a
+ * quarter of it wait for their copy).
  * Returns A2A_EINVAL for an unknown key. */
 int a2a_set_option(a2a_ctx *ctx, const char *key, double value);
 /* Bytes of device memory in the context's live buffers.  Freed buffers are kept for reuse

@@ -557,6 +557,16 @@ extern "C" int a2a_set_option(a2a_ctx* h, const char* key, double v) {
     c->ru_correction = v != 0;
   } else if (k == "schur_sym") {
     c->schur_sym = v != 0;
+  } else if (k == "upload_stage_bytes") {
+    if (!(v >= 0 && v <= (double)((size_t)1 << 32))) return c->fail(A2A_EINVAL, "upload_stage_bytes must be in [0, 4 GiB]");
+    if (c->stage) {  // the next upload allocates the new size
+      A2A_TRY(c->sync());
+      (void)hipHostFree(c->stage);
+      c->stage = nullptr;
+    }
+    c->stage_cap = c->stage_off = 0;
+    c->stage_failed = false;
+    c->stage_req = (size_t)v;
   } else if (k == "tail_checks") {
     c->tail_checks = v != 0;
   } else if (k == "target_frac") {

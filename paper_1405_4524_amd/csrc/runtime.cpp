@@ -509,7 +509,7 @@ int Solver::add_slot(Slot* s) {
 // four round trips per subset upload at each residual check.)
 static int upload(Ctx* c, void* dst, const void* src, size_t n) {
   if (!n) return A2A_OK;
-  constexpr size_t STAGE = (size_t)64 << 20;
+  const size_t STAGE = c->stage_req ? c->stage_req : (size_t)64 << 20;
   if (!c->stage && !c->stage_failed) {
     if (hipHostMalloc((void**)&c->stage, STAGE, hipHostMallocDefault) == hipSuccess) {
       c->stage_cap = STAGE;

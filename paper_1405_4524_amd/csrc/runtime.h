@@ -264,6 +264,7 @@ struct Ctx {
   char* stage = nullptr;
   size_t stage_cap = 0, stage_off = 0;
   bool stage_failed = false;
+  size_t stage_req = 0;  // option "upload_stage_bytes": staging size (0: 64 MiB)
   double* partials = nullptr;
   int partial_slots = 0, partial_blk = 0;
   std::vector<int> sid_free;

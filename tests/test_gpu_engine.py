@@ -487,6 +487,29 @@ def test_reliable_update_correction_form(ctx, orc, fields, prec, nsrc):
     assert rel(out[1], out[0]) < 1e-8
 
 
+def test_upload_staging_paths_are_bitwise(ctx, orc, fields):
+    """Device tables uploaded through a tiny pinned staging buffer (uploads above a quarter of it
+    take the waiting copy, the others fill it and force a synchronisation before reuse) give
+    bitwise the solutions, residuals and iteration counts of the default staging."""
+    f = fields[1]
+    print("[gpu] upload staging paths", flush=True)
+    eta = inputs.z2_noise(f["dims"], 20, seed=97)
+    out = []
+    for size in (0, 4096):
+        ctx.set_option("upload_stage_bytes", size)
+        try:
+            X, info, rc = ctx.solve_propagators(f["c"], eta, 0.126, 1.5, tol=1e-10, prec=2)
+        finally:
+            ctx.set_option("upload_stage_bytes", 0)
+        assert rc == 0
+        out.append((X, [x["true_rel_residual"] for x in info], [x["iters"] for x in info]))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
+    A = orc.clover(f["U"], 0.126, 1.5)
+    res = eta[0] - orc.apply_D(f["U"], A, 0.126, out[1][0][0], -1)
+    assert np.linalg.norm(res) / np.linalg.norm(eta[0]) <= 1e-10
+
+
 @pytest.mark.parametrize("prec,nsrc", [(2, 20), (2, 5), (3, 16), (1, 4)])
 def test_symmetric_schur_form(ctx, orc, fields, prec, nsrc):
     """BiCGStab on the symmetric Schur form (the default; FP16 in a lane-interleaved group on the
