@@ -1048,8 +1048,8 @@ static int autotune_cfg(Ctx* c, int clover_h, double kappa, int prec, int nrhs, 
     ++tried;
     return ru_time(c, clover_h, kappa, prec, n64, 2, best, t, ms);
   };
-  // width x brick x order jointly: which width wins depends on the brick (and on the box: the
-  // correction-form pair's time varies up to 2x between boxes, with the ranking of the widths)
+  // width x brick x order jointly: which width wins depends on the brick (and on the GPU: the
+  // correction-form pair's time varies up to 2x between GPUs, with the ranking of the widths)
   {
     std::vector<TuneCfg> cand;
     for (int r : {1, 2})

@@ -1,4 +1,4 @@
-// runtime.cpp -- context, resident fields and the batched mixed-precision BiCGStab driver.
+// runtime.cpp -- context, resident fields and the batched mixed-precision BiCGStab solver.
 //
 // Solve (Sec. 7: X_i = D^{-1} eta_i for every noise source) with even-odd preconditioning:
 //   b_o = eta_o + kappa H_oe A_ee^{-1} eta_e,   M = A_oo - kappa^2 H_oe A_ee^{-1} H_eo,
